@@ -1,0 +1,207 @@
+"""Valencia ideal GRMHD pieces, oracle side (plain NumPy FP64).
+
+Paper: Results, "GRMHD Conservative Form" (conserved variables D, S_j, tau,
+B^k; fluxes; Lorentz factor; magnetic four-vector b^mu; source term; magnetic
+constraint), Methods, "The Primitive Variable Recovery", "The Conserved Fluxes
+and Geometric Source Terms", "Stress-Energy Tensor" and "Ideal-gas EOS".
+
+Readings (listed in the design doc):
+  * conserved variables: the paper's h* = 1 + eps + p/rho + b^2/rho followed by
+    (rho h* + b^2) counts b^2 twice; the standard Valencia form is used:
+      D = rho W,  S_j = (rho h W^2 + B^2) v_j - (B.v) B_j,
+      tau = rho h W^2 - p + B^2 - (B^2/W^2 + (B.v)^2)/2 - D,
+    with h = 1 + eps + p/rho, B^2 = gamma_ij B^i B^j, B.v = gamma_ij B^i v^j.
+  * fluxes: the printed fluxes omit lapse and shift; the standard form with
+    vt^i = v^i - beta^i/alpha and the conservation law
+      d_t(sqrt(gamma) U) + d_i(alpha sqrt(gamma) F^i) = sqrt(gamma) S
+    is used; at alpha = 1, beta = 0 it reduces to the printed fluxes.
+  * sources: the Christoffel form of the paper is written in the equivalent
+    3+1 form (lapse, shift and extrinsic-curvature terms).
+  * b^0 in the recovery step means alpha b^0 (only gamma_ij enters).
+  * con2prim: the result is the unique primitive state reproducing U; it is
+    computed here by bisection on a one-dimensional residual in
+    Z = rho h W^2 down to adjacent floating-point numbers (the paper's damped
+    iteration is one way to approach the same root).
+  * EOS: p = (Gamma - 1) rho eps with the adiabatic index given by the caller.
+"""
+
+import numpy as np
+
+
+def lower(g, v):
+    """v_i = g_ij v^j."""
+    return np.einsum('ij...,j...->i...', g, v)
+
+
+def dot(a, b):
+    return np.einsum('i...,i...->...', a, b)
+
+
+def inv3(g):
+    """Inverse of a stack of symmetric 3x3 matrices with shape (3, 3, ...)."""
+    gm = np.moveaxis(np.moveaxis(g, 0, -1), 0, -1)  # (..., 3, 3)
+    inv = np.linalg.inv(gm)
+    return np.moveaxis(np.moveaxis(inv, -1, 0), -1, 0)
+
+
+def det3(g):
+    gm = np.moveaxis(np.moveaxis(g, 0, -1), 0, -1)
+    return np.linalg.det(gm)
+
+
+def eos_pressure(rho, eps, Gamma):
+    return (Gamma - 1.0) * rho * eps
+
+
+def eos_eps(rho, p, Gamma):
+    return p / ((Gamma - 1.0) * rho)
+
+
+def lorentz(v_up, gam):
+    """W = 1/sqrt(1 - gamma_ij v^i v^j)."""
+    return 1.0 / np.sqrt(1.0 - dot(lower(gam, v_up), v_up))
+
+
+def magnetic(v_up, B_up, gam):
+    """Return W, alpha b^0, b_i (lower), b^2 for Eulerian field B^i.
+
+    alpha b^0 = W (B.v); b_i = B_i/W + W (B.v) v_i; b^2 = B^2/W^2 + (B.v)^2."""
+    W = lorentz(v_up, gam)
+    v_lo = lower(gam, v_up)
+    B_lo = lower(gam, B_up)
+    Bv = dot(B_up, v_lo)
+    B2 = dot(B_up, B_lo)
+    ab0 = W * Bv
+    b_lo = B_lo / W + W * Bv * v_lo
+    b2 = B2 / W ** 2 + Bv ** 2
+    return W, ab0, b_lo, b2
+
+
+def prim_to_cons(rho, p, v_up, B_up, gam, Gamma):
+    """Undensitised (D, S_j, tau) from primitives (standard Valencia form)."""
+    W = lorentz(v_up, gam)
+    eps = eos_eps(rho, p, Gamma)
+    h = 1.0 + eps + p / rho
+    v_lo = lower(gam, v_up)
+    B_lo = lower(gam, B_up)
+    Bv = dot(B_up, v_lo)
+    B2 = dot(B_up, B_lo)
+    Z = rho * h * W * W
+    D = rho * W
+    S = (Z + B2) * v_lo - Bv * B_lo
+    tau = Z - p + B2 - 0.5 * (B2 / W ** 2 + Bv ** 2) - D
+    return D, S, tau
+
+
+def _c2p_residual(Z, D, tau, S2, B2, BS, Gamma):
+    """f(Z) = Z + B^2 - p - B^2/(2W^2) - (B.S)^2/(2Z^2) - tau - D, with
+    v^2(Z) = (Z^2 S^2 + (2Z + B^2)(B.S)^2) / (Z^2 (Z + B^2)^2) and the ideal-gas
+    pressure p = (Gamma-1)/Gamma (Z/W^2 - D/W).  Points where v^2 >= 1 are
+    reported as f = -inf (Z below the physical range)."""
+    with np.errstate(divide='ignore', invalid='ignore'):
+        v2 = (Z * Z * S2 + (2.0 * Z + B2) * BS * BS) / (Z * Z * (Z + B2) ** 2)
+        ok = (v2 < 1.0) & (Z > 0.0)
+        iw2 = np.where(ok, 1.0 - v2, 1.0)
+        p = (Gamma - 1.0) / Gamma * (Z * iw2 - D * np.sqrt(iw2))
+        f = Z + B2 - p - 0.5 * B2 * iw2 - 0.5 * BS * BS / (Z * Z) - tau - D
+    return np.where(ok, f, -np.inf)
+
+
+def con2prim(D, S_lo, tau, B_up, gam, gamu, Gamma, rho_fl, p_fl):
+    """Primitive state (rho, p, v^i) with prim_to_cons(...) == (D, S_j, tau).
+
+    Bisection on f(Z) over (0, Z_hi], Z_hi >= Gamma (tau + D) >= the root,
+    halving until the bracket ends are adjacent doubles; then
+      v_j = (S_j + (B.S) B_j / Z) / (Z + B^2),  rho = D/W,
+      p = (Gamma-1)/Gamma (Z/W^2 - rho).
+    Failure policy (both implementations): D <= 0, tau + D <= 0, no sign change,
+    v^2 >= 1, rho < rho_fl or p < p_fl -> atmosphere (rho_fl, p_fl, v = 0) and
+    the point is flagged.  Returns rho, p, v_up, fail (bool array)."""
+    D = np.asarray(D, float)
+    shape = D.shape
+    S2 = dot(S_lo, np.einsum('ij...,j...->i...', gamu, S_lo))
+    B_lo = lower(gam, B_up)
+    B2 = dot(B_up, B_lo)
+    BS = dot(B_up, S_lo)
+    bad = ~((D > 0.0) & (tau + D > 0.0))
+    Dc = np.where(bad, 1.0, D)
+    tc = np.where(bad, 1.0, tau)
+    lo = np.zeros(shape)
+    hi = Gamma * (tc + Dc) + B2 + 1e-300
+    fhi = _c2p_residual(hi, Dc, tc, S2, B2, BS, Gamma)
+    for _ in range(8):  # widen the upper end if needed (not expected)
+        need = ~(fhi >= 0.0)
+        if not need.any():
+            break
+        hi = np.where(need, 2.0 * hi, hi)
+        fhi = _c2p_residual(hi, Dc, tc, S2, B2, BS, Gamma)
+    bad |= ~(fhi >= 0.0)
+    for _ in range(2000):
+        mid = 0.5 * (lo + hi)
+        active = (mid > lo) & (mid < hi)
+        if not active.any():
+            break
+        fm = _c2p_residual(mid, Dc, tc, S2, B2, BS, Gamma)
+        up = fm < 0.0
+        lo = np.where(active & up, mid, lo)
+        hi = np.where(active & ~up, mid, hi)
+    Z = hi
+    v_lo = (S_lo + BS * B_lo / Z) / (Z + B2)
+    v_up = np.einsum('ij...,j...->i...', gamu, v_lo)
+    v2 = dot(v_up, v_lo)
+    with np.errstate(invalid='ignore', divide='ignore'):
+        W = 1.0 / np.sqrt(1.0 - v2)
+        rho = Dc / W
+        p = (Gamma - 1.0) / Gamma * (Z / W ** 2 - rho)
+    fail = bad | ~(v2 < 1.0) | ~(rho >= rho_fl) | ~(p >= p_fl)
+    rho = np.where(fail, rho_fl, rho)
+    p = np.where(fail, p_fl, p)
+    v_up = np.where(fail[None], 0.0, v_up)
+    return rho, p, v_up, fail
+
+
+def fluxes(D, S_lo, tau, B_up, rho, p, v_up, alpha, beta, gam, sqrtg):
+    """Densitised fluxes alpha sqrt(gamma) F^i of (D, S_j, tau, B^k).
+
+    Returns an array of shape (8, 3, ...): [variable, direction i, grid]."""
+    W, ab0, b_lo, b2 = magnetic(v_up, B_up, gam)
+    vt = v_up - beta / alpha
+    ps = p + 0.5 * b2
+    F = np.zeros((8, 3) + np.shape(D))
+    for i in range(3):
+        F[0, i] = D * vt[i]
+        for j in range(3):
+            F[1 + j, i] = S_lo[j] * vt[i] - b_lo[j] * B_up[i] / W + (ps if i == j else 0.0)
+        F[4, i] = tau * vt[i] + ps * v_up[i] - ab0 * B_up[i] / W
+        for k in range(3):
+            F[5 + k, i] = vt[i] * B_up[k] - vt[k] * B_up[i]
+    return F * (alpha * sqrtg)
+
+
+def matter_3p1(rho, p, v_up, B_up, D, tau, gam, Gamma):
+    """ADM matter projections of T^{mu nu} = rho h* u u + p* g - b b:
+    energy density E = tau + D and spatial stress
+    S_ij = (rho h + b^2) W^2 v_i v_j + p* gamma_ij - b_i b_j (lower indices).
+    (The momentum density S_j is the conserved momentum itself.)"""
+    W, ab0, b_lo, b2 = magnetic(v_up, B_up, gam)
+    eps = eos_eps(rho, p, Gamma)
+    h = 1.0 + eps + p / rho
+    v_lo = lower(gam, v_up)
+    ps = p + 0.5 * b2
+    E = tau + D
+    Sij = (rho * h + b2) * W * W * np.einsum('i...,j...->ij...', v_lo, v_lo) \
+        + ps * gam - np.einsum('i...,j...->ij...', b_lo, b_lo)
+    return E, Sij
+
+
+def sources_3p1(E, S_lo, Sij, alpha, dalpha, dbeta, dgam, Kij, gamu):
+    """Source vector sqrt(gamma)-free part for S_j and tau (3+1 form):
+      Sbar_{S_j} = -E d_j alpha + S_k d_j beta^k + (alpha/2) S^{kl} d_j gamma_kl
+      Sbar_tau   = alpha S^{kl} K_kl - S^k d_k alpha
+    dalpha[j] = d_j alpha, dbeta[j, k] = d_j beta^k, dgam[j, k, l] = d_j gamma_kl."""
+    Sup = np.einsum('ik...,jl...,kl...->ij...', gamu, gamu, Sij)
+    S_up = np.einsum('ij...,j...->i...', gamu, S_lo)
+    srcS = -E * dalpha + np.einsum('k...,jk...->j...', S_lo, dbeta) \
+        + 0.5 * alpha * np.einsum('kl...,jkl...->j...', Sup, dgam)
+    srcT = alpha * np.einsum('kl...,kl...->...', Sup, Kij) - dot(S_up, dalpha)
+    return srcS, srcT

@@ -1,0 +1,148 @@
+"""Pins for the oracle's time stepping, boundary treatment, initial data and
+diagnostics (Methods: Time Integration, The Stability and Complexity; Results:
+Magnetic Constraint, Entropy Curve)."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import spectral, evolve, initial_data, diagnostics, kerr_schild as ks
+
+R_IN, R_OUT, TH0, TH1 = 1.8, 20.0, 0.05, np.pi - 0.05
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def grid16():
+    return spectral.Grid(16, 16, 16, R_IN, R_OUT, TH0, TH1)
+
+
+def test_cfl_time_step_closed_form():
+    """dt = 0.25 min(dr, r dtheta, r sin(theta) dphi); on the 16^3 grid the
+    azimuthal spacing at r_in, theta = 0.05 is the smallest."""
+    pb = evolve.Problem(grid16())
+    assert abs(pb.dt() - 0.25 * 1.8 * np.sin(0.05) * 2 * np.pi / 16) < 1e-16
+    g = spectral.Grid(64, 64, 128, R_IN, R_OUT, TH0, TH1)
+    dr = 1.8 * (np.exp(0.5 * np.log(20 / 1.8) * (1 - np.cos(np.pi / 63))) - 1)
+    assert abs(evolve.Problem(g).dt() - 0.25 * dr) < 1e-15
+
+
+def test_rk4_global_order_four(monkeypatch):
+    """Classic RK4 tableau: global error O(dt^4) on y' = lambda y."""
+    g = spectral.Grid(4, 4, 4, R_IN, R_OUT, TH0, TH1)
+    pb = evolve.Problem(g, filter_on=False)
+    lam = -1.3 + 0.0
+    monkeypatch.setattr(pb, "rhs", lambda U, K0: lam * U)
+    U0 = np.ones((32,) + g.shape)
+    errs = []
+    for n in (10, 20, 40, 80):
+        U = pb.evolve(U0, None, 1.0 / n, n)
+        errs.append(abs(U[0, 0, 0, 0] - np.exp(lam)))
+    slopes = -np.diff(np.log(errs)) / np.log(2)
+    assert np.all(np.abs(slopes - 4) < 0.1)
+
+
+def test_boundary_nodes_are_frozen():
+    g = spectral.Grid(10, 8, 6, R_IN, R_OUT, TH0, TH1)
+    pb = evolve.Problem(g)
+    U, K0, _ = evolve.initial_state(g, pb)
+    R = pb.rhs(U, K0)
+    assert np.all(R[..., 0] == 0) and np.all(R[:, :, 0, :] == 0) and np.all(R[:, :, -1, :] == 0)
+    assert np.abs(R[..., 1:]).max() > 0
+
+
+def test_splitmix64_reference_outputs():
+    tab = json.load(open(os.path.join(GOLD, "splitmix64_seed0.json")))
+    step = int(tab["state_step"], 16)
+    for n, out in enumerate(tab["outputs"]):
+        assert initial_data.splitmix64((n * step) & ((1 << 64) - 1)) == int(out, 16)
+    u = initial_data.uniform01(1, 1000)
+    assert u.min() >= 0 and u.max() < 1 and abs(u.mean() - 0.5) < 0.05
+
+
+def test_michel_closed_form_relations():
+    """Mass flux rho u r^2 and Bernoulli h^2 (1 - 2M/r + u^2) are constant;
+    at r_c: u^2 = M/(2 r_c) and c_s^2 = u^2/(1 - 3u^2); inflow is supersonic
+    inside r_c and subsonic outside."""
+    G = 4.0 / 3.0
+    mic = initial_data.Michel(1.0, G, 8.0, 1e-8)
+    r = spectral.Grid(32, 4, 4, R_IN, R_OUT, TH0, TH1).r
+    rho, p, ur = mic.profile(r)
+    T = p / rho
+    h = 1 + T * G / (G - 1)
+    flux = rho * ur * r ** 2
+    bern = h ** 2 * (1 - 2 / r + ur ** 2)
+    assert np.abs(flux / flux[0] - 1).max() < 1e-12
+    assert np.abs(bern / bern[0] - 1).max() < 1e-13
+    assert abs(-flux[0] - mic.rho_c * 0.25 * 64) < 1e-20
+    cs2 = G * T / h
+    V2 = ur ** 2 / (1 - 2 / r + ur ** 2)
+    outside = r > 8.2
+    inside = (r < 7.8) & (r > 2.0)
+    assert np.all(V2[outside] < cs2[outside]) and np.all(V2[inside] > cs2[inside])
+    Tc = mic.temperature(8.0)
+    assert abs(Tc / mic.Tc - 1) < 1e-6
+    assert abs(G * mic.Tc / (1 + 4 * mic.Tc) - (1 / 16) / (1 - 3 / 16)) < 1e-15
+
+
+def test_initial_data_properties():
+    g = grid16()
+    pb = evolve.Problem(g)
+    U, K0, mat = evolve.initial_state(g, pb)
+    f, m = evolve.unpack(U)
+    # BSSN metric reproduces the Kerr-Schild spatial metric and sqrt(gamma)
+    alpha, beta, gam = ks.adm(g.R, g.TH, 1.0, 0.5)
+    gam_b = np.exp(4 * f['phi']) * f['gt']
+    assert np.abs(gam_b - gam).max() < 1e-12 * np.abs(gam).max()
+    from oracle.grmhd import det3
+    assert np.abs(det3(f['gt']) - 1).max() < 1e-13
+    # minimum plasma beta is the requested 100 (before the density perturbation)
+    from oracle.grmhd import magnetic
+    _, _, _, b2 = magnetic(mat['v'], mat['B'], gam_b)
+    assert abs(np.min(2 * mat['p'] / b2) - 100.0) < 1e-9
+    # seeded perturbation is within +-1e-6 and matches the SplitMix64 stream
+    pb0 = evolve.Problem(g)
+    _, _, mat0 = evolve.initial_state(g, pb0, pert_amp=0.0)
+    rel = mat['rho'] / mat0['rho'] - 1
+    assert np.abs(rel).max() <= 1e-6 * (1 + 1e-9)
+    u = initial_data.uniform01(1, g.npts).reshape(g.shape)
+    assert np.abs(rel - 1e-6 * (2 * u - 1)).max() < 1e-15
+    # con2prim recovers the primitives the data were built from
+    P = pb.primitives(U)
+    assert not P['fail'].any()
+    assert np.abs(P['rho'] / mat['rho'] - 1).max() < 1e-13
+    # magnetic constraint: the monopole is discretely divergence free
+    divB = diagnostics.div_B(pb, U)
+    assert np.abs(divB).max() < 1e-12 * np.abs(U[29]).max()
+
+
+def test_michel_cowling_stationary_a0():
+    """a = 0, fixed metric: magnetised Michel flow is an exact stationary
+    solution, so the GRMHD right-hand side of D, S_r, tau vanishes to
+    truncation + round-off and that of S_theta falls geometrically with the
+    theta resolution."""
+    out = []
+    for nth in (16, 32):
+        g = spectral.Grid(24, nth, 4, R_IN, R_OUT, TH0, TH1)
+        pb = evolve.Problem(g, a=0.0, cowling=True)
+        U, K0, _ = evolve.initial_state(g, pb, pert_amp=0.0)
+        R = pb.rhs(U, K0)
+        inner = (slice(None), slice(1, -1), slice(1, None))
+        for v in (24, 25, 28):
+            assert np.abs(R[v][inner]).max() < 1e-11 * np.abs(U[v]).max()
+        assert np.abs(R[:24]).max() == 0
+        out.append(np.abs(R[26][inner]).max() / np.abs(U[25]).max())
+    assert out[1] < out[0] / 20
+
+
+@pytest.mark.slow
+def test_ten_steps_small_grid_sane():
+    g = grid16()
+    pb = evolve.Problem(g)
+    U, K0, _ = evolve.initial_state(g, pb)
+    m0 = diagnostics.rest_mass(pb, U)
+    V = pb.evolve(U, K0, pb.dt(), 10)
+    assert np.all(np.isfinite(V))
+    assert not pb.last_fail.any()
+    assert abs(diagnostics.rest_mass(pb, V) / m0 - 1) < 1e-4
