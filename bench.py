@@ -1,0 +1,162 @@
+"""Benchmark: grid-point RK-stage updates per second of the coupled BSSN +
+Valencia GRMHD spectral stage on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+A step is one classic RK4 step (four RHS evaluations + RK updates) followed by
+the spectral filter, over the whole grid of the workload, with the state
+resident in HBM.  value = points x 4 x K / (wall time of K steps).  Prints one
+JSON line.  Also reported: per-launch durations measured with HIP events on
+the library's stream (the dominant kernel's roofline), and the plain FP64
+oracle timed on this host on a bounded sample (one RHS evaluation of the same
+workload)."""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = "point-updates/s per RK stage (BSSN+GRMHD), FP64 vs mixed; p50/p99 job latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (matrix and vector)
+RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+
+
+def launch_costs(nr, nth, nph):
+    """Algorithmic HBM bytes and FP64 flops per grid point for one launch of
+    each kind (compulsory reads + writes of that launch; flops of the dense
+    contractions, 2 N per output element)."""
+    d = 8.0
+    c = {}
+    c["c2p_flux"] = (54 * d, 0.0)                       # 24 in, 30 out
+    c["deriv_r2"] = (33 * d, 2 * 2 * nr * 11)           # 11 in, 22 out
+    c["deriv_r1"] = (36 * d, 2 * nr * 18)               # 18 in, 18 out
+    c["deriv_t2"] = (33 * d, 2 * 2 * nth * 11)
+    c["deriv_t1"] = (58 * d, 2 * nth * 29)              # 29 in, 29 out
+    c["deriv_p2"] = (33 * d, 2 * 2 * nph * 11)
+    c["deriv_p1"] = (80 * d, 2 * nph * 40)              # 40 in, 40 out
+    c["rhs_rk"] = (303 * d, 0.0)                        # mean over the 4 stage modes
+    for k, n in (("filter_r", nr), ("filter_t", nth), ("filter_p", nph)):
+        c[k] = (64 * d, 2 * n * 32)
+    return c
+
+
+def roofline(kind, ms, P, costs):
+    b, f = costs[kind]
+    sec = ms * 1e-3
+    if f > 0 and f / b > RIDGE:
+        ach = f * P / sec / 1e12
+        return {"kernel": kind, "bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None}
+    ach = b * P / sec / 1e9
+    return {"kernel": kind, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None}
+
+
+def cpu_baseline(w):
+    """The oracle as it stands: one RHS evaluation (one RK stage) of the same
+    workload on this host."""
+    from oracle import spectral, evolve
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    ga, pk, ik = workloads.oracle_kwargs(w)
+    g = spectral.Grid(*ga)
+    pb = evolve.Problem(g, **pk)
+    U, K0, _ = evolve.initial_state(g, pb, **ik)
+    t0 = time.perf_counter()
+    pb.rhs(U, K0)
+    t = time.perf_counter() - t0
+    return {"value": g.npts / t, "unit": "point-stage updates/s", "cores": int(blas),
+            "kind": "oracle",
+            "sample": f"one RHS evaluation (one RK stage) of {w['grid']['nr']}x{w['grid']['nth']}x"
+                      f"{w['grid']['nph']} after untimed oracle initial data; {t:.1f} s; NumPy FP64, "
+                      f"dense BLAS solves on {blas} threads, einsum/FFT single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ks_michel_64x64x128")
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is a design (see the sharding section of the docs)",
+              file=sys.stderr)
+        sys.exit(2)
+    w = workloads.WORKLOADS[args.workload]
+    K = args.steps if args.steps is not None else w["steps"]
+    W = args.warmup
+
+    import torch
+    from paper_2508_18221_amd import Solver, make_grid, make_phys
+    torch.cuda.set_device(0)
+    s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]))
+    g = w["grid"]
+    P = g["nr"] * g["nth"] * g["nph"]
+    s.init_state()
+    if W > 0:
+        s.step(W)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    s.step(K)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    diag = s.diagnostics()
+    # per-launch durations (HIP events on the library stream), a few more steps
+    prof = s.profile_step(args.profile_steps)
+    costs = launch_costs(g["nr"], g["nth"], g["nph"])
+    per_step = {k: ms * cnt / args.profile_steps for k, (ms, cnt) in prof.items()}
+    dom = max(per_step, key=per_step.get)
+    rl = roofline(dom, prof[dom][0], P, costs)
+    kernels = {k: {"avg_ms": round(ms, 5), "launches_per_step": cnt // args.profile_steps,
+                   "GB_per_s": round(costs[k][0] * P / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                   "TFLOP_per_s": round(costs[k][1] * P / (ms * 1e-3) / 1e12, 2) if ms > 0 else None}
+               for k, (ms, cnt) in prof.items()}
+    s.close()
+    out = {
+        "metric": METRIC,
+        "value": P * 4 * K / wall,
+        "unit": "point-stage updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall * 1e3 / K,
+        "ms_per_step_hip_events": ev_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [g["nr"], g["nth"], g["nph"]], "points": P,
+                   "rk_stages_per_step": 4, "precision": "fp64",
+                   "physics": "Kerr-Schild a=0.5 + magnetised Michel accretion, BSSN+1+log+Gamma-driver"},
+        "state_after": {"t": diag["t"], "c2p_fail": diag["c2p_fail"], "nonfinite": diag["nonfinite"],
+                        "rest_mass": diag["rest_mass"]},
+        "roofline": rl,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

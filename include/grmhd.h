@@ -1,0 +1,206 @@
+/*
+ * grmhd.h -- C-ABI of the MI355X (gfx950) coupled BSSN + Valencia GRMHD
+ * spectral RK stage (arXiv 2508.18221).
+ *
+ * What the library computes (paper citations by section/equation):
+ *  - grid: Chebyshev-Gauss-Lobatto nodes x_j = cos(j pi/(N-1)) in r (log map
+ *    ln r = Lc + Lh x) and theta (affine map onto [th_min, th_max]), uniform
+ *    phi_l = 2 pi l / N_phi (Methods, "Grid Discretization");
+ *  - derivatives: derivative of the Chebyshev / trigonometric interpolant at
+ *    the nodes, as dense differentiation matrices applied along grid lines
+ *    (Methods, "The Spectral Derivative Operators"; Fourier Nyquist mode:
+ *    dropped from odd, kept as -(N/2)^2 in even derivatives);
+ *  - one RHS evaluation: per-point con2prim (Methods, "The Primitive Variable
+ *    Recovery": the unique primitive state reproducing U), densitised fluxes
+ *    alpha sqrt(gamma) F^i and 3+1 geometric sources (Results, "GRMHD
+ *    Conservative Form"; Methods, "The Conserved Fluxes and Geometric Source
+ *    Terms"), BSSN + 1+log + Gamma-driver right-hand side with matter
+ *    coupling (Methods, "BSSN Evolution Equations", "Gauge Conditions",
+ *    "Stress-Energy Tensor"); RHS frozen (= 0) at r_out and both theta ends;
+ *  - one step: classic RK4 (Methods, "Time Integration") followed by the
+ *    exponential filter sigma(k) = exp(-alpha (|k|/k_max)^p) along r, theta,
+ *    phi (Methods, "Dealiasing and Spectral Filtering").
+ *
+ * State layout: 32 FP64 fields, field-major, each field laid out
+ * [phi][theta][r] with r fastest (P = n_r n_theta n_phi doubles per field):
+ *    0 phi (conformal factor, (1/12) ln det gamma)
+ *    1-6  gt_rr gt_rth gt_rph gt_thth gt_thph gt_phph   (conformal metric)
+ *    7-12 At_rr ... At_phph                             (trace-free curvature)
+ *   13 K, 14-16 Gt^r Gt^th Gt^ph, 17 alpha, 18-20 beta^i, 21-23 Bd^i (driver)
+ *   24 sqrt(gamma) D, 25-27 sqrt(gamma) S_j (lower), 28 sqrt(gamma) tau,
+ *   29-31 sqrt(gamma) B^i (upper).
+ * Node order: index 0 of r is r_out, index 0 of theta is th_max.
+ *
+ * Ownership: the caller owns all device memory.  grmhd_query_bytes() gives
+ * the sizes of the two device buffers ("resident": state, static fields,
+ * operators; "scratch": stage temporaries) that grmhd_create() borrows for
+ * the context's lifetime.  The library never allocates or frees device
+ * memory.  Every call that takes a device pointer expects memory on the
+ * context's device.  All work is enqueued on the caller's HIP stream; calls
+ * marked "syncs" wait for that stream.
+ *
+ * Errors: functions return GRMHD_OK (0) or a negative code; the thread-local
+ * message of the last failure is grmhd_last_error().  Device-side faults
+ * surface at the next syncing call.  Con2prim failures are not errors: they
+ * are counted (grmhd_diagnostics) and handled by the atmosphere policy.
+ * A context is single-threaded; different contexts are independent.
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GRMHD_OK = 0,
+  GRMHD_E_ARG = -1,      /* invalid argument (null pointer, bad size, ...) */
+  GRMHD_E_SIZE = -2,     /* buffer size does not match the grid            */
+  GRMHD_E_DEVICE = -3,   /* HIP runtime error                              */
+  GRMHD_E_STATE = -4,    /* call out of order (e.g. step before a state)   */
+  GRMHD_E_BUDGET = -5    /* server: job does not fit the memory budget     */
+};
+
+#define GRMHD_NFIELDS 32
+
+typedef enum { GRMHD_FP64 = 0, GRMHD_MIX_FP32 = 1, GRMHD_MIX_BF16X3 = 2 } grmhd_prec;
+
+/* Grid (Methods, "Grid Discretization"; readings: log radial map, Chebyshev
+ * theta on [th_min, th_max]).  n_r, n_theta >= 4; n_phi even, >= 4;
+ * each <= 256. */
+typedef struct {
+  int32_t nr, nth, nph;
+  double r_in, r_out;       /* radial domain, 0 < r_in < r_out               */
+  double th_min, th_max;    /* polar domain, 0 < th_min < th_max < pi        */
+  double filt_alpha;        /* exponential filter strength (36)              */
+  int32_t filt_order;       /* filter order p (16)                           */
+  int32_t filter_on;        /* 1: filter after every RK4 step                */
+} grmhd_grid;
+
+/* Physics and initial-data parameters. */
+typedef struct {
+  double M, a;              /* black-hole mass and spin (Kerr-Schild)        */
+  double gamma_ad;          /* ideal-gas adiabatic index Gamma               */
+  double cfl;               /* dt = cfl * min(dr, r dth, r sin th dph)       */
+  double eta;               /* Gamma-driver damping                          */
+  int32_t cowling;          /* 1: spacetime right-hand sides set to zero     */
+  int32_t gauge_k0;         /* 1: d_t alpha = ... - 2 alpha (K - K0)         */
+  double r_c, rho_c;        /* Michel sonic radius, density there            */
+  double beta_min;          /* min over nodes of 2p/b^2 (monopole field)     */
+  double pert_amp;          /* rho -> rho (1 + pert_amp (2u - 1))            */
+  uint64_t seed;            /* SplitMix64 seed of the perturbation           */
+  double rho_floor, p_floor;/* atmosphere: rho_floor r^-1.5, p_floor r^-2.5  */
+} grmhd_phys;
+
+/* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"). */
+typedef struct {
+  double t;                 /* simulation time                              */
+  int64_t step;             /* completed RK4 steps                          */
+  int64_t c2p_fail;         /* points that took the atmosphere policy in the
+                               last RHS evaluation                          */
+  int64_t nonfinite;        /* NaN/Inf entries in the state                  */
+  double rest_mass;         /* sum sqrt(gamma) D w (quadrature weights w)    */
+  double entropy;           /* E^n = sum rho s sqrt(gamma) w                 */
+  double max_abs_divB;      /* max |d_i (sqrt(gamma) B^i)|                  */
+  double min_alpha, max_W;
+} grmhd_diag;
+
+typedef struct grmhd_ctx grmhd_ctx;
+
+/* Bytes of device memory the context borrows (resident, scratch). */
+int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec,
+                      size_t* resident_bytes, size_t* scratch_bytes);
+
+/* Build operators (host, long double) and upload them into dev_resident.
+ * dev_resident / dev_scratch: device buffers of at least the queried sizes,
+ * 256-byte aligned; hip_stream: a hipStream_t (0 = null stream).  Syncs. */
+int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec,
+                 void* dev_resident, void* dev_scratch, void* hip_stream,
+                 grmhd_ctx** out);
+
+/* Waits for the stream and releases host metadata (never device memory). */
+int grmhd_destroy(grmhd_ctx* ctx);
+
+/* Kerr-Schild background in BSSN variables + magnetised Michel flow + seeded
+ * density perturbation, computed on the host and uploaded; sets K0 and
+ * primes the con2prim guesses.  t = 0.  Syncs. */
+int grmhd_init_state(grmhd_ctx* ctx);
+
+/* Copy a state in (host, n = 32 P doubles, layout above), set the static
+ * 1+log source K0 (host, P doubles; NULL: K0 = K - beta^k d_k alpha/(2 alpha)
+ * computed on the device from the state) and the time t; primes the
+ * con2prim guesses by a cold-start recovery.  Syncs. */
+int grmhd_set_state(grmhd_ctx* ctx, const double* host_U, size_t n,
+                    const double* host_K0, double t);
+
+/* Copy the state (and optionally K0, P doubles) out.  Syncs. */
+int grmhd_get_state(grmhd_ctx* ctx, double* host_U, size_t n, double* host_K0);
+
+/* Device pointers of the resident state (32 P doubles) and K0 (P doubles);
+ * valid for the context's lifetime.  No copy, no sync. */
+int grmhd_state_ptr(grmhd_ctx* ctx, double** dev_U, double** dev_K0);
+
+/* One RHS evaluation dU/dt = L(U) of a device state (32 P doubles) into
+ * dev_dUdt (32 P doubles); uses the context's K0 and con2prim guesses.
+ * dev_U may be the resident state.  Async. */
+int grmhd_rhs(grmhd_ctx* ctx, const double* dev_U, double* dev_dUdt);
+
+/* nsteps classic RK4 steps of size grmhd_dt(), each followed by the filter
+ * when enabled.  Async. */
+int grmhd_step(grmhd_ctx* ctx, int32_t nsteps);
+
+/* Reductions over the current state.  Syncs. */
+int grmhd_diagnostics(grmhd_ctx* ctx, grmhd_diag* out);
+
+double grmhd_dt(const grmhd_ctx* ctx);
+double grmhd_time(const grmhd_ctx* ctx);
+const char* grmhd_last_error(void);
+
+/* ---- operator access (tests and tools) --------------------------------- */
+
+/* Apply one spectral operator along one axis to nfields device fields
+ * (each P doubles, layout above) from dev_in into dev_out.
+ * axis: 0 = r, 1 = theta, 2 = phi.  op: 1 = first derivative, 2 = second
+ * derivative, 3 = filter.  Uses the same contraction kernels as the RHS.
+ * Async. */
+int grmhd_apply_operator(grmhd_ctx* ctx, int32_t axis, int32_t op,
+                         const double* dev_in, double* dev_out, int32_t nfields);
+
+/* Primitive recovery and densitised fluxes of a device state: writes
+ * dev_prim (5 P doubles: rho, p, v^r, v^theta, v^phi) and, if non-null,
+ * dev_flux (24 P doubles, [direction][variable], variables in state order
+ * 24..31).  Async. */
+int grmhd_con2prim(grmhd_ctx* ctx, const double* dev_U, double* dev_prim,
+                   double* dev_flux);
+
+/* ---- timing ---------------------------------------------------------------- */
+
+/* Launch kinds of one RK4 step (4 stages x 8 launches + 3 filter launches). */
+enum {
+  GRMHD_K_C2P_FLUX = 0,   /* con2prim + densitised fluxes                        */
+  GRMHD_K_DERIV_R2 = 1,   /* r axis, first + second derivative (11 fields)        */
+  GRMHD_K_DERIV_R1 = 2,   /* r axis, first derivative (10 fields + 8 fluxes)      */
+  GRMHD_K_DERIV_T2 = 3,   /* theta axis, first + second                            */
+  GRMHD_K_DERIV_T1 = 4,   /* theta axis, first (10 + 11 mixed + 8 fluxes)          */
+  GRMHD_K_DERIV_P2 = 5,   /* phi axis, first + second                              */
+  GRMHD_K_DERIV_P1 = 6,   /* phi axis, first (10 + 22 mixed + 8 fluxes)            */
+  GRMHD_K_RHS_RK = 7,     /* BSSN + Valencia RHS and RK4 stage update              */
+  GRMHD_K_FILTER_R = 8, GRMHD_K_FILTER_T = 9, GRMHD_K_FILTER_P = 10,
+  GRMHD_K_COUNT = 11
+};
+
+/* Advance nsteps RK4 steps exactly as grmhd_step, recording a HIP event on
+ * the context stream after every launch; ms[k] (nkinds >= GRMHD_K_COUNT)
+ * receives the average duration in milliseconds of launch kind k (time
+ * between the event before and after it) and counts[k] (optional) the
+ * number of launches of that kind.  Syncs. */
+int grmhd_profile_step(grmhd_ctx* ctx, int32_t nsteps, double* ms, int32_t nkinds, int32_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRMHD_H */

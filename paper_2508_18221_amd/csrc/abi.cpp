@@ -1,0 +1,508 @@
+// C-ABI of the gfx950 BSSN + Valencia GRMHD spectral RK stage: context set-up,
+// state transfer, the RHS pipeline, RK4 stepping with the post-step filter,
+// diagnostics.  Declarations and contracts: include/grmhd.h.
+//
+// One RHS evaluation (per RK stage) on the caller's stream:
+//   1. k_c2p_flux           con2prim + 24 densitised flux arrays
+//   2. r pass   (2 launches) d_r, d_rr of 11 fields; d_r of 10 fields, 8 r-fluxes
+//   3. th pass  (2 launches) d_th, d_thth; d_th of 10 fields, of the 11 d_r
+//                            arrays (mixed r-th) and of 8 th-fluxes
+//   4. ph pass  (2 launches) d_ph, d_phph; d_ph of 10 fields, of the 11 d_r and
+//                            11 d_th arrays (mixed) and of 8 ph-fluxes
+//   5. k_rhs_rk             BSSN + Valencia RHS, boundary freeze, RK4 update
+// After the fourth stage the filter runs as three contraction passes.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "grmhd_internal.h"
+
+using namespace grmhd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(GRMHD_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct Layout {
+  size_t P;
+  size_t res_fields, mats[3][3], rnode, wr, wth, partials, res_total;
+  size_t scr_total;
+};
+
+int validate_grid(const grmhd_grid* g) {
+  if (!g) return fail(GRMHD_E_ARG, "grid is null");
+  if (g->nr < 4 || g->nth < 4 || g->nph < 4 || g->nr > 256 || g->nth > 256 || g->nph > 256)
+    return fail(GRMHD_E_ARG, "grid sizes must be in [4, 256]");
+  if (g->nph % 2) return fail(GRMHD_E_ARG, "n_phi must be even");
+  if (!(g->r_in > 0 && g->r_out > g->r_in)) return fail(GRMHD_E_ARG, "need 0 < r_in < r_out");
+  if (!(g->th_min > 0 && g->th_max > g->th_min && g->th_max < M_PI))
+    return fail(GRMHD_E_ARG, "need 0 < th_min < th_max < pi");
+  if (g->filt_order < 1) return fail(GRMHD_E_ARG, "filter order must be >= 1");
+  return GRMHD_OK;
+}
+
+Layout layout(const grmhd_grid& g) {
+  Layout L;
+  L.P = (size_t)g.nr * g.nth * g.nph;
+  size_t off = 0;
+  L.res_fields = off;
+  off += align256((size_t)RS_NFIELDS * L.P * sizeof(double));
+  const int n[3] = {g.nr, g.nth, g.nph};
+  for (int a = 0; a < 3; ++a) {
+    const size_t np = (size_t)round_up(n[a], 16);
+    for (int o = 0; o < 3; ++o) {
+      L.mats[a][o] = off;
+      off += align256(np * np * sizeof(double));
+    }
+  }
+  L.rnode = off;
+  off += align256((size_t)g.nr * sizeof(double));
+  L.wr = off;
+  off += align256((size_t)g.nr * sizeof(double));
+  L.wth = off;
+  off += align256((size_t)g.nth * sizeof(double));
+  L.partials = off;
+  off += align256((size_t)diag_partials_blocks((long long)L.P) * 8 * sizeof(double));
+  L.res_total = off;
+  L.scr_total = align256((size_t)SC_NFIELDS * L.P * sizeof(double));
+  return L;
+}
+
+}  // namespace
+
+struct grmhd_ctx {
+  grmhd_grid grid;
+  grmhd_phys phys;
+  grmhd_prec prec;
+  Layout L;
+  Operators ops;
+  char* res;
+  double* scr;
+  hipStream_t stream;
+  int device;
+  double *U, *K0, *prim, *fail;
+  const double* mats[3][3];
+  double *rnode, *wr, *wth, *partials;
+  PointParams pp;
+  double dt, t;
+  int64_t step;
+  bool have_state;
+};
+
+namespace {
+
+double* sf(grmhd_ctx* c, int f) { return c->scr + (size_t)f * c->L.P; }
+
+// Optional event recorder: an event after every launch, tagged with its kind.
+struct Recorder {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+  size_t n = 0;
+  hipError_t mark(int k, hipStream_t s) {
+    if (n >= ev.size()) return hipErrorInvalidValue;
+    kind[n] = k;
+    return hipEventRecord(ev[n++], s);
+  }
+};
+
+#define MARK(rec, k)                                               \
+  do {                                                             \
+    if (rec) HIPCHK((rec)->mark((k), c->stream));                  \
+  } while (0)
+
+hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const TaskList& tl,
+                    const Bases& B) {
+  return launch_contract(axis, nmat, tl, B, c->mats[axis][op0], c->mats[axis][op1], c->ops.n,
+                         c->ops.npad, (long long)c->L.P, c->stream);
+}
+
+void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = 0) {
+  Task& t = tl.t[tl.n++];
+  t.src_sel = ssel;
+  t.src = src;
+  t.dst_sel = dsel;
+  t.dst0 = d0;
+  t.dst1 = d1;
+}
+
+// Selectors: 0 = stage input state, 1 = scratch, 2 = resident
+int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, Recorder* rec = nullptr) {
+  Bases B;
+  B.b[0] = const_cast<double*>(Uin);
+  B.b[1] = c->scr;
+  B.b[2] = (double*)c->res;
+  B.b[3] = nullptr;
+  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, c->stream));
+  MARK(rec, GRMHD_K_C2P_FLUX);
+  for (int a = 0; a < 3; ++a) {
+    TaskList t2, t1;
+    t2.n = t1.n = 0;
+    for (int s = 0; s < ND2; ++s) add(t2, 0, D2_FIELD[s], 1, SC_D1 + 21 * a + D2_FIELD[s], SC_D2 + 11 * a + s);
+    for (int q = 0; q < 10; ++q) add(t1, 0, D1_ONLY[q], 1, SC_D1 + 21 * a + D1_ONLY[q]);
+    if (a == 1)  // mixed r-theta: d_theta of d_r
+      for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + s);
+    if (a == 2) {  // mixed r-phi, theta-phi
+      for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + 11 + s);
+      for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + 21 + D2_FIELD[s], 1, SC_MX + 22 + s);
+    }
+    for (int v = 0; v < 8; ++v) add(t1, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
+    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, t2, B));
+    MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, t1, B));
+    MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
+  }
+  HIPCHK(launch_rhs_rk(mode, Uin, c->scr, c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->dt, c->pp,
+                       c->stream));
+  MARK(rec, GRMHD_K_RHS_RK);
+  return GRMHD_OK;
+}
+
+int filter_state(grmhd_ctx* c, Recorder* rec = nullptr) {
+  Bases B;
+  B.b[0] = c->U;
+  B.b[1] = c->scr;
+  B.b[2] = (double*)c->res;
+  B.b[3] = nullptr;
+  // U -> Us (r), Us -> acc (theta), acc -> U (phi)
+  const int src_sel[3] = {0, 1, 1}, src_base[3] = {0, SC_US, SC_ACC};
+  const int dst_sel[3] = {1, 1, 0}, dst_base[3] = {SC_US, SC_ACC, 0};
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    for (int f = 0; f < NF; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
+    HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B));
+    MARK(rec, GRMHD_K_FILTER_R + a);
+  }
+  return GRMHD_OK;
+}
+
+int one_step(grmhd_ctx* c, Recorder* rec) {
+  double* Us = sf(c, SC_US);
+  int rc;
+  if ((rc = rhs_eval(c, c->U, 1, Us, rec))) return rc;
+  if ((rc = rhs_eval(c, Us, 2, Us, rec))) return rc;
+  if ((rc = rhs_eval(c, Us, 3, Us, rec))) return rc;
+  if ((rc = rhs_eval(c, Us, 4, c->U, rec))) return rc;
+  if (c->grid.filter_on && (rc = filter_state(c, rec))) return rc;
+  c->t += c->dt;
+  c->step += 1;
+  return GRMHD_OK;
+}
+
+int prime_guesses(grmhd_ctx* c) {
+  HIPCHK(hipMemsetAsync(c->prim, 0, 5 * c->L.P * sizeof(double), c->stream));
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->rnode, c->pp, c->stream));
+  return GRMHD_OK;
+}
+
+int compute_k0(grmhd_ctx* c) {
+  Bases B;
+  B.b[0] = c->U;
+  B.b[1] = c->scr;
+  B.b[2] = (double*)c->res;
+  B.b[3] = nullptr;
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    add(tl, 0, 17, 1, SC_D1 + 21 * a + 17);
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B));
+  }
+  HIPCHK(launch_k0(c->U, c->scr, c->K0, c->pp, c->stream));
+  return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grmhd_last_error(void) { return g_err.c_str(); }
+
+int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec, size_t* resident, size_t* scratch) {
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (prec != GRMHD_FP64) return fail(GRMHD_E_ARG, "only GRMHD_FP64 is implemented");
+  if (!resident || !scratch) return fail(GRMHD_E_ARG, "null output pointer");
+  Layout L = layout(*grid);
+  *resident = L.res_total;
+  *scratch = L.scr_total;
+  return GRMHD_OK;
+}
+
+int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
+                 void* dev_scratch, void* hip_stream, grmhd_ctx** out) {
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (!phys || !out || !dev_resident || !dev_scratch) return fail(GRMHD_E_ARG, "null argument");
+  if (prec != GRMHD_FP64) return fail(GRMHD_E_ARG, "only GRMHD_FP64 is implemented");
+  if (((uintptr_t)dev_resident & 255) || ((uintptr_t)dev_scratch & 255))
+    return fail(GRMHD_E_ARG, "device buffers must be 256-byte aligned");
+  if (!(phys->gamma_ad > 1.0) || !(phys->cfl > 0.0) || !(phys->M >= 0.0) || !(fabs(phys->a) <= phys->M))
+    return fail(GRMHD_E_ARG, "need Gamma > 1, cfl > 0, M >= 0, |a| <= M");
+  grmhd_ctx* c = new grmhd_ctx();
+  c->grid = *grid;
+  c->phys = *phys;
+  c->prec = prec;
+  c->L = layout(*grid);
+  c->res = (char*)dev_resident;
+  c->scr = (double*)dev_scratch;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(GRMHD_E_DEVICE, "hipGetDevice failed");
+  }
+  build_operators(*grid, phys->cfl, &c->ops);
+  const size_t P = c->L.P;
+  double* rf = (double*)(c->res + c->L.res_fields);
+  c->U = rf + (size_t)RS_U * P;
+  c->K0 = rf + (size_t)RS_K0 * P;
+  c->prim = rf + (size_t)RS_PRIM * P;
+  c->fail = rf + (size_t)RS_FAIL * P;
+  for (int a = 0; a < 3; ++a)
+    for (int o = 0; o < 3; ++o) c->mats[a][o] = (const double*)(c->res + c->L.mats[a][o]);
+  c->rnode = (double*)(c->res + c->L.rnode);
+  c->wr = (double*)(c->res + c->L.wr);
+  c->wth = (double*)(c->res + c->L.wth);
+  c->partials = (double*)(c->res + c->L.partials);
+  c->pp.nr = grid->nr;
+  c->pp.nth = grid->nth;
+  c->pp.nph = grid->nph;
+  c->pp.P = (long long)P;
+  c->pp.gamma_ad = phys->gamma_ad;
+  c->pp.eta = phys->eta;
+  c->pp.cowling = phys->cowling;
+  c->pp.gauge_k0 = phys->gauge_k0;
+  c->pp.rho_floor = phys->rho_floor;
+  c->pp.p_floor = phys->p_floor;
+  c->dt = c->ops.dt;
+  c->t = 0.0;
+  c->step = 0;
+  c->have_state = false;
+  hipError_t e = set_kernel_attributes();
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    for (int o = 0; o < 3 && e == hipSuccess; ++o)
+      e = hipMemcpyAsync((void*)c->mats[a][o], c->ops.at[a][o].data(), c->ops.at[a][o].size() * sizeof(double),
+                         hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->rnode, c->ops.r.data(), grid->nr * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->wr, c->ops.wr.data(), grid->nr * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->wth, c->ops.wth.data(), grid->nth * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(GRMHD_E_DEVICE, std::string("create: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return GRMHD_OK;
+}
+
+int grmhd_destroy(grmhd_ctx* c) {
+  if (!c) return GRMHD_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  delete c;
+  if (e != hipSuccess) return fail(GRMHD_E_DEVICE, std::string("destroy: ") + hipGetErrorString(e));
+  return GRMHD_OK;
+}
+
+int grmhd_init_state(grmhd_ctx* c) {
+  if (!c) return fail(GRMHD_E_ARG, "null context");
+  std::vector<double> U, K0;
+  std::string err;
+  int rc = host_initial_data(c->grid, c->phys, c->ops, &U, &K0, &err);
+  if (rc) return fail(rc, err);
+  HIPCHK(hipMemcpyAsync(c->U, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->K0, K0.data(), K0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if ((rc = prime_guesses(c))) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->t = 0.0;
+  c->step = 0;
+  c->have_state = true;
+  return GRMHD_OK;
+}
+
+int grmhd_set_state(grmhd_ctx* c, const double* host_U, size_t n, const double* host_K0, double t) {
+  if (!c || !host_U) return fail(GRMHD_E_ARG, "null argument");
+  if (n != (size_t)NF * c->L.P) return fail(GRMHD_E_SIZE, "state size must be 32 * P");
+  HIPCHK(hipMemcpyAsync(c->U, host_U, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  int rc;
+  if (host_K0) {
+    HIPCHK(hipMemcpyAsync(c->K0, host_K0, c->L.P * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  } else if ((rc = compute_k0(c))) {
+    return rc;
+  }
+  if ((rc = prime_guesses(c))) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->t = t;
+  c->step = 0;
+  c->have_state = true;
+  return GRMHD_OK;
+}
+
+int grmhd_get_state(grmhd_ctx* c, double* host_U, size_t n, double* host_K0) {
+  if (!c || !host_U) return fail(GRMHD_E_ARG, "null argument");
+  if (n != (size_t)NF * c->L.P) return fail(GRMHD_E_SIZE, "state size must be 32 * P");
+  HIPCHK(hipMemcpyAsync(host_U, c->U, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (host_K0)
+    HIPCHK(hipMemcpyAsync(host_K0, c->K0, c->L.P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GRMHD_OK;
+}
+
+int grmhd_state_ptr(grmhd_ctx* c, double** dev_U, double** dev_K0) {
+  if (!c) return fail(GRMHD_E_ARG, "null context");
+  if (dev_U) *dev_U = c->U;
+  if (dev_K0) *dev_K0 = c->K0;
+  return GRMHD_OK;
+}
+
+int grmhd_rhs(grmhd_ctx* c, const double* dev_U, double* dev_dUdt) {
+  if (!c || !dev_U || !dev_dUdt) return fail(GRMHD_E_ARG, "null argument");
+  if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
+  return rhs_eval(c, dev_U, 0, dev_dUdt);
+}
+
+int grmhd_step(grmhd_ctx* c, int32_t nsteps) {
+  if (!c) return fail(GRMHD_E_ARG, "null context");
+  if (nsteps < 0) return fail(GRMHD_E_ARG, "nsteps < 0");
+  if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
+  for (int n = 0; n < nsteps; ++n) {
+    int rc = one_step(c, nullptr);
+    if (rc) return rc;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_profile_step(grmhd_ctx* c, int32_t nsteps, double* ms, int32_t nkinds, int32_t* counts) {
+  if (!c || !ms || nkinds < GRMHD_K_COUNT) return fail(GRMHD_E_ARG, "need ms[GRMHD_K_COUNT]");
+  if (nsteps < 1) return fail(GRMHD_E_ARG, "nsteps < 1");
+  if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
+  Recorder rec;
+  const size_t per_step = 4 * 8 + 3 + 1;  // 8 launches per stage, 3 filter passes, start
+  rec.ev.resize(per_step);
+  rec.kind.resize(per_step);
+  for (auto& e : rec.ev) HIPCHK(hipEventCreate(&e));
+  std::vector<double> acc(GRMHD_K_COUNT, 0.0);
+  std::vector<int> cnt(GRMHD_K_COUNT, 0);
+  int rc = GRMHD_OK;
+  for (int n = 0; n < nsteps && rc == GRMHD_OK; ++n) {
+    rec.n = 0;
+    hipError_t e = rec.mark(-1, c->stream);  // start marker
+    if (e != hipSuccess) {
+      rc = fail(GRMHD_E_DEVICE, hipGetErrorString(e));
+      break;
+    }
+    if ((rc = one_step(c, &rec))) break;
+    e = hipEventSynchronize(rec.ev[rec.n - 1]);
+    for (size_t i = 1; i < rec.n && e == hipSuccess; ++i) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, rec.ev[i - 1], rec.ev[i]);
+      acc[rec.kind[i]] += t;
+      cnt[rec.kind[i]] += 1;
+    }
+    if (e != hipSuccess) rc = fail(GRMHD_E_DEVICE, hipGetErrorString(e));
+  }
+  for (auto& e : rec.ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  for (int k = 0; k < GRMHD_K_COUNT; ++k) {
+    ms[k] = cnt[k] ? acc[k] / cnt[k] : 0.0;
+    if (counts) counts[k] = cnt[k];
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
+  if (!c || !out) return fail(GRMHD_E_ARG, "null argument");
+  if (!c->have_state) return fail(GRMHD_E_STATE, "no state");
+  // con2prim of the current state, then d_i (sqrt(gamma) B^i) into free scratch slots
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->rnode, c->pp, c->stream));
+  Bases B;
+  B.b[0] = c->U;
+  B.b[1] = c->scr;
+  B.b[2] = (double*)c->res;
+  B.b[3] = nullptr;
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    add(tl, 0, 29 + a, 1, SC_D1 + 21 * a + a);
+    hipError_t e = contract(c, a, 1, OP_D1, OP_D1, tl, B);
+    if (e != hipSuccess) return fail(GRMHD_E_DEVICE, hipGetErrorString(e));
+  }
+  int nb = 0;
+  HIPCHK(launch_diag_partials(c->U, c->prim, c->fail, c->scr, c->wr, c->wth, c->phys.gamma_ad, c->pp,
+                              c->partials, &nb, c->stream));
+  std::vector<double> h((size_t)nb * 8);
+  HIPCHK(hipMemcpyAsync(h.data(), c->partials, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, mx4 = 0, mn5 = INFINITY, mx6 = 0;
+  for (int b = 0; b < nb; ++b) {
+    const double* q = &h[(size_t)b * 8];
+    s0 += q[0];
+    s1 += q[1];
+    s2 += q[2];
+    s3 += q[3];
+    mx4 = fmax(mx4, q[4]);
+    mn5 = fmin(mn5, q[5]);
+    mx6 = fmax(mx6, q[6]);
+  }
+  out->t = c->t;
+  out->step = c->step;
+  out->rest_mass = s0;
+  out->entropy = s1;
+  out->c2p_fail = (int64_t)llround(s2);
+  out->nonfinite = (int64_t)llround(s3);
+  out->max_abs_divB = mx4;
+  out->min_alpha = mn5;
+  out->max_W = mx6;
+  return GRMHD_OK;
+}
+
+double grmhd_dt(const grmhd_ctx* c) { return c ? c->dt : NAN; }
+double grmhd_time(const grmhd_ctx* c) { return c ? c->t : NAN; }
+
+int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* dev_in, double* dev_out,
+                         int32_t nfields) {
+  if (!c || !dev_in || !dev_out) return fail(GRMHD_E_ARG, "null argument");
+  if (axis < 0 || axis > 2 || op < 1 || op > 3) return fail(GRMHD_E_ARG, "axis in 0..2, op in 1..3");
+  if (nfields < 0) return fail(GRMHD_E_ARG, "nfields < 0");
+  Bases B;
+  B.b[0] = const_cast<double*>(dev_in);
+  B.b[1] = dev_out;
+  B.b[2] = nullptr;
+  B.b[3] = nullptr;
+  const int o = op == 1 ? OP_D1 : (op == 2 ? OP_D2 : OP_FILT);
+  for (int f0 = 0; f0 < nfields; f0 += MAX_TASKS) {
+    TaskList tl;
+    tl.n = 0;
+    for (int f = f0; f < nfields && f < f0 + MAX_TASKS; ++f) add(tl, 0, f, 1, f);
+    HIPCHK(contract(c, axis, 1, o, o, tl, B));
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_con2prim(grmhd_ctx* c, const double* dev_U, double* dev_prim, double* dev_flux) {
+  if (!c || !dev_U || !dev_prim) return fail(GRMHD_E_ARG, "null argument");
+  // guesses come from the context's last recovery; results also stored there
+  HIPCHK(launch_c2p_flux(dev_U, c->prim, c->fail, dev_flux, c->rnode, c->pp, c->stream));
+  HIPCHK(hipMemcpyAsync(dev_prim, c->prim, 5 * c->L.P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return GRMHD_OK;
+}
+
+}  // extern "C"

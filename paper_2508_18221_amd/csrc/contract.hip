@@ -1,0 +1,193 @@
+// Dense spectral-operator contractions along grid lines on FP64 MFMA (gfx950).
+//
+// Every derivative and filter of the method (Methods, "The Spectral Derivative
+// Operators", "Dealiasing and Spectral Filtering") is a dense N x N matrix
+// applied along one coordinate of fields laid out [phi][theta][r] (r fastest):
+//   axis r     : out[line][i]    = sum_k A[i][k] in[line][k]     (lines = th*ph)
+//   axis theta : out[o][i][c]    = sum_k A[i][k] in[o][k][c]     (o = phi, c = r)
+//   axis phi   : out[i][c]       = sum_k A[i][k] in[k][c]        (c = theta*r)
+// A workgroup stages one input tile [k = 0..Npad) x [64 columns] in LDS
+// (columns are r-lines for the r axis, contiguous inner points otherwise),
+// reads each input element from HBM once, and applies one or two operators
+// (first and second derivative share the read).  Operators are read
+// transposed (AT[k][i]) from L2 as MFMA fragments.
+//
+// MFMA v_mfma_f64_16x16x4_f64 fragment layout (wave64):
+//   A operand (16x4):  lane l holds A[l % 16][l / 16]
+//   B operand (4x16):  lane l holds B[l / 16][l % 16]
+//   D (16x16, 4 regs): lane l, reg v holds D[(l / 16) + 4 v][l % 16]
+// (the f64 accumulator interleaves rows by 4, unlike the f32 16x16x4 form).
+#include "grmhd_internal.h"
+
+namespace grmhd {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int TILE_COLS = 64;
+constexpr int LDS_STRIDE = 80;  // doubles; 160 dwords = 32 banks offset per row
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// INNER = true : r axis (tile columns are r-lines, output rows are lines)
+// INNER = false: theta / phi axes (tile columns are contiguous inner points)
+template <int NMAT, bool INNER>
+__global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
+                                                  const double* __restrict__ AT0,
+                                                  const double* __restrict__ AT1, int N, int Npad,
+                                                  int inner, int slab, long long P) {
+  extern __shared__ double tile[];  // [Npad][LDS_STRIDE]
+  const Task tk = tl.t[blockIdx.z];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int c0 = blockIdx.x * TILE_COLS;
+  const size_t off = (size_t)blockIdx.y * (size_t)slab;
+  const double* __restrict__ src = B.b[tk.src_sel] + (size_t)tk.src * (size_t)P + off;
+  double* __restrict__ dst0 = B.b[tk.dst_sel] + (size_t)tk.dst0 * (size_t)P + off;
+  double* __restrict__ dst1 = B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + off;
+
+  // ---- stage the input tile ------------------------------------------------
+  if (INNER) {
+    // 64 consecutive lines of N doubles: contiguous in memory; stored transposed
+    const int ncols = min(TILE_COLS, inner - c0);  // lines in this tile
+    const double* __restrict__ s = src + (size_t)c0 * N;
+    for (int e = threadIdx.x; e < TILE_COLS * N; e += 256) {
+      const int line = e / N, k = e - line * N;
+      tile[k * LDS_STRIDE + line] = (line < ncols) ? s[e] : 0.0;
+    }
+    for (int e = threadIdx.x; e < (Npad - N) * TILE_COLS; e += 256)
+      tile[(N + e / TILE_COLS) * LDS_STRIDE + (e % TILE_COLS)] = 0.0;
+  } else {
+    for (int e = threadIdx.x; e < Npad * TILE_COLS; e += 256) {
+      const int k = e >> 6, c = e & 63;
+      double v = 0.0;
+      if (k < N && c0 + c < inner) v = src[(size_t)k * inner + c0 + c];
+      tile[k * LDS_STRIDE + c] = v;
+    }
+  }
+  __syncthreads();
+
+  // ---- work split: i-tiles (operator rows) x column fragments ---------------
+  const int T = Npad >> 4;
+  const int WI = T >= 4 ? 4 : (T >= 2 ? 2 : 1);
+  const int FW = 4 / (4 / WI);  // fragments per wave: 4, 2, 1 for WI = 4, 2, 1
+  const int wi = wave % WI, wf = wave / WI;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  for (int it = wi; it < T; it += WI) {
+    d4 acc[NMAT][4];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[m][f] = d4{0.0, 0.0, 0.0, 0.0};
+    const double* __restrict__ a0p = AT0 + (size_t)lk * Npad + it * 16 + lr;
+    const double* __restrict__ a1p = (NMAT > 1 ? AT1 : AT0) + (size_t)lk * Npad + it * 16 + lr;
+    const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
+#pragma unroll 2
+    for (int k0 = 0; k0 < Npad; k0 += 4) {
+      const double a0 = a0p[(size_t)k0 * Npad];
+      const double a1 = (NMAT > 1) ? a1p[(size_t)k0 * Npad] : 0.0;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if (f < FW) {
+          const double b = tp[k0 * LDS_STRIDE + f * 16];
+          if (INNER) {
+            // D[line][i] = sum_k tile^T[line][k] AT[k][i]
+            acc[0][f] = mfma_f64(b, a0, acc[0][f]);
+            if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(b, a1, acc[NMAT - 1][f]);
+          } else {
+            // D[i][c] = sum_k A[i][k] tile[k][c]
+            acc[0][f] = mfma_f64(a0, b, acc[0][f]);
+            if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(a1, b, acc[NMAT - 1][f]);
+          }
+        }
+      }
+    }
+    // ---- store ------------------------------------------------------------
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if (f < FW) {
+        const int cf = (wf * FW + f) * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = lk + 4 * v;  // D row within the 16x16 block
+          if (INNER) {
+            const int line = c0 + cf + row, i = it * 16 + lr;
+            if (line < inner && i < N) {
+              dst0[(size_t)line * N + i] = acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)line * N + i] = acc[NMAT - 1][f][v];
+            }
+          } else {
+            const int i = it * 16 + row, c = c0 + cf + lr;
+            if (i < N && c < inner) {
+              dst0[(size_t)i * inner + c] = acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)i * inner + c] = acc[NMAT - 1][f][v];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+static size_t lds_bytes(int npad) { return (size_t)npad * LDS_STRIDE * sizeof(double); }
+
+hipError_t set_kernel_attributes() {
+  const int max_lds = 256 * LDS_STRIDE * (int)sizeof(double);  // npad <= 256
+  hipError_t e;
+  if ((e = hipFuncSetAttribute((const void*)k_contract<1, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_contract<2, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_contract<1, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
+    return e;
+  return hipFuncSetAttribute((const void*)k_contract<2, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
+                           const double* AT0, const double* AT1, const int n[3],
+                           const int npad[3], long long P, hipStream_t s) {
+  if (tl.n <= 0) return hipSuccess;
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2)
+    return hipErrorInvalidValue;
+  const int N = n[axis], Npad = npad[axis];
+  int inner, outer, slab;
+  if (axis == 0) {          // lines of length nr, nth*nph of them
+    inner = n[1] * n[2];
+    outer = 1;
+    slab = 0;
+  } else if (axis == 1) {   // [phi][theta][r]: theta rows of nr, one slab per phi
+    inner = n[0];
+    outer = n[2];
+    slab = n[1] * n[0];
+  } else {                  // [phi][theta r]
+    inner = n[0] * n[1];
+    outer = 1;
+    slab = 0;
+  }
+  dim3 grid((inner + TILE_COLS - 1) / TILE_COLS, outer, tl.n);
+  const size_t lds = lds_bytes(Npad);
+  if (axis == 0) {
+    if (nmat == 1)
+      hipLaunchKernelGGL((k_contract<1, true>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                         inner, slab, P);
+    else
+      hipLaunchKernelGGL((k_contract<2, true>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                         inner, slab, P);
+  } else {
+    if (nmat == 1)
+      hipLaunchKernelGGL((k_contract<1, false>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                         inner, slab, P);
+    else
+      hipLaunchKernelGGL((k_contract<2, false>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                         inner, slab, P);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace grmhd

@@ -1,0 +1,114 @@
+// Internal declarations of the gfx950 BSSN + Valencia GRMHD spectral stage.
+// Layout of the device buffers and the launch interface between the host
+// orchestration (abi.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "grmhd.h"
+
+namespace grmhd {
+
+constexpr int NF = 32;    // evolved fields
+constexpr int ND1 = 21;   // fields with first derivatives (0..20)
+constexpr int ND2 = 11;   // fields with second derivatives
+// fields with second derivatives: phi, gt_ij, alpha, beta^i
+constexpr int D2_FIELD[ND2] = {0, 1, 2, 3, 4, 5, 6, 17, 18, 19, 20};
+// fields with first derivatives only: At_ij, K, Gt^i
+constexpr int D1_ONLY[10] = {7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
+
+// Scratch buffer: fields of P doubles.
+enum : int {
+  SC_US = 0,      // 32  stage state U^(s)
+  SC_ACC = 32,    // 32  RK accumulator
+  SC_FLUX = 64,   // 24  alpha sqrt(gamma) F^a of var v at SC_FLUX + 8a + v
+  SC_D1 = 88,     // 63  d_a f at SC_D1 + 21a + f (f = 0..20)
+  SC_D2 = 151,    // 33  d_a d_a of second-derivative field s at SC_D2 + 11a + s
+  SC_MX = 184,    // 33  mixed (r th, r ph, th ph) at SC_MX + 11m + s
+  SC_DF = 217,    // 24  d_a (alpha sqrt(gamma) F^a_v) at SC_DF + 8a + v
+  SC_NFIELDS = 241
+};
+
+// Resident buffer: fields of P doubles, then operators and small arrays.
+enum : int {
+  RS_U = 0,       // 32  state U^n
+  RS_K0 = 32,     // 1   static 1+log source
+  RS_PRIM = 33,   // 5   rho, p, v^r, v^th, v^ph (last recovery; warm start)
+  RS_FAIL = 38,   // 1   1.0 where the atmosphere policy was taken
+  RS_NFIELDS = 39
+};
+
+// Operators per axis: first derivative, second derivative, filter.
+enum : int { OP_D1 = 0, OP_D2 = 1, OP_FILT = 2 };
+
+inline int round_up(int n, int m) { return (n + m - 1) / m * m; }
+
+// One contraction task: out_m = A_m applied along the axis to `src`.
+struct Task {
+  int src_sel, src;     // base selector, field index
+  int dst_sel, dst0;    // destination of matrix 0
+  int dst1;             // destination of matrix 1 (same base as dst0)
+};
+constexpr int MAX_TASKS = 48;
+struct TaskList {
+  int n;
+  Task t[MAX_TASKS];
+};
+// Up to four base pointers a task can address (selectors 0..3).
+struct Bases {
+  double* b[4];
+};
+
+struct PointParams {
+  int nr, nth, nph;
+  long long P;
+  double gamma_ad, eta;
+  int cowling, gauge_k0;
+  double rho_floor, p_floor;
+};
+
+// Host-side operator set (built in long double, stored as double).
+struct Operators {
+  int n[3];            // nr, nth, nph
+  int npad[3];         // padded to multiples of 16
+  // transposed, zero-padded: AT[k * npad + i] = A[i][k]
+  std::vector<double> at[3][3];   // [axis][op]
+  std::vector<double> r, th, ph;  // nodes
+  std::vector<double> wr, wth;    // quadrature weights (d r, d theta)
+  double Lc, Lh, Tc, Th;
+  double dt;
+};
+
+void build_operators(const grmhd_grid& g, double cfl, Operators* ops);
+
+// Host initial data: 32 fields + K0 (P doubles each) in state layout.
+int host_initial_data(const grmhd_grid& g, const grmhd_phys& ph, const Operators& ops,
+                      std::vector<double>* U, std::vector<double>* K0, std::string* err);
+
+// ---- kernel launchers (kernels.hip) --------------------------------------
+// Contraction along axis (0 r, 1 theta, 2 phi) with nmat = 1 or 2 matrices.
+hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
+                           const double* AT0, const double* AT1, const int n[3],
+                           const int npad[3], long long P, hipStream_t s);
+hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
+                           const double* rnode, const PointParams& pp, hipStream_t s);
+// mode 0: out = L(U_s); 1..4: classic RK4 stage s (see kernels.hip)
+hipError_t launch_rhs_rk(int mode, const double* Us, const double* scr, const double* prim,
+                         const double* K0, const double* Un, double* acc, double* out,
+                         double dt, const PointParams& pp, hipStream_t s);
+hipError_t launch_k0(const double* U, const double* scr, double* K0, const PointParams& pp,
+                     hipStream_t s);
+// Per-block partial reductions for diagnostics: writes nblocks x 8 doubles.
+hipError_t launch_diag_partials(const double* U, const double* prim, const double* fail,
+                                const double* scr, const double* wr, const double* wth,
+                                double gamma_ad, const PointParams& pp, double* partials,
+                                int* nblocks, hipStream_t s);
+int diag_partials_blocks(long long P);
+hipError_t set_kernel_attributes();
+
+}  // namespace grmhd

@@ -1,0 +1,342 @@
+// Host initial data: Kerr-Schild background in BSSN variables, magnetised
+// Michel accretion and the seeded density perturbation.
+//
+// Paper: Results, "The Kerr-Schild Metric and 3+1 Decomposition" (line
+// element, H = M r / Sigma, alpha = (1+2H)^(-1/2)); Methods, "BSSN Evolution
+// Equations" (conformal variables).  The matter data are the standard
+// relativistic Bondi (Michel) flow: rest-mass flux rho u^r r^2 and Bernoulli
+// constant h^2 (1 - 2M/r + (u^r)^2) fixed by the sonic point u_c^2 = M/(2 r_c),
+// c_s^2 = u_c^2/(1 - 3 u_c^2) of a polytrope; a monopole field
+// sqrt(gamma) B^r = B0 sin(theta) scaled to a minimum plasma beta.
+//
+// Readings: phi = (1/12) ln det gamma; K_ij = L_beta gamma_ij / (2 alpha)
+// (stationary background) and Gamma-tilde^i = gt^jk Gamma-tilde^i_jk with
+// spectral derivatives; K0 = K - beta^k d_k alpha / (2 alpha); the Michel
+// radial profile is used for every spin with u^theta = u^phi = 0 and u^t from
+// the normalisation; supersonic branch inside r_c, subsonic outside.
+// The background does not depend on phi, so its derivatives are taken on one
+// (theta, r) plane and phi-derivatives are zero.
+#include <math.h>
+#include <stdio.h>
+
+#include <algorithm>
+
+#include "grmhd_internal.h"
+
+namespace grmhd {
+
+namespace {
+
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct Bondi {
+  double M, G, rc, rhoc, n, Tc, Kp, uc, C1, C2;
+  Bondi(double M_, double G_, double rc_, double rhoc_) : M(M_), G(G_), rc(rc_), rhoc(rhoc_) {
+    n = 1.0 / (G - 1.0);
+    const double uc2 = M / (2.0 * rc);
+    const double cs2 = uc2 / (1.0 - 3.0 * uc2);
+    Tc = cs2 / (G - (n + 1.0) * cs2);   // c_s^2 = G T / (1 + (n+1) T)
+    Kp = Tc / pow(rhoc, G - 1.0);
+    uc = sqrt(uc2);
+    C1 = rhoc * uc * rc * rc;
+    C2 = pow(1.0 + (n + 1.0) * Tc, 2) * (1.0 - 2.0 * M / rc + uc2);
+  }
+  // Bernoulli residual as a function of ln T at radius r
+  double F(double lnT, double r) const {
+    const double T = exp(lnT);
+    const double rho = pow(T / Kp, n);
+    const double u = C1 / (r * r * rho);
+    const double h = 1.0 + (n + 1.0) * T;
+    return h * h * (1.0 - 2.0 * M / r + u * u) - C2;
+  }
+  // T = p/rho on the transonic branch: scan ln T, take the first + to - sign
+  // change inside r_c (supersonic) or the last - to + outside (subsonic),
+  // bisect to adjacent doubles; no sign change (double root at r ~ r_c):
+  // golden-section minimum of F.
+  double temperature(double r) const {
+    const int NS = 8001;
+    const double a = log(Tc) - 30.0, b = log(Tc) + 12.0;
+    std::vector<double> g(NS), f(NS);
+    for (int i = 0; i < NS; ++i) {
+      g[i] = a + (b - a) * i / (NS - 1);
+      f[i] = F(g[i], r);
+    }
+    int i0 = -1;
+    for (int i = 0; i + 1 < NS; ++i) {
+      const bool change = (f[i] > 0 && f[i + 1] < 0) || (f[i] < 0 && f[i + 1] > 0);
+      if (!change) continue;
+      if (r < rc) {
+        if (f[i] > 0) { i0 = i; break; }
+      } else if (f[i] < 0) {
+        i0 = i;
+      }
+    }
+    if (i0 < 0) {
+      int im = (int)(std::min_element(f.begin(), f.end()) - f.begin());
+      double lo = g[std::max(im - 1, 0)], hi = g[std::min(im + 1, NS - 1)];
+      const double gr = (sqrt(5.0) - 1.0) / 2.0;
+      for (int it = 0; it < 200; ++it) {
+        const double m1 = hi - gr * (hi - lo), m2 = lo + gr * (hi - lo);
+        if (F(m1, r) < F(m2, r)) hi = m2;
+        else lo = m1;
+      }
+      return exp(0.5 * (lo + hi));
+    }
+    double lo = g[i0], hi = g[i0 + 1];
+    const bool lo_pos = F(lo, r) > 0;
+    for (;;) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(lo < mid && mid < hi)) break;
+      if ((F(mid, r) > 0) == lo_pos) lo = mid;
+      else hi = mid;
+    }
+    return exp(0.5 * (lo + hi));
+  }
+};
+
+// 3x3 symmetric helpers on row-major 9-arrays
+double det3(const double* g) {
+  return g[0] * (g[4] * g[8] - g[5] * g[7]) - g[1] * (g[3] * g[8] - g[5] * g[6]) + g[2] * (g[3] * g[7] - g[4] * g[6]);
+}
+void inv3(const double* g, double* u) {
+  const double d = det3(g);
+  u[0] = (g[4] * g[8] - g[5] * g[7]) / d;
+  u[1] = (g[2] * g[7] - g[1] * g[8]) / d;
+  u[2] = (g[1] * g[5] - g[2] * g[4]) / d;
+  u[3] = (g[5] * g[6] - g[3] * g[8]) / d;
+  u[4] = (g[0] * g[8] - g[2] * g[6]) / d;
+  u[5] = (g[2] * g[3] - g[0] * g[5]) / d;
+  u[6] = (g[3] * g[7] - g[4] * g[6]) / d;
+  u[7] = (g[1] * g[6] - g[0] * g[7]) / d;
+  u[8] = (g[0] * g[4] - g[1] * g[3]) / d;
+}
+const int SI[6] = {0, 0, 0, 1, 1, 2}, SJ[6] = {0, 1, 2, 1, 2, 2};
+
+}  // namespace
+
+int host_initial_data(const grmhd_grid& gr, const grmhd_phys& ph, const Operators& ops,
+                      std::vector<double>* Uout, std::vector<double>* K0out, std::string* err) {
+  const int nr = gr.nr, nth = gr.nth, nph = gr.nph;
+  const size_t P = (size_t)nr * nth * nph, PL = (size_t)nr * nth;
+  const double M = ph.M, a = ph.a;
+  // derivative along r / theta of a plane function f[k * nr + j]
+  auto dr = [&](const std::vector<double>& f, std::vector<double>& out) {
+    const int np = ops.npad[0];
+    const std::vector<double>& AT = ops.at[0][OP_D1];
+    out.assign(PL, 0.0);
+    for (int k = 0; k < nth; ++k)
+      for (int i = 0; i < nr; ++i) {
+        double s = 0.0;
+        for (int m = 0; m < nr; ++m) s += AT[(size_t)m * np + i] * f[(size_t)k * nr + m];
+        out[(size_t)k * nr + i] = s;
+      }
+  };
+  auto dth = [&](const std::vector<double>& f, std::vector<double>& out) {
+    const int np = ops.npad[1];
+    const std::vector<double>& AT = ops.at[1][OP_D1];
+    out.assign(PL, 0.0);
+    for (int i = 0; i < nth; ++i)
+      for (int j = 0; j < nr; ++j) {
+        double s = 0.0;
+        for (int m = 0; m < nth; ++m) s += AT[(size_t)m * np + i] * f[(size_t)m * nr + j];
+        out[(size_t)i * nr + j] = s;
+      }
+  };
+
+  // ---- Kerr-Schild 3+1 fields on the (theta, r) plane ----
+  std::vector<double> alpha(PL), betar(PL), gam[9];
+  for (int c = 0; c < 9; ++c) gam[c].assign(PL, 0.0);
+  for (int k = 0; k < nth; ++k)
+    for (int j = 0; j < nr; ++j) {
+      const size_t e = (size_t)k * nr + j;
+      const double r = ops.r[j], th = ops.th[k];
+      const double S = r * r + a * a * cos(th) * cos(th);
+      const double H = M * r / S;
+      const double s2 = sin(th) * sin(th);
+      alpha[e] = 1.0 / sqrt(1.0 + 2.0 * H);
+      betar[e] = 2.0 * H / (1.0 + 2.0 * H);
+      gam[0][e] = 1.0 + 2.0 * H;
+      gam[2][e] = gam[6][e] = -a * s2 * (1.0 + 2.0 * H);
+      gam[4][e] = S;
+      gam[8][e] = s2 * (S + a * a * s2 * (1.0 + 2.0 * H));
+    }
+  // spectral derivatives of gamma_ij and beta^r along r and theta
+  std::vector<double> dgam[2][9], dbr[2], tmp;
+  for (int c = 0; c < 9; ++c) {
+    dr(gam[c], dgam[0][c]);
+    dth(gam[c], dgam[1][c]);
+  }
+  dr(betar, dbr[0]);
+  dth(betar, dbr[1]);
+
+  std::vector<double> phi(PL), gt[6], At[6], Kf(PL), Gt[3], K0(PL);
+  for (int s = 0; s < 6; ++s) {
+    gt[s].assign(PL, 0.0);
+    At[s].assign(PL, 0.0);
+  }
+  for (int i = 0; i < 3; ++i) Gt[i].assign(PL, 0.0);
+  for (size_t e = 0; e < PL; ++e) {
+    double g[9], gu[9];
+    for (int c = 0; c < 9; ++c) g[c] = gam[c][e];
+    inv3(g, gu);
+    phi[e] = log(det3(g)) / 12.0;
+    const double em4 = exp(-4.0 * phi[e]);
+    // K_ij = (beta^k d_k gamma_ij + gamma_ik d_j beta^k + gamma_jk d_i beta^k)/(2 alpha);
+    // only beta^r is non-zero, phi-derivatives vanish
+    double Kij[9];
+    for (int i = 0; i < 3; ++i)
+      for (int jj = 0; jj < 3; ++jj) {
+        double v = betar[e] * dgam[0][i * 3 + jj][e];
+        if (jj < 2) v += g[i * 3 + 0] * dbr[jj][e];
+        if (i < 2) v += g[jj * 3 + 0] * dbr[i][e];
+        Kij[i * 3 + jj] = v / (2.0 * alpha[e]);
+      }
+    double K = 0.0;
+    for (int c = 0; c < 9; ++c) K += gu[c] * Kij[c];
+    Kf[e] = K;
+    for (int s = 0; s < 6; ++s) {
+      const int c = SI[s] * 3 + SJ[s];
+      gt[s][e] = em4 * g[c];
+      At[s][e] = em4 * (Kij[c] - g[c] * K / 3.0);
+    }
+  }
+  // Gamma-tilde^i = gt^jk Gamma-tilde^i_jk from spectral derivatives of gt_ij
+  {
+    std::vector<double> dgt[2][6];
+    for (int s = 0; s < 6; ++s) {
+      dr(gt[s], dgt[0][s]);
+      dth(gt[s], dgt[1][s]);
+    }
+    for (size_t e = 0; e < PL; ++e) {
+      double g[9], gu[9], d[3][9];
+      for (int s = 0; s < 6; ++s) {
+        const int i = SI[s], jj = SJ[s];
+        g[i * 3 + jj] = g[jj * 3 + i] = gt[s][e];
+        for (int q = 0; q < 2; ++q) d[q][i * 3 + jj] = d[q][jj * 3 + i] = dgt[q][s][e];
+        d[2][i * 3 + jj] = d[2][jj * 3 + i] = 0.0;
+      }
+      inv3(g, gu);
+      // Gamma-tilde_ljk = (d_j g_lk + d_k g_lj - d_l g_jk)/2
+      for (int i = 0; i < 3; ++i) {
+        double s = 0.0;
+        for (int l = 0; l < 3; ++l)
+          for (int jj = 0; jj < 3; ++jj)
+            for (int kk = 0; kk < 3; ++kk) {
+              const double Gl = 0.5 * (d[jj][l * 3 + kk] + d[kk][l * 3 + jj] - d[l][jj * 3 + kk]);
+              s += gu[i * 3 + l] * gu[jj * 3 + kk] * Gl;
+            }
+        Gt[i][e] = s;
+      }
+    }
+  }
+  // K0 = K - beta^k d_k alpha / (2 alpha)
+  {
+    std::vector<double> dal;
+    dr(alpha, dal);
+    for (size_t e = 0; e < PL; ++e) K0[e] = Kf[e] - betar[e] * dal[e] / (2.0 * alpha[e]);
+  }
+
+  // ---- Michel matter + monopole ----
+  const Bondi mic(M, ph.gamma_ad, ph.r_c, ph.rho_c);
+  std::vector<double> rho1(nr), p1(nr), ur1(nr);
+  for (int j = 0; j < nr; ++j) {
+    const double r = ops.r[j];
+    const double T = mic.temperature(r);
+    rho1[j] = pow(T / mic.Kp, mic.n);
+    p1[j] = rho1[j] * T;
+    ur1[j] = -mic.C1 / (r * r * rho1[j]);
+  }
+  std::vector<double> vr(PL), sqrtg(PL), Br1(PL);
+  double min_pb = INFINITY;
+  for (int k = 0; k < nth; ++k)
+    for (int j = 0; j < nr; ++j) {
+      const size_t e = (size_t)k * nr + j;
+      const double r = ops.r[j], th = ops.th[k];
+      const double S = r * r + a * a * cos(th) * cos(th);
+      const double H = M * r / S;
+      // u^t from g_tt (u^t)^2 + 2 g_tr u^t u^r + g_rr (u^r)^2 = -1
+      const double gtt = -(1.0 - 2.0 * H), gtr = 2.0 * H, grr = 1.0 + 2.0 * H;
+      const double ur = ur1[j];
+      const double A = gtt, Bq = gtr * ur, C = grr * ur * ur + 1.0;
+      const double ut = C / (-Bq + sqrt(Bq * Bq - A * C));
+      const double W = alpha[e] * ut;
+      vr[e] = ur / W + betar[e] / alpha[e];
+      double gtm[9];
+      for (int s = 0; s < 6; ++s) gtm[SI[s] * 3 + SJ[s]] = gtm[SJ[s] * 3 + SI[s]] = gt[s][e];
+      sqrtg[e] = exp(6.0 * phi[e]) * sqrt(det3(gtm));
+      // b^2 for B^r = sin(theta)/sqrt(gamma) (B0 = 1), v = (v^r, 0, 0)
+      const double e4 = exp(4.0 * phi[e]);
+      const double g_rr = e4 * gt[0][e];
+      Br1[e] = sin(th) / sqrtg[e];
+      const double vv = g_rr * vr[e] * vr[e];
+      const double Wv = 1.0 / sqrt(1.0 - vv);
+      const double B2 = g_rr * Br1[e] * Br1[e], Bv = g_rr * Br1[e] * vr[e];
+      const double b2 = B2 / (Wv * Wv) + Bv * Bv;
+      min_pb = std::min(min_pb, p1[j] / b2);
+    }
+  const double B0 = sqrt(2.0 * min_pb / ph.beta_min);
+
+  // ---- assemble the 3D state ----
+  Uout->assign((size_t)NF * P, 0.0);
+  K0out->assign(P, 0.0);
+  std::vector<double>& U = *Uout;
+  const double G = ph.gamma_ad;
+  for (int l = 0; l < nph; ++l)
+    for (int k = 0; k < nth; ++k)
+      for (int j = 0; j < nr; ++j) {
+        const size_t e = (size_t)k * nr + j;
+        const size_t n = ((size_t)l * nth + k) * nr + j;
+        U[0 * P + n] = phi[e];
+        for (int s = 0; s < 6; ++s) {
+          U[(1 + s) * P + n] = gt[s][e];
+          U[(7 + s) * P + n] = At[s][e];
+        }
+        U[13 * P + n] = Kf[e];
+        for (int i = 0; i < 3; ++i) U[(14 + i) * P + n] = Gt[i][e];
+        U[17 * P + n] = alpha[e];
+        U[18 * P + n] = betar[e];
+        (*K0out)[n] = K0[e];
+        // matter
+        double rho = rho1[j];
+        const double p = p1[j];
+        if (ph.pert_amp != 0.0) {
+          const double u = (double)(splitmix64(ph.seed ^ (uint64_t)n) >> 11) * 0x1.0p-53;
+          rho = rho * (1.0 + ph.pert_amp * (2.0 * u - 1.0));
+        }
+        const double e4 = exp(4.0 * phi[e]);
+        double gm[9];
+        for (int s = 0; s < 6; ++s) gm[SI[s] * 3 + SJ[s]] = gm[SJ[s] * 3 + SI[s]] = e4 * gt[s][e];
+        const double v[3] = {vr[e], 0.0, 0.0};
+        const double Bu[3] = {B0 * Br1[e], 0.0, 0.0};
+        double vl[3], Bl[3];
+        for (int i = 0; i < 3; ++i) {
+          vl[i] = gm[i * 3 + 0] * v[0] + gm[i * 3 + 1] * v[1] + gm[i * 3 + 2] * v[2];
+          Bl[i] = gm[i * 3 + 0] * Bu[0] + gm[i * 3 + 1] * Bu[1] + gm[i * 3 + 2] * Bu[2];
+        }
+        const double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
+        const double W = 1.0 / sqrt(1.0 - v2);
+        const double Bv = Bu[0] * vl[0] + Bu[1] * vl[1] + Bu[2] * vl[2];
+        const double B2 = Bu[0] * Bl[0] + Bu[1] * Bl[1] + Bu[2] * Bl[2];
+        const double h = 1.0 + p / rho * G / (G - 1.0);
+        const double Z = rho * h * W * W;
+        const double D = rho * W;
+        const double tau = Z - p + B2 - 0.5 * (B2 / (W * W) + Bv * Bv) - D;
+        const double sg = sqrtg[e];
+        U[24 * P + n] = sg * D;
+        for (int i = 0; i < 3; ++i) U[(25 + i) * P + n] = sg * ((Z + B2) * vl[i] - Bv * Bl[i]);
+        U[28 * P + n] = sg * tau;
+        U[29 * P + n] = B0 * sin(ops.th[k]);
+      }
+  if (!(B0 > 0.0) || !std::isfinite(B0)) {
+    if (err) *err = "initial data: field normalisation failed";
+    return GRMHD_E_ARG;
+  }
+  return GRMHD_OK;
+}
+
+}  // namespace grmhd

@@ -1,0 +1,747 @@
+// Pointwise kernels of the RHS evaluation (one thread per grid point,
+// structure-of-arrays FP64 streaming from HBM):
+//   k_c2p_flux : metric reconstruction, primitive recovery, densitised fluxes
+//   k_rhs_rk   : BSSN + gauge RHS with matter sources, Valencia RHS
+//                (-div + sqrt(gamma) S), boundary freeze, RK4 stage update
+//   k_k0       : static 1+log source K0 = K - beta^k d_k alpha/(2 alpha)
+//   k_diag     : per-block partial sums / extrema for diagnostics
+//
+// Paper: Results, "GRMHD Conservative Form" (conserved variables, fluxes,
+// Lorentz factor, magnetic four-vector, source term); Methods, "The Primitive
+// Variable Recovery", "The Conserved Fluxes and Geometric Source Terms",
+// "Stress-Energy Tensor", "BSSN Evolution Equations", "Gauge Conditions",
+// "Time Integration".  Forms used where the printed equations are garbled:
+// standard Valencia conserved variables and fluxes with lapse and shift
+// (vt^i = v^i - beta^i/alpha, conservation law for sqrt(gamma) U with flux
+// alpha sqrt(gamma) F^i), 3+1 source terms, textbook BSSN Ricci tensor with
+// phi = (1/12) ln det gamma, the +12 alpha A^ij d_j phi term in the
+// Gamma-tilde equation, Gamma-tilde from the conformal metric wherever it is
+// not differentiated.
+#include <math.h>
+
+#include "grmhd_internal.h"
+
+namespace grmhd {
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+// symmetric 3x3 storage: xx xy xz yy yz zz
+__device__ __forceinline__ int S6(int i, int j) {
+  const int t[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  return t[i][j];
+}
+
+struct Sym {
+  double m[6];
+  __device__ __forceinline__ double operator()(int i, int j) const { return m[S6(i, j)]; }
+};
+
+__device__ __forceinline__ double det_sym(const Sym& g) {
+  return g.m[0] * (g.m[3] * g.m[5] - g.m[4] * g.m[4]) - g.m[1] * (g.m[1] * g.m[5] - g.m[4] * g.m[2]) +
+         g.m[2] * (g.m[1] * g.m[4] - g.m[3] * g.m[2]);
+}
+
+__device__ __forceinline__ Sym inv_sym(const Sym& g, double det) {
+  const double id = 1.0 / det;
+  Sym u;
+  u.m[0] = (g.m[3] * g.m[5] - g.m[4] * g.m[4]) * id;
+  u.m[1] = (g.m[2] * g.m[4] - g.m[1] * g.m[5]) * id;
+  u.m[2] = (g.m[1] * g.m[4] - g.m[2] * g.m[3]) * id;
+  u.m[3] = (g.m[0] * g.m[5] - g.m[2] * g.m[2]) * id;
+  u.m[4] = (g.m[1] * g.m[2] - g.m[0] * g.m[4]) * id;
+  u.m[5] = (g.m[0] * g.m[3] - g.m[1] * g.m[1]) * id;
+  return u;
+}
+
+__device__ __forceinline__ void mv(const Sym& g, const double* v, double* out) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) out[i] = g(i, 0) * v[0] + g(i, 1) * v[1] + g(i, 2) * v[2];
+}
+
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// ---- primitive recovery ------------------------------------------------------
+// Unknown Z = rho h W^2.  From S_j = (Z + B^2) v_j - (B.v) B_j and B.S = Z B.v:
+//   v^2(Z) = (Z^2 S^2 + (2Z + B^2)(B.S)^2) / (Z^2 (Z + B^2)^2)
+// and tau + D = Z + B^2 - p - B^2/(2W^2) - (B.S)^2/(2 Z^2) with the ideal-gas
+// p = (Gamma-1)/Gamma (Z/W^2 - D/W).  Newton iteration on the residual with
+// analytic derivative, kept inside a bracket [lo, hi] that shrinks with the
+// sign of the residual (bisection whenever a step leaves it or v^2 >= 1).
+struct C2POut {
+  double rho, p, v[3];
+  int fail;
+};
+
+__device__ C2POut con2prim(double D, const double* S, double tau, const double* B, const Sym& gam,
+                           const Sym& gamu, double G, double rho_fl, double p_fl,
+                           double zguess) {
+  C2POut o;
+  double Su[3], Bl[3];
+  mv(gamu, S, Su);
+  mv(gam, B, Bl);
+  const double S2 = dot3(S, Su), B2 = dot3(B, Bl), BS = dot3(B, S), BS2 = BS * BS;
+  const double gf = (G - 1.0) / G;
+  bool bad = !(D > 0.0 && tau + D > 0.0);
+  const double Dc = bad ? 1.0 : D, Ec = bad ? 2.0 : tau + D;
+  double lo = 0.0, hi = G * Ec + B2 + 1e-300;
+  // residual f and derivative; returns false where v^2 >= 1 (Z below range)
+  auto resid = [&](double Z, double& f, double& fp) -> bool {
+    const double a = Z + B2;
+    const double Z2 = Z * Z, a2 = a * a;
+    const double v2 = (Z2 * S2 + (2.0 * Z + B2) * BS2) / (Z2 * a2);
+    if (!(v2 < 1.0) || !(Z > 0.0)) return false;
+    const double iw2 = 1.0 - v2, sq = sqrt(iw2);
+    const double dv2 = -2.0 * S2 / (a2 * a) - 2.0 * BS2 * (3.0 * Z2 + 3.0 * Z * B2 + B2 * B2) / (Z2 * Z * a2 * a);
+    const double p = gf * (Z * iw2 - Dc * sq);
+    const double dp = gf * (iw2 - Z * dv2 + Dc * dv2 / (2.0 * sq));
+    f = Z + B2 - p - 0.5 * B2 * iw2 - 0.5 * BS2 / Z2 - Ec;
+    fp = 1.0 - dp + 0.5 * B2 * dv2 + BS2 / (Z2 * Z);
+    return true;
+  };
+  double f, fp;
+  for (int w = 0; w < 8; ++w) {  // make sure the upper end has f >= 0
+    if (resid(hi, f, fp) && f >= 0.0) break;
+    hi *= 2.0;
+  }
+  if (!(resid(hi, f, fp) && f >= 0.0)) bad = true;
+  double Z = (zguess > lo && zguess < hi) ? zguess : 0.5 * (lo + hi);
+  if (!bad) {
+    for (int it = 0; it < 200; ++it) {
+      double zn;
+      if (!resid(Z, f, fp)) {
+        lo = Z;
+        zn = 0.5 * (lo + hi);
+      } else {
+        if (f < 0.0) lo = Z;
+        else hi = Z;
+        zn = Z - f / fp;
+        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+        if (fabs(zn - Z) <= 1e-15 * zn) {
+          Z = zn;
+          break;
+        }
+      }
+      if (!(zn > lo && zn < hi)) {  // bracket collapsed onto adjacent doubles
+        Z = hi;
+        break;
+      }
+      Z = zn;
+    }
+  }
+  double vl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) vl[i] = (S[i] + BS * Bl[i] / Z) / (Z + B2);
+  mv(gamu, vl, o.v);
+  const double v2 = dot3(o.v, vl);
+  const double W = 1.0 / sqrt(1.0 - v2);
+  o.rho = Dc / W;
+  o.p = gf * (Z / (W * W) - o.rho);
+  o.fail = bad || !(v2 < 1.0) || !(o.rho >= rho_fl) || !(o.p >= p_fl);
+  if (o.fail) {
+    o.rho = rho_fl;
+    o.p = p_fl;
+    o.v[0] = o.v[1] = o.v[2] = 0.0;
+  }
+  return o;
+}
+
+// Magnetic quantities for Eulerian field B^i and velocity v^i:
+// W, alpha b^0 = W (B.v), b_i = B_i/W + W (B.v) v_i, b^2 = B^2/W^2 + (B.v)^2.
+struct Mag {
+  double W, ab0, bl[3], b2, vl[3];
+};
+
+__device__ __forceinline__ Mag magnetic(const double* v, const double* B, const Sym& gam) {
+  Mag m;
+  double Bl[3];
+  mv(gam, v, m.vl);
+  mv(gam, B, Bl);
+  m.W = 1.0 / sqrt(1.0 - dot3(v, m.vl));
+  const double Bv = dot3(B, m.vl), B2 = dot3(B, Bl);
+  m.ab0 = m.W * Bv;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) m.bl[i] = Bl[i] / m.W + m.W * Bv * m.vl[i];
+  m.b2 = B2 / (m.W * m.W) + Bv * Bv;
+  return m;
+}
+
+__device__ __forceinline__ double rnode_floor(const double* rn, int j, double scale, double ex) {
+  return scale * pow(rn[j], ex);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
+                                                  double* __restrict__ prim,
+                                                  double* __restrict__ fail,
+                                                  double* __restrict__ flux,
+                                                  const double* __restrict__ rnode, PointParams pp) {
+  const long long P = pp.P;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P) return;
+  const int j = (int)(idx % pp.nr);
+#define LD(f) U[(size_t)(f) * P + idx]
+  const double phi = LD(0);
+  Sym gt;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gt.m[s] = LD(1 + s);
+  const double alpha = LD(17);
+  double beta[3] = {LD(18), LD(19), LD(20)};
+  const double e4 = exp(4.0 * phi);
+  const double detgt = det_sym(gt);
+  const double sqrtg = exp(6.0 * phi) * sqrt(detgt);
+  Sym gam;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gam.m[s] = e4 * gt.m[s];
+  const Sym gamu = inv_sym(gam, e4 * e4 * e4 * detgt);
+  const double isg = 1.0 / sqrtg;
+  const double D = LD(24) * isg, tau = LD(28) * isg;
+  double S[3] = {LD(25) * isg, LD(26) * isg, LD(27) * isg};
+  double B[3] = {LD(29) * isg, LD(30) * isg, LD(31) * isg};
+#undef LD
+  // warm start Z = rho h W^2 from the last recovered primitives
+  double zg = -1.0;
+  {
+    const double rg = prim[idx], pg = prim[(size_t)P + idx];
+    double vg[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    double vgl[3];
+    mv(gam, vg, vgl);
+    const double v2 = dot3(vg, vgl);
+    if (rg > 0.0 && pg > 0.0 && v2 < 1.0)
+      zg = (rg + pg * pp.gamma_ad / (pp.gamma_ad - 1.0)) / (1.0 - v2);
+  }
+  const double rho_fl = rnode_floor(rnode, j, pp.rho_floor, -1.5);
+  const double p_fl = rnode_floor(rnode, j, pp.p_floor, -2.5);
+  C2POut c = con2prim(D, S, tau, B, gam, gamu, pp.gamma_ad, rho_fl, p_fl, zg);
+  prim[idx] = c.rho;
+  prim[(size_t)P + idx] = c.p;
+  prim[2 * (size_t)P + idx] = c.v[0];
+  prim[3 * (size_t)P + idx] = c.v[1];
+  prim[4 * (size_t)P + idx] = c.v[2];
+  fail[idx] = c.fail ? 1.0 : 0.0;
+  if (flux == nullptr) return;
+  const Mag m = magnetic(c.v, B, gam);
+  const double ps = c.p + 0.5 * m.b2;
+  const double asg = alpha * sqrtg;
+  const double iW = 1.0 / m.W;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double vta = c.v[a] - beta[a] / alpha;
+    double* F = flux + (size_t)(8 * a) * P + idx;
+    F[0] = asg * D * vta;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+      F[(size_t)(1 + jj) * P] = asg * (S[jj] * vta - m.bl[jj] * B[a] * iW + (a == jj ? ps : 0.0));
+    F[(size_t)4 * P] = asg * (tau * vta + ps * c.v[a] - m.ab0 * B[a] * iW);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double vtk = c.v[k] - beta[k] / alpha;
+      F[(size_t)(5 + k) * P] = asg * (vta * B[k] - vtk * B[a]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Second-derivative field index s: phi 0, gt 1..6, alpha 7, beta 8..10.
+// Us, Un, acc and out may alias (in-place stages): no restrict on them; every
+// element is read and written by the same thread.
+__global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
+                                                const double* __restrict__ scr,
+                                                const double* __restrict__ prim,
+                                                const double* __restrict__ K0p,
+                                                const double* Un, double* acc, double* out,
+                                                double dt, PointParams pp) {
+  const long long P = pp.P;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P) return;
+  const int j = (int)(idx % pp.nr);
+  const int k = (int)((idx / pp.nr) % pp.nth);
+#define LU(f) Us[(size_t)(f) * P + idx]
+#define LS(f) scr[(size_t)(f) * P + idx]
+#define D1(a, f) LS(SC_D1 + 21 * (a) + (f))
+  // second derivative d_a d_b of field s
+  auto DD = [&](int a, int b, int s) -> double {
+    if (a == b) return LS(SC_D2 + 11 * a + s);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int m = (lo == 0) ? (hi == 1 ? 0 : 1) : 2;
+    return LS(SC_MX + 11 * m + s);
+  };
+
+  const double phi = LU(0);
+  Sym gt, At;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    gt.m[s] = LU(1 + s);
+    At.m[s] = LU(7 + s);
+  }
+  const double K = LU(13);
+  const double Gt[3] = {LU(14), LU(15), LU(16)};
+  const double alpha = LU(17);
+  const double beta[3] = {LU(18), LU(19), LU(20)};
+  const double Bd[3] = {LU(21), LU(22), LU(23)};
+
+  const double detgt = det_sym(gt);
+  const Sym gtu = inv_sym(gt, detgt);
+  const double e4 = exp(4.0 * phi), em4 = 1.0 / e4;
+  const double sqrtg = e4 * exp(2.0 * phi) * sqrt(detgt);
+
+  double dphi[3], dal[3], dK[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dphi[a] = D1(a, 0);
+    dal[a] = D1(a, 17);
+    dK[a] = D1(a, 13);
+  }
+  double dbeta[3][3];  // [a][i] = d_a beta^i
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dbeta[a][i] = D1(a, 18 + i);
+  const double divb = dbeta[0][0] + dbeta[1][1] + dbeta[2][2];
+
+  // conformal Christoffels: Gl_ijk = (d_j gt_ik + d_k gt_ij - d_i gt_jk)/2 ; Gu^i_jk
+  double Gl[3][6], Gu[3][6];
+  double adv_gt[6];
+  {
+    double dgt[3][6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int s = 0; s < 6; ++s) dgt[a][s] = D1(a, 1 + s);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) adv_gt[s] = beta[0] * dgt[0][s] + beta[1] * dgt[1][s] + beta[2] * dgt[2][s];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int kk = jj; kk < 3; ++kk)
+          Gl[i][S6(jj, kk)] = 0.5 * (dgt[jj][S6(i, kk)] + dgt[kk][S6(i, jj)] - dgt[i][S6(jj, kk)]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) Gu[i][s] = gtu(i, 0) * Gl[0][s] + gtu(i, 1) * Gl[1][s] + gtu(i, 2) * Gl[2][s];
+  double Gd[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) s += gtu(jj, kk) * Gu[i][S6(jj, kk)];
+    Gd[i] = s;
+  }
+
+  // ---- Ricci tensor R_ij = Rt_ij + Rphi_ij ----------------------------------
+  Sym R;
+  {
+    double dGt[3][3];  // [a][i] = d_a Gt^i
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dGt[a][i] = D1(a, 14 + i);
+    // -1/2 gt^{lm} d_l d_m gt_ij
+#pragma unroll
+    for (int s = 0; s < 6; ++s) R.m[s] = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double w = -0.5 * gtu(l, m);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) R.m[s] += w * DD(l, m, 1 + s);
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj) {
+        double t = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          // gt_k(i d_j) Gt^k
+          t += 0.5 * (gt(kk, i) * dGt[jj][kk] + gt(kk, jj) * dGt[i][kk]);
+          // Gd^k Gl_(ij)k
+          t += 0.5 * Gd[kk] * (Gl[i][S6(jj, kk)] + Gl[jj][S6(i, kk)]);
+        }
+        // gt^{lm} (Gu^k_li Gl_jkm + Gu^k_lj Gl_ikm + Gu^k_im Gl_klj)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            double q = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk)
+              q += Gu[kk][S6(l, i)] * Gl[jj][S6(kk, m)] + Gu[kk][S6(l, jj)] * Gl[i][S6(kk, m)] +
+                   Gu[kk][S6(i, m)] * Gl[kk][S6(l, jj)];
+            t += gtu(l, m) * q;
+          }
+        R.m[S6(i, jj)] += t;
+      }
+    // conformal-factor part
+    double DDphi[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj)
+        DDphi[S6(i, jj)] = DD(i, jj, 0) - (Gu[0][S6(i, jj)] * dphi[0] + Gu[1][S6(i, jj)] * dphi[1] +
+                                           Gu[2][S6(i, jj)] * dphi[2]);
+    double lap = 0.0, grad2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        lap += gtu(l, m) * DDphi[S6(l, m)];
+        grad2 += gtu(l, m) * dphi[l] * dphi[m];
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj) {
+        const int s = S6(i, jj);
+        R.m[s] += -2.0 * DDphi[s] - 2.0 * gt.m[s] * lap + 4.0 * dphi[i] * dphi[jj] - 4.0 * gt.m[s] * grad2;
+      }
+  }
+
+  // ---- D_i D_j alpha with the physical Christoffels --------------------------
+  double DDa[6];
+  {
+    double dphiu[3];
+    mv(gtu, dphi, dphiu);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj) {
+        const int s = S6(i, jj);
+        double t = DD(i, jj, 7);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const double Gp = Gu[kk][s] + 2.0 * ((kk == i ? dphi[jj] : 0.0) + (kk == jj ? dphi[i] : 0.0) -
+                                               gt.m[s] * dphiu[kk]);
+          t -= Gp * dal[kk];
+        }
+        DDa[s] = t;
+      }
+  }
+  double trDDa = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) trDDa += gtu(l, m) * DDa[S6(l, m)];
+  trDDa *= em4;
+
+  // ---- A-tilde contractions ------------------------------------------------------
+  double Amix[3][3];  // A_ik gt^kl  (mixed A_i^l)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) Amix[i][l] = At(i, 0) * gtu(0, l) + At(i, 1) * gtu(1, l) + At(i, 2) * gtu(2, l);
+  Sym Atu;  // gt^ik gt^jl A_kl
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = i; jj < 3; ++jj)
+      Atu.m[S6(i, jj)] = gtu(i, 0) * Amix[0][jj] + gtu(i, 1) * Amix[1][jj] + gtu(i, 2) * Amix[2][jj];
+  double AA = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) AA += At(i, jj) * Atu(i, jj);
+
+  // ---- matter: E = tau + D, S_j, S_ij from the recovered primitives -------------
+  const double isg = 1.0 / sqrtg;
+  const double Em = (LU(28) + LU(24)) * isg;
+  const double Sl[3] = {LU(25) * isg, LU(26) * isg, LU(27) * isg};
+  Sym gam, gamu;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    gam.m[s] = e4 * gt.m[s];
+    gamu.m[s] = em4 * gtu.m[s];
+  }
+  Sym Sij;
+  {
+    const double rho = prim[idx], p = prim[(size_t)P + idx];
+    const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
+    const Mag m = magnetic(v, B, gam);
+    const double h = 1.0 + p / rho * pp.gamma_ad / (pp.gamma_ad - 1.0);
+    const double cw = (rho * h + m.b2) * m.W * m.W;
+    const double ps = p + 0.5 * m.b2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj)
+        Sij.m[S6(i, jj)] = cw * m.vl[i] * m.vl[jj] + ps * gam.m[S6(i, jj)] - m.bl[i] * m.bl[jj];
+  }
+  double Sup[3][3];  // S^{kl} = gamma^{ki} gamma^{lj} S_ij
+  {
+    double t[3][3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) t[kk][jj] = gamu(kk, 0) * Sij(0, jj) + gamu(kk, 1) * Sij(1, jj) + gamu(kk, 2) * Sij(2, jj);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) Sup[kk][l] = t[kk][0] * gamu(l, 0) + t[kk][1] * gamu(l, 1) + t[kk][2] * gamu(l, 2);
+  }
+  double Str = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) Str += gamu(i, jj) * Sij(i, jj);
+
+  double rhs[32];
+  // ---- BSSN ------------------------------------------------------------------------
+  rhs[0] = -alpha * K / 6.0 + dot3(beta, dphi) + divb / 6.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = i; jj < 3; ++jj) {
+      const int s = S6(i, jj);
+      double lie = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) lie += gt(i, kk) * dbeta[jj][kk] + gt(jj, kk) * dbeta[i][kk];
+      rhs[1 + s] = -2.0 * alpha * At.m[s] + adv_gt[s] + lie - (2.0 / 3.0) * gt.m[s] * divb;
+    }
+  rhs[13] = -trDDa + alpha * (AA + K * K / 3.0) + 4.0 * PI * alpha * (Em + Str) + dot3(beta, dK);
+  {
+    double X[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) X[s] = -DDa[s] + alpha * (R.m[s] - 8.0 * PI * Sij.m[s]);
+    double trX = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) trX += gtu(l, m) * X[S6(l, m)];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj) {
+        const int s = S6(i, jj);
+        double AAij = At(i, 0) * Amix[jj][0] + At(i, 1) * Amix[jj][1] + At(i, 2) * Amix[jj][2];
+        double lie = 0.0, adv = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          lie += At(i, kk) * dbeta[jj][kk] + At(jj, kk) * dbeta[i][kk];
+          adv += beta[kk] * D1(kk, 7 + s);
+        }
+        rhs[7 + s] = em4 * (X[s] - gt.m[s] * trX / 3.0) + alpha * (K * At.m[s] - 2.0 * AAij) + adv + lie -
+                     (2.0 / 3.0) * At.m[s] * divb;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      t += -2.0 * Atu(i, jj) * dal[jj];
+      t += 2.0 * alpha * (6.0 * Atu(i, jj) * dphi[jj] - (2.0 / 3.0) * gtu(i, jj) * dK[jj]);
+      t += -16.0 * PI * alpha * gtu(i, jj) * Sl[jj];
+      t += beta[jj] * D1(jj, 14 + i) - Gd[jj] * dbeta[jj][i];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        t += 2.0 * alpha * Gu[i][S6(jj, kk)] * Atu(jj, kk);
+        t += gtu(jj, kk) * DD(jj, kk, 8 + i);
+        t += gtu(i, jj) * DD(jj, kk, 8 + kk) / 3.0;
+      }
+    }
+    rhs[14 + i] = t + (2.0 / 3.0) * Gd[i] * divb;
+  }
+  const double K0 = K0p[idx];
+  rhs[17] = dot3(beta, dal) - 2.0 * alpha * (pp.gauge_k0 ? (K - K0) : K);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rhs[18 + i] = 0.75 * Bd[i];
+    rhs[21 + i] = rhs[14 + i] - pp.eta * Bd[i];
+  }
+  if (pp.cowling) {
+#pragma unroll
+    for (int f = 0; f < 24; ++f) rhs[f] = 0.0;
+  }
+
+  // ---- Valencia: -d_a(alpha sqrt(gamma) F^a) + sqrt(gamma) Sbar -----------------
+  {
+    double src[3];
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      double t = -Em * dal[jj];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) t += Sl[kk] * dbeta[jj][kk];
+      double q = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const double dgam = e4 * (D1(jj, 1 + S6(kk, l)) + 4.0 * gt(kk, l) * dphi[jj]);
+          q += Sup[kk][l] * dgam;
+        }
+      src[jj] = t + 0.5 * alpha * q;
+    }
+    double srcT = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) srcT += Sup[kk][l] * e4 * (At(kk, l) + gt(kk, l) * K / 3.0);
+    srcT *= alpha;
+    double Su[3];
+    mv(gamu, Sl, Su);
+    srcT -= dot3(Su, dal);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double div = LS(SC_DF + v) + LS(SC_DF + 8 + v) + LS(SC_DF + 16 + v);
+      rhs[24 + v] = -div;
+    }
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) rhs[25 + jj] += sqrtg * src[jj];
+    rhs[28] += sqrtg * srcT;
+  }
+#undef D1
+#undef LS
+
+  // ---- boundary freeze: r_out nodes and theta end nodes ---------------------------
+  if (j == 0 || k == 0 || k == pp.nth - 1) {
+#pragma unroll
+    for (int f = 0; f < 32; ++f) rhs[f] = 0.0;
+  }
+
+  // ---- output / classic RK4 stage --------------------------------------------------
+  // mode 0: out = k; 1: acc = k/6, out = Un + dt/2 k; 2: acc += k/3, out = Un + dt/2 k;
+  // 3: acc += k/3, out = Un + dt k; 4: out = Un + dt (acc + k/6)
+#pragma unroll
+  for (int f = 0; f < 32; ++f) {
+    const size_t e = (size_t)f * P + idx;
+    const double kf = rhs[f];
+    if (mode == 0) {
+      out[e] = kf;
+    } else if (mode == 1) {
+      acc[e] = kf / 6.0;
+      out[e] = Un[e] + 0.5 * dt * kf;
+    } else if (mode == 2) {
+      acc[e] += kf / 3.0;
+      out[e] = Un[e] + 0.5 * dt * kf;
+    } else if (mode == 3) {
+      acc[e] += kf / 3.0;
+      out[e] = Un[e] + dt * kf;
+    } else {
+      out[e] = Un[e] + dt * (acc[e] + kf / 6.0);
+    }
+  }
+#undef LU
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_k0(const double* __restrict__ U, const double* __restrict__ scr,
+                                            double* __restrict__ K0, long long P) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P) return;
+  const double alpha = U[17 * (size_t)P + idx];
+  double adv = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) adv += U[(size_t)(18 + a) * P + idx] * scr[(size_t)(SC_D1 + 21 * a + 17) * P + idx];
+  K0[idx] = U[13 * (size_t)P + idx] - adv / (2.0 * alpha);
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics partials per block (fixed-order tree; no floating-point atomics):
+// [0] sum sqrt(g) D w, [1] sum rho s sqrt(g) w, [2] fails, [3] non-finite count,
+// [4] max |div B| (from scratch d1 slots of sqrt(g)B), [5] min alpha, [6] max W
+constexpr int DIAG_THREADS = 256;
+
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict__ U,
+                                                       const double* __restrict__ prim,
+                                                       const double* __restrict__ fail,
+                                                       const double* __restrict__ scr,
+                                                       const double* __restrict__ wr,
+                                                       const double* __restrict__ wth, double G,
+                                                       PointParams pp, double* __restrict__ partials) {
+  __shared__ double sh[7][DIAG_THREADS];
+  const long long P = pp.P;
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+  for (long long idx = (long long)blockIdx.x * DIAG_THREADS + threadIdx.x; idx < P;
+       idx += (long long)gridDim.x * DIAG_THREADS) {
+    const int j = (int)(idx % pp.nr), k = (int)((idx / pp.nr) % pp.nth);
+    const double w = wr[j] * wth[k] * (2.0 * PI / pp.nph);
+    Sym gt;
+    for (int s = 0; s < 6; ++s) gt.m[s] = U[(size_t)(1 + s) * P + idx];
+    const double phi = U[idx];
+    const double sqrtg = exp(6.0 * phi) * sqrt(det_sym(gt));
+    const double rho = prim[idx], p = prim[(size_t)P + idx];
+    v[0] += U[(size_t)24 * P + idx] * w;
+    v[1] += rho * log(p / pow(rho, G)) / (G - 1.0) * sqrtg * w;
+    v[2] += fail[idx];
+    int nf = 0;
+    for (int f = 0; f < 32; ++f) nf += !isfinite(U[(size_t)f * P + idx]);
+    v[3] += nf;
+    const double dB = scr[(size_t)(SC_D1 + 0) * P + idx] + scr[(size_t)(SC_D1 + 21 + 1) * P + idx] +
+                      scr[(size_t)(SC_D1 + 42 + 2) * P + idx];
+    v[4] = fmax(v[4], fabs(dB));
+    v[5] = fmin(v[5], U[(size_t)17 * P + idx]);
+    const double e4 = exp(4.0 * phi);
+    Sym gam;
+    for (int s = 0; s < 6; ++s) gam.m[s] = e4 * gt.m[s];
+    double vv[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]}, vl[3];
+    mv(gam, vv, vl);
+    v[6] = fmax(v[6], 1.0 / sqrt(1.0 - dot3(vv, vl)));
+  }
+  for (int q = 0; q < 7; ++q) sh[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int half = DIAG_THREADS / 2; half > 0; half >>= 1) {
+    if ((int)threadIdx.x < half) {
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + half];
+      sh[4][threadIdx.x] = fmax(sh[4][threadIdx.x], sh[4][threadIdx.x + half]);
+      sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + half]);
+      sh[6][threadIdx.x] = fmax(sh[6][threadIdx.x], sh[6][threadIdx.x + half]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 7; ++q) partials[(size_t)blockIdx.x * 8 + q] = sh[q][0];
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long long P) { return (unsigned)((P + 255) / 256); }
+
+hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
+                           const double* rnode, const PointParams& pp, hipStream_t s) {
+  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P)), dim3(256), 0, s, U, prim, fail, flux, rnode, pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_rk(int mode, const double* Us, const double* scr, const double* prim,
+                         const double* K0, const double* Un, double* acc, double* out, double dt,
+                         const PointParams& pp, hipStream_t s) {
+  if (mode < 0 || mode > 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rhs_rk, dim3(nblk(pp.P)), dim3(256), 0, s, mode, Us, scr, prim, K0, Un, acc,
+                     out, dt, pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_k0(const double* U, const double* scr, double* K0, const PointParams& pp,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_k0, dim3(nblk(pp.P)), dim3(256), 0, s, U, scr, K0, pp.P);
+  return hipGetLastError();
+}
+
+int diag_partials_blocks(long long P) {
+  long long b = (P + DIAG_THREADS - 1) / DIAG_THREADS;
+  return (int)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_diag_partials(const double* U, const double* prim, const double* fail,
+                                const double* scr, const double* wr, const double* wth,
+                                double gamma_ad, const PointParams& pp, double* partials,
+                                int* nblocks, hipStream_t s) {
+  const int nb = diag_partials_blocks(pp.P);
+  *nblocks = nb;
+  hipLaunchKernelGGL(k_diag, dim3(nb), dim3(DIAG_THREADS), 0, s, U, prim, fail, scr, wr, wth, gamma_ad,
+                     pp, partials);
+  return hipGetLastError();
+}
+
+}  // namespace grmhd

@@ -1,0 +1,60 @@
+"""Synthetic workload definitions shared by tests, bench and smoke.
+
+Pure data and seeded input generators: no arithmetic of the method lives here.
+The grids, physics parameters and step counts are those of the five
+workloads the build is measured on (Kerr-Schild a = 0.5 Michel accretion with
+a monopole field at min plasma beta 100 on log-mapped Chebyshev(r) x
+Chebyshev(theta) x Fourier(phi) grids)."""
+
+import math
+
+import numpy as np
+
+COMMON_GRID = dict(r_in=1.8, r_out=20.0, th_min=0.05, th_max=math.pi - 0.05,
+                   filt_alpha=36.0, filt_order=16, filter_on=True)
+COMMON_PHYS = dict(M=1.0, a=0.5, gamma_ad=4.0 / 3.0, cfl=0.25, eta=2.0, cowling=False, gauge_k0=True,
+                   r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, rho_floor=1e-20, p_floor=1e-24)
+
+WORKLOADS = {
+    # tiny coupled evolution: 16^3, 10 RK4 steps
+    "ks_michel_16x16x16": dict(grid=dict(nr=16, nth=16, nph=16, **COMMON_GRID),
+                               phys=dict(seed=1, **COMMON_PHYS), steps=10),
+    # plain FP64 GPU baseline: 64 x 64 x 128, 100 RK4 steps
+    "ks_michel_64x64x128": dict(grid=dict(nr=64, nth=64, nph=128, **COMMON_GRID),
+                                phys=dict(seed=2, **COMMON_PHYS), steps=100),
+}
+
+
+def oracle_kwargs(w):
+    """Split a workload into (grid args, Problem kwargs, initial_state kwargs) for the oracle."""
+    g = w["grid"]
+    p = w["phys"]
+    grid_args = (g["nr"], g["nth"], g["nph"], g["r_in"], g["r_out"], g["th_min"], g["th_max"])
+    prob = dict(M=p["M"], a=p["a"], Gamma=p["gamma_ad"], eta=p["eta"], cowling=p["cowling"],
+                gauge_k0=p["gauge_k0"], rho_floor=p["rho_floor"], p_floor=p["p_floor"],
+                filt_alpha=g["filt_alpha"], filt_order=g["filt_order"], filter_on=g["filter_on"],
+                cfl=p["cfl"])
+    init = dict(r_c=p["r_c"], rho_c=p["rho_c"], beta_min=p["beta_min"], pert_amp=p["pert_amp"],
+                seed=p["seed"])
+    return grid_args, prob, init
+
+
+def random_fields(shape, nfields, seed):
+    """Seeded standard-normal test fields (float64), for operator tests."""
+    return np.random.default_rng(seed).standard_normal((nfields,) + tuple(shape))
+
+
+def smooth_fields(grid_r, grid_th, grid_ph, nfields, seed):
+    """Seeded smooth fields: random low-order products of 1/(r + c), cos/sin of
+    theta and low Fourier modes in phi."""
+    rng = np.random.default_rng(seed)
+    R = grid_r[None, None, :]
+    T = grid_th[None, :, None]
+    Ph = grid_ph[:, None, None]
+    out = []
+    for _ in range(nfields):
+        c = rng.uniform(0.5, 3.0)
+        a, b = rng.uniform(0.5, 2.0, 2)
+        m = rng.integers(0, 4)
+        out.append((1.0 / (R + c)) * np.cos(a * T + b) * (1.0 + 0.3 * np.cos(m * Ph + rng.uniform(0, 6))))
+    return np.array(out)
