@@ -82,6 +82,46 @@ def cpu_baseline(w):
                       f"dense BLAS solves on {blas} threads, einsum/FFT single-threaded"}
 
 
+def mixed_forms(w, K, fp64_rate, Solver, make_grid, make_phys, torch):
+    """Reduced-precision derivative contractions (FP32, split-BF16x3): the same
+    K steps from the same initial data; throughput, speedup over FP64, and the
+    errors against the FP64 path (itself equal to the oracle to 1e-11 per
+    field): density L2 relative (unweighted over the nodes) and the ratio of
+    Hamiltonian-constraint L2 norms."""
+    ref = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]), prec=0)
+    ref.init_state()
+    ref.step(K)
+    d_ref = ref.diagnostics()
+    shape = ref.shape
+    prim_ref = torch.empty((5,) + shape, dtype=torch.float64, device="cuda")
+    ref.con2prim(ref.U, prim_ref)
+    rho_ref = prim_ref[0].clone()
+    ref.close()
+    out = {}
+    g = w["grid"]
+    P = g["nr"] * g["nth"] * g["nph"]
+    for name, prec in (("fp32", 1), ("bf16x3", 2)):
+        s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]), prec=prec)
+        s.init_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = s.diagnostics()
+        prim = torch.empty_like(prim_ref)
+        s.con2prim(s.U, prim)
+        rho = prim[0]
+        l2 = float(torch.sqrt(torch.sum((rho - rho_ref) ** 2) / torch.sum(rho_ref ** 2)))
+        rate = P * 4 * K / wall
+        out[name] = {"value": rate, "speedup_vs_fp64": rate / fp64_rate, "ms_per_step": wall * 1e3 / K,
+                     "rho_l2_rel_vs_fp64": l2, "ham_l2": d["ham_l2"], "ham_l2_fp64": d_ref["ham_l2"],
+                     "ham_ratio": d["ham_l2"] / d_ref["ham_l2"], "c2p_fail": d["c2p_fail"],
+                     "nonfinite": d["nonfinite"]}
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +130,7 @@ def main():
     ap.add_argument("--workload", default="ks_michel_64x64x128")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -149,10 +190,12 @@ def main():
                    "rk_stages_per_step": 4, "precision": "fp64",
                    "physics": "Kerr-Schild a=0.5 + magnetised Michel accretion, BSSN+1+log+Gamma-driver"},
         "state_after": {"t": diag["t"], "c2p_fail": diag["c2p_fail"], "nonfinite": diag["nonfinite"],
-                        "rest_mass": diag["rest_mass"]},
+                        "rest_mass": diag["rest_mass"], "ham_l2": diag["ham_l2"]},
         "roofline": rl,
         "kernels": kernels,
     }
+    if not args.no_mixed:
+        out["mixed_precision"] = mixed_forms(w, K, out["value"], Solver, make_grid, make_phys, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

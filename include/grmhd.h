@@ -66,6 +66,11 @@ enum {
 
 #define GRMHD_NFIELDS 32
 
+/* Precision of the derivative contractions (the only part that changes):
+ * FP64; FP32 MFMA with FP32 accumulation; split-BF16 x3 MFMA with FP32
+ * accumulation.  In the reduced forms the derivative arrays are FP32; the
+ * metric reconstruction, con2prim, RHS algebra, constraint damping terms, the
+ * RK accumulator and the filter stay FP64. */
 typedef enum { GRMHD_FP64 = 0, GRMHD_MIX_FP32 = 1, GRMHD_MIX_BF16X3 = 2 } grmhd_prec;
 
 /* Grid (Methods, "Grid Discretization"; readings: log radial map, Chebyshev
@@ -106,6 +111,9 @@ typedef struct {
   double entropy;           /* E^n = sum rho s sqrt(gamma) w                 */
   double max_abs_divB;      /* max |d_i (sqrt(gamma) B^i)|                  */
   double min_alpha, max_W;
+  double ham_l2;            /* sqrt(sum H^2 w / sum w), Hamiltonian constraint
+                               H = R + 2/3 K^2 - A_ij A^ij - 16 pi E          */
+  double ham_linf;          /* max |H| over the nodes                        */
 } grmhd_diag;
 
 typedef struct grmhd_ctx grmhd_ctx;
@@ -152,7 +160,8 @@ int grmhd_rhs(grmhd_ctx* ctx, const double* dev_U, double* dev_dUdt);
  * when enabled.  Async. */
 int grmhd_step(grmhd_ctx* ctx, int32_t nsteps);
 
-/* Reductions over the current state.  Syncs. */
+/* Reductions over the current state (FP64 derivatives whatever the context's
+ * precision; uses the scratch buffer, so call it between steps).  Syncs. */
 int grmhd_diagnostics(grmhd_ctx* ctx, grmhd_diag* out);
 
 double grmhd_dt(const grmhd_ctx* ctx);

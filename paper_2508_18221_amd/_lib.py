@@ -35,7 +35,8 @@ class Diag(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("step", ctypes.c_int64), ("c2p_fail", ctypes.c_int64),
                 ("nonfinite", ctypes.c_int64), ("rest_mass", ctypes.c_double),
                 ("entropy", ctypes.c_double), ("max_abs_divB", ctypes.c_double),
-                ("min_alpha", ctypes.c_double), ("max_W", ctypes.c_double)]
+                ("min_alpha", ctypes.c_double), ("max_W", ctypes.c_double),
+                ("ham_l2", ctypes.c_double), ("ham_linf", ctypes.c_double)]
 
 
 _P = ctypes.POINTER

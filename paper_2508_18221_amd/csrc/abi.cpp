@@ -43,6 +43,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 struct Layout {
   size_t P;
   size_t res_fields, mats[3][3], rnode, wr, wth, partials, res_total;
+  size_t m32[3][2], mhi[3][2], mlo[3][2];  // reduced-precision operators (D1, D2)
   size_t scr_total;
 };
 
@@ -72,6 +73,17 @@ Layout layout(const grmhd_grid& g) {
       off += align256(np * np * sizeof(double));
     }
   }
+  for (int a = 0; a < 3; ++a) {
+    const size_t np = (size_t)round_up(n[a], 16), kp = (size_t)round_up(n[a], 32);
+    for (int o = 0; o < 2; ++o) {
+      L.m32[a][o] = off;
+      off += align256(np * np * sizeof(float));
+      L.mhi[a][o] = off;
+      off += align256(np * kp * 2);
+      L.mlo[a][o] = off;
+      off += align256(np * kp * 2);
+    }
+  }
   L.rnode = off;
   off += align256((size_t)g.nr * sizeof(double));
   L.wr = off;
@@ -79,7 +91,7 @@ Layout layout(const grmhd_grid& g) {
   L.wth = off;
   off += align256((size_t)g.nth * sizeof(double));
   L.partials = off;
-  off += align256((size_t)diag_partials_blocks((long long)L.P) * 8 * sizeof(double));
+  off += align256((size_t)diag_partials_blocks((long long)L.P) * DIAG_Q * sizeof(double));
   L.res_total = off;
   L.scr_total = align256((size_t)SC_NFIELDS * L.P * sizeof(double));
   return L;
@@ -99,6 +111,7 @@ struct grmhd_ctx {
   int device;
   double *U, *K0, *prim, *fail;
   const double* mats[3][3];
+  MixedOps mops[3][2];
   double *rnode, *wr, *wth, *partials;
   PointParams pp;
   double dt, t;
@@ -142,15 +155,57 @@ void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = 0) {
   t.dst1 = d1;
 }
 
-// Selectors: 0 = stage input state, 1 = scratch, 2 = resident
-int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, Recorder* rec = nullptr) {
+void addm(MixedTaskList& tl, int ssel, int src, int f32, int dsel, int d0, int d1 = 0) {
+  MixedTask& t = tl.t[tl.n++];
+  t.src_sel = ssel;
+  t.src = src;
+  t.src_f32 = f32;
+  t.dst_sel = dsel;
+  t.dst0 = d0;
+  t.dst1 = d1;
+}
+
+// Reduced-precision derivative passes: inputs FP64 (stage state, fluxes) or
+// FP32 (first derivatives for the mixed ones), FP32 outputs in the derivative
+// block of the scratch buffer (field g of the block at float offset g P).
+// Selectors: 0 = stage input state (FP64), 1 = FP32 derivative block,
+// 2 = scratch (FP64 fluxes).  Derivative indices are relative to SC_D1.
+int mixed_derivs(grmhd_ctx* c, const double* Uin, Recorder* rec) {
+  Bases B;
+  B.b[0] = const_cast<double*>(Uin);
+  B.b[1] = sf(c, SC_D1);
+  B.b[2] = c->scr;
+  B.b[3] = nullptr;
+  const int o2 = SC_D2 - SC_D1, omx = SC_MX - SC_D1, odf = SC_DF - SC_D1;
+  for (int a = 0; a < 3; ++a) {
+    MixedTaskList t2, t1;
+    t2.n = t1.n = 0;
+    for (int s = 0; s < ND2; ++s) addm(t2, 0, D2_FIELD[s], 0, 1, 21 * a + D2_FIELD[s], o2 + 11 * a + s);
+    for (int q = 0; q < 10; ++q) addm(t1, 0, D1_ONLY[q], 0, 1, 21 * a + D1_ONLY[q]);
+    if (a == 1)
+      for (int s = 0; s < ND2; ++s) addm(t1, 1, D2_FIELD[s], 1, 1, omx + s);
+    if (a == 2) {
+      for (int s = 0; s < ND2; ++s) addm(t1, 1, D2_FIELD[s], 1, 1, omx + 11 + s);
+      for (int s = 0; s < ND2; ++s) addm(t1, 1, 21 + D2_FIELD[s], 1, 1, omx + 22 + s);
+    }
+    for (int v = 0; v < 8; ++v) addm(t1, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
+    HIPCHK(launch_contract_mixed(c->prec, a, 2, t2, B, c->mops[a][0], c->mops[a][1], c->ops.n, c->ops.npad,
+                                 (long long)c->L.P, c->stream));
+    MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
+    HIPCHK(launch_contract_mixed(c->prec, a, 1, t1, B, c->mops[a][0], c->mops[a][0], c->ops.n, c->ops.npad,
+                                 (long long)c->L.P, c->stream));
+    MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
+  }
+  return GRMHD_OK;
+}
+
+// FP64 derivative passes (selectors: 0 = stage input state, 1 = scratch).
+int fp64_derivs(grmhd_ctx* c, const double* Uin, Recorder* rec) {
   Bases B;
   B.b[0] = const_cast<double*>(Uin);
   B.b[1] = c->scr;
   B.b[2] = (double*)c->res;
   B.b[3] = nullptr;
-  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, c->stream));
-  MARK(rec, GRMHD_K_C2P_FLUX);
   for (int a = 0; a < 3; ++a) {
     TaskList t2, t1;
     t2.n = t1.n = 0;
@@ -168,8 +223,17 @@ int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, Recorder* r
     HIPCHK(contract(c, a, 1, OP_D1, OP_D1, t1, B));
     MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
   }
-  HIPCHK(launch_rhs_rk(mode, Uin, c->scr, c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->dt, c->pp,
-                       c->stream));
+  return GRMHD_OK;
+}
+
+int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, Recorder* rec = nullptr) {
+  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, c->stream));
+  MARK(rec, GRMHD_K_C2P_FLUX);
+  const bool mixed = c->prec != GRMHD_FP64;
+  int rc = mixed ? mixed_derivs(c, Uin, rec) : fp64_derivs(c, Uin, rec);
+  if (rc) return rc;
+  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->dt,
+                       c->pp, c->stream));
   MARK(rec, GRMHD_K_RHS_RK);
   return GRMHD_OK;
 }
@@ -237,7 +301,8 @@ const char* grmhd_last_error(void) { return g_err.c_str(); }
 int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec, size_t* resident, size_t* scratch) {
   int rc = validate_grid(grid);
   if (rc) return rc;
-  if (prec != GRMHD_FP64) return fail(GRMHD_E_ARG, "only GRMHD_FP64 is implemented");
+  if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3)
+    return fail(GRMHD_E_ARG, "unknown precision");
   if (!resident || !scratch) return fail(GRMHD_E_ARG, "null output pointer");
   Layout L = layout(*grid);
   *resident = L.res_total;
@@ -250,7 +315,8 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   int rc = validate_grid(grid);
   if (rc) return rc;
   if (!phys || !out || !dev_resident || !dev_scratch) return fail(GRMHD_E_ARG, "null argument");
-  if (prec != GRMHD_FP64) return fail(GRMHD_E_ARG, "only GRMHD_FP64 is implemented");
+  if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3)
+    return fail(GRMHD_E_ARG, "unknown precision");
   if (((uintptr_t)dev_resident & 255) || ((uintptr_t)dev_scratch & 255))
     return fail(GRMHD_E_ARG, "device buffers must be 256-byte aligned");
   if (!(phys->gamma_ad > 1.0) || !(phys->cfl > 0.0) || !(phys->M >= 0.0) || !(fabs(phys->a) <= phys->M))
@@ -276,6 +342,12 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->fail = rf + (size_t)RS_FAIL * P;
   for (int a = 0; a < 3; ++a)
     for (int o = 0; o < 3; ++o) c->mats[a][o] = (const double*)(c->res + c->L.mats[a][o]);
+  for (int a = 0; a < 3; ++a)
+    for (int o = 0; o < 2; ++o) {
+      c->mops[a][o].f32 = (const float*)(c->res + c->L.m32[a][o]);
+      c->mops[a][o].bhi = (const __bf16*)(c->res + c->L.mhi[a][o]);
+      c->mops[a][o].blo = (const __bf16*)(c->res + c->L.mlo[a][o]);
+    }
   c->rnode = (double*)(c->res + c->L.rnode);
   c->wr = (double*)(c->res + c->L.wr);
   c->wth = (double*)(c->res + c->L.wth);
@@ -295,6 +367,18 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->step = 0;
   c->have_state = false;
   hipError_t e = set_kernel_attributes();
+  if (e == hipSuccess) e = set_mixed_kernel_attributes();
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    for (int o = 0; o < 2 && e == hipSuccess; ++o) {
+      e = hipMemcpyAsync((void*)c->mops[a][o].f32, c->ops.at32[a][o].data(), c->ops.at32[a][o].size() * 4,
+                         hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((void*)c->mops[a][o].bhi, c->ops.bhi[a][o].data(), c->ops.bhi[a][o].size() * 2,
+                           hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((void*)c->mops[a][o].blo, c->ops.blo[a][o].data(), c->ops.blo[a][o].size() * 2,
+                           hipMemcpyHostToDevice, c->stream);
+    }
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
     for (int o = 0; o < 3 && e == hipSuccess; ++o)
       e = hipMemcpyAsync((void*)c->mats[a][o], c->ops.at[a][o].data(), c->ops.at[a][o].size() * sizeof(double),
@@ -431,8 +515,14 @@ int grmhd_profile_step(grmhd_ctx* c, int32_t nsteps, double* ms, int32_t nkinds,
 int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
   if (!c || !out) return fail(GRMHD_E_ARG, "null argument");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state");
-  // con2prim of the current state, then d_i (sqrt(gamma) B^i) into free scratch slots
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->rnode, c->pp, c->stream));
+  // con2prim and FP64 derivatives of the current state -> Hamiltonian constraint
+  // (into the accumulator slot, free between steps); then d_i (sqrt(gamma) B^i)
+  // into free first-derivative slots
+  int rc = GRMHD_OK;
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, c->stream));
+  if ((rc = fp64_derivs(c, c->U, nullptr))) return rc;
+  double* H = sf(c, SC_ACC);
+  HIPCHK(launch_ham(c->U, sf(c, SC_D1), c->prim, H, c->pp, c->stream));
   Bases B;
   B.b[0] = c->U;
   B.b[1] = c->scr;
@@ -446,14 +536,14 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     if (e != hipSuccess) return fail(GRMHD_E_DEVICE, hipGetErrorString(e));
   }
   int nb = 0;
-  HIPCHK(launch_diag_partials(c->U, c->prim, c->fail, c->scr, c->wr, c->wth, c->phys.gamma_ad, c->pp,
+  HIPCHK(launch_diag_partials(c->U, c->prim, c->fail, c->scr, H, c->wr, c->wth, c->phys.gamma_ad, c->pp,
                               c->partials, &nb, c->stream));
-  std::vector<double> h((size_t)nb * 8);
+  std::vector<double> h((size_t)nb * DIAG_Q);
   HIPCHK(hipMemcpyAsync(h.data(), c->partials, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, mx4 = 0, mn5 = INFINITY, mx6 = 0;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, mx4 = 0, mn5 = INFINITY, mx6 = 0, s7 = 0, mx8 = 0, s9 = 0;
   for (int b = 0; b < nb; ++b) {
-    const double* q = &h[(size_t)b * 8];
+    const double* q = &h[(size_t)b * DIAG_Q];
     s0 += q[0];
     s1 += q[1];
     s2 += q[2];
@@ -461,7 +551,12 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     mx4 = fmax(mx4, q[4]);
     mn5 = fmin(mn5, q[5]);
     mx6 = fmax(mx6, q[6]);
+    s7 += q[7];
+    mx8 = fmax(mx8, q[8]);
+    s9 += q[9];
   }
+  out->ham_l2 = s9 > 0 ? sqrt(s7 / s9) : 0.0;
+  out->ham_linf = mx8;
   out->t = c->t;
   out->step = c->step;
   out->rest_mass = s0;

@@ -24,7 +24,9 @@ namespace grmhd {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int TILE_COLS = 64;
-constexpr int LDS_STRIDE = 80;  // doubles; 160 dwords = 32 banks offset per row
+constexpr int LDS_STRIDE = 72;  // doubles: rows 16 banks apart, so the 4 rows a
+                                // fragment read touches hit each bank twice
+constexpr int KC = 8;           // k-steps (of 4) of operator fragments held in registers
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -48,22 +50,47 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
   double* __restrict__ dst1 = B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + off;
 
   // ---- stage the input tile ------------------------------------------------
+  // LOADS independent global loads per thread are issued before any of them
+  // is written to LDS (memory-level parallelism for the HBM stream)
+  constexpr int LOADS = 16;
   if (INNER) {
     // 64 consecutive lines of N doubles: contiguous in memory; stored transposed
     const int ncols = min(TILE_COLS, inner - c0);  // lines in this tile
     const double* __restrict__ s = src + (size_t)c0 * N;
-    for (int e = threadIdx.x; e < TILE_COLS * N; e += 256) {
-      const int line = e / N, k = e - line * N;
-      tile[k * LDS_STRIDE + line] = (line < ncols) ? s[e] : 0.0;
+    const int total = TILE_COLS * N, valid = ncols * N;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double v[LOADS];
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        v[q] = (e < valid) ? s[e] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) {
+          const int line = e / N, k = e - line * N;
+          tile[k * LDS_STRIDE + line] = v[q];
+        }
+      }
     }
     for (int e = threadIdx.x; e < (Npad - N) * TILE_COLS; e += 256)
       tile[(N + e / TILE_COLS) * LDS_STRIDE + (e % TILE_COLS)] = 0.0;
   } else {
-    for (int e = threadIdx.x; e < Npad * TILE_COLS; e += 256) {
-      const int k = e >> 6, c = e & 63;
-      double v = 0.0;
-      if (k < N && c0 + c < inner) v = src[(size_t)k * inner + c0 + c];
-      tile[k * LDS_STRIDE + c] = v;
+    const int total = Npad * TILE_COLS;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double v[LOADS];
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        const int k = e >> 6, c = e & 63;
+        v[q] = (e < total && k < N && c0 + c < inner) ? src[(size_t)k * inner + c0 + c] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) tile[(e >> 6) * LDS_STRIDE + (e & 63)] = v[q];
+      }
     }
   }
   __syncthreads();
@@ -75,6 +102,7 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
   const int wi = wave % WI, wf = wave / WI;
   const int lr = lane & 15, lk = lane >> 4;
 
+  const int nks = Npad >> 2;  // k-steps
   for (int it = wi; it < T; it += WI) {
     d4 acc[NMAT][4];
 #pragma unroll
@@ -84,24 +112,47 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
     const double* __restrict__ a0p = AT0 + (size_t)lk * Npad + it * 16 + lr;
     const double* __restrict__ a1p = (NMAT > 1 ? AT1 : AT0) + (size_t)lk * Npad + it * 16 + lr;
     const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
-#pragma unroll 2
-    for (int k0 = 0; k0 < Npad; k0 += 4) {
-      const double a0 = a0p[(size_t)k0 * Npad];
-      const double a1 = (NMAT > 1) ? a1p[(size_t)k0 * Npad] : 0.0;
+    // operator fragments for KC k-steps live in registers; the next chunk is
+    // requested before the current one is consumed (one L2 latency per chunk)
+    double a[NMAT][KC], an[NMAT][KC];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        if (f < FW) {
-          const double b = tp[k0 * LDS_STRIDE + f * 16];
-          if (INNER) {
-            // D[line][i] = sum_k tile^T[line][k] AT[k][i]
-            acc[0][f] = mfma_f64(b, a0, acc[0][f]);
-            if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(b, a1, acc[NMAT - 1][f]);
-          } else {
-            // D[i][c] = sum_k A[i][k] tile[k][c]
-            acc[0][f] = mfma_f64(a0, b, acc[0][f]);
-            if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(a1, b, acc[NMAT - 1][f]);
+    for (int q = 0; q < KC; ++q) {
+      const bool ok = q < nks;
+      a[0][q] = ok ? a0p[(size_t)(4 * q) * Npad] : 0.0;
+      if (NMAT > 1) a[NMAT - 1][q] = ok ? a1p[(size_t)(4 * q) * Npad] : 0.0;
+    }
+    for (int kc = 0; kc < nks; kc += KC) {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        const bool ok = kc + KC + q < nks;
+        an[0][q] = ok ? a0p[(size_t)(4 * (kc + KC + q)) * Npad] : 0.0;
+        if (NMAT > 1) an[NMAT - 1][q] = ok ? a1p[(size_t)(4 * (kc + KC + q)) * Npad] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        if (kc + q < nks) {
+          const int k0 = 4 * (kc + q);
+#pragma unroll
+          for (int f = 0; f < 4; ++f) {
+            if (f < FW) {
+              const double b = tp[k0 * LDS_STRIDE + f * 16];
+              if (INNER) {
+                // D[line][i] = sum_k tile^T[line][k] AT[k][i]
+                acc[0][f] = mfma_f64(b, a[0][q], acc[0][f]);
+                if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(b, a[NMAT - 1][q], acc[NMAT - 1][f]);
+              } else {
+                // D[i][c] = sum_k A[i][k] tile[k][c]
+                acc[0][f] = mfma_f64(a[0][q], b, acc[0][f]);
+                if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(a[NMAT - 1][q], b, acc[NMAT - 1][f]);
+              }
+            }
           }
         }
+      }
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        a[0][q] = an[0][q];
+        if (NMAT > 1) a[NMAT - 1][q] = an[NMAT - 1][q];
       }
     }
     // ---- store ------------------------------------------------------------

@@ -1,0 +1,345 @@
+// Reduced-precision derivative contractions (the mixed-precision form):
+// the same dense line contractions as contract.hip, with FP32 outputs, in
+//   FP32   : v_mfma_f32_16x16x4f32, FP32 operands and accumulation;
+//   BF16x3 : v_mfma_f32_16x16x32_bf16 on split operands x = x_hi + x_lo
+//            (bf16 each), A x ~ A_hi x_hi + A_hi x_lo + A_lo x_hi, FP32
+//            accumulation.
+// Before the cast every grid line is shifted by its value at the middle node,
+// computed in FP64.  Derivative matrices annihilate constants (zero row sums),
+// so the shift changes nothing in exact arithmetic and the rounding error
+// scales with the variation along the line instead of its magnitude.  Inputs
+// are FP64 (state, fluxes) or FP32 (first derivatives feeding the mixed
+// second derivatives), chosen per task.
+//
+// Fragment layouts (measured on gfx950):
+//   f32 16x16x4   A: lane l holds A[l%16][l/16]; B: B[l/16][l%16];
+//                 D: lane l, reg v holds D[4(l/16) + v][l%16]
+//   bf16 16x16x32 A: lane l holds A[l%16][8(l/16) + q], q = 0..7 (any k order
+//                 shared by A and B gives the same sum); B: B[8(l/16) + q][l%16];
+//                 D as for f32.
+#include "grmhd_internal.h"
+
+namespace grmhd {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+constexpr int MT_COLS = 64;
+constexpr int F32_STRIDE = 80;   // floats per tile row: 4 rows cover 64 banks once
+constexpr int BF_PAD = 8;        // bf16 padding per tile row (rows 4 banks apart)
+
+__device__ __forceinline__ double load_in(const MixedTask& t, const Bases& B, long long P,
+                                          size_t off) {
+  if (t.src_f32) return (double)(((const float*)B.b[t.src_sel]) + (size_t)t.src * (size_t)P)[off];
+  return (B.b[t.src_sel] + (size_t)t.src * (size_t)P)[off];
+}
+
+// Element (k, c) of the tile of this workgroup, as an offset inside one field.
+// INNER: lines c0 + c of length N (r axis); otherwise rows k of `inner` points.
+template <bool INNER>
+__device__ __forceinline__ size_t elem(int k, int c, int c0, int N, int inner, size_t slab_off) {
+  return INNER ? (size_t)(c0 + c) * N + k : slab_off + (size_t)k * inner + c0 + c;
+}
+
+// ---------------------------------------------------------------------------
+template <int NMAT, bool INNER>
+__global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
+                                                      const float* __restrict__ AT0,
+                                                      const float* __restrict__ AT1, int N, int Npad,
+                                                      int inner, int slab, long long P) {
+  extern __shared__ float tf[];  // [Npad][F32_STRIDE] + 64 doubles of line offsets
+  double* shift = (double*)(tf + (size_t)Npad * F32_STRIDE);
+  const MixedTask tk = tl.t[blockIdx.z];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = blockIdx.x * MT_COLS;
+  const size_t soff = (size_t)blockIdx.y * (size_t)slab;
+  const int ncols = min(MT_COLS, inner - c0);
+  if (threadIdx.x < MT_COLS)
+    shift[threadIdx.x] =
+        threadIdx.x < ncols ? load_in(tk, B, P, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
+  __syncthreads();
+  constexpr int LOADS = 16;
+  const int total = Npad * MT_COLS;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+    double v[LOADS];
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = e0 + q * 256;
+      int k, c;
+      if (INNER) { c = e / Npad; k = e - c * Npad; } else { k = e >> 6; c = e & 63; }
+      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
+                                               : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = e0 + q * 256;
+      if (e < total) {
+        int k, c;
+        if (INNER) { c = e / Npad; k = e - c * Npad; } else { k = e >> 6; c = e & 63; }
+        tf[k * F32_STRIDE + c] = (float)v[q];
+      }
+    }
+  }
+  __syncthreads();
+  const int T = Npad >> 4;
+  const int WI = T >= 4 ? 4 : (T >= 2 ? 2 : 1);
+  const int FW = 4 / (4 / WI);
+  const int wi = wave % WI, wf = wave / WI;
+  const int lr = lane & 15, lk = lane >> 4;
+  float* dst0 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst0 * (size_t)P + soff;
+  float* dst1 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + soff;
+  for (int it = wi; it < T; it += WI) {
+    f4 acc[NMAT][4];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[m][f] = f4{0.f, 0.f, 0.f, 0.f};
+    const float* a0p = AT0 + (size_t)lk * Npad + it * 16 + lr;
+    const float* a1p = (NMAT > 1 ? AT1 : AT0) + (size_t)lk * Npad + it * 16 + lr;
+    const float* tp = tf + lk * F32_STRIDE + wf * FW * 16 + lr;
+#pragma unroll 4
+    for (int k0 = 0; k0 < Npad; k0 += 4) {
+      const float a0 = a0p[(size_t)k0 * Npad];
+      const float a1 = (NMAT > 1) ? a1p[(size_t)k0 * Npad] : 0.f;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if (f < FW) {
+          const float b = tp[k0 * F32_STRIDE + f * 16];
+          if (INNER) {
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a0, acc[0][f], 0, 0, 0);
+            if (NMAT > 1) acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a1, acc[NMAT - 1][f], 0, 0, 0);
+          } else {
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][f], 0, 0, 0);
+            if (NMAT > 1) acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[NMAT - 1][f], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if (f < FW) {
+        const int cf = (wf * FW + f) * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 4 * lk + v;
+          if (INNER) {
+            const int line = c0 + cf + row, i = it * 16 + lr;
+            if (line < inner && i < N) {
+              dst0[(size_t)line * N + i] = acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)line * N + i] = acc[NMAT - 1][f][v];
+            }
+          } else {
+            const int i = it * 16 + row, c = c0 + cf + lr;
+            if (i < N && c < inner) {
+              dst0[(size_t)i * inner + c] = acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)i * inner + c] = acc[NMAT - 1][f][v];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operators for BF16x3: row-major A[i][k] (i padded to 16, k padded to 32),
+// high and low parts in two arrays.  The tile is stored column-major
+// (tile[c][k], k contiguous) so each lane reads 8 consecutive k with one
+// 16-byte load, for both the r axis and the theta/phi axes.
+template <int NMAT, bool INNER>
+__global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
+                                                      const __bf16* __restrict__ A0h,
+                                                      const __bf16* __restrict__ A0l,
+                                                      const __bf16* __restrict__ A1h,
+                                                      const __bf16* __restrict__ A1l, int N, int Npad,
+                                                      int Kpad, int inner, int slab, long long P) {
+  extern __shared__ __bf16 tb[];  // hi [64][Kpad + BF_PAD], lo [64][Kpad + BF_PAD], 64 doubles
+  const int RS = Kpad + BF_PAD;
+  __bf16* thi = tb;
+  __bf16* tlo = tb + (size_t)MT_COLS * RS;
+  double* shift = (double*)(tb + (size_t)2 * MT_COLS * RS);
+  const MixedTask tk = tl.t[blockIdx.z];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = blockIdx.x * MT_COLS;
+  const size_t soff = (size_t)blockIdx.y * (size_t)slab;
+  const int ncols = min(MT_COLS, inner - c0);
+  if (threadIdx.x < MT_COLS)
+    shift[threadIdx.x] =
+        threadIdx.x < ncols ? load_in(tk, B, P, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
+  __syncthreads();
+  constexpr int LOADS = 16;
+  const int total = Kpad * MT_COLS;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+    double v[LOADS];
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = e0 + q * 256;
+      int k, c;
+      if (INNER) { c = e / Kpad; k = e - c * Kpad; } else { k = e >> 6; c = e & 63; }
+      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
+                                               : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < LOADS; ++q) {
+      const int e = e0 + q * 256;
+      if (e < total) {
+        int k, c;
+        if (INNER) { c = e / Kpad; k = e - c * Kpad; } else { k = e >> 6; c = e & 63; }
+        const float x = (float)v[q];
+        const __bf16 h = (__bf16)x;
+        thi[c * RS + k] = h;
+        tlo[c * RS + k] = (__bf16)(x - (float)h);
+      }
+    }
+  }
+  __syncthreads();
+  const int T = Npad >> 4;
+  const int WI = T >= 4 ? 4 : (T >= 2 ? 2 : 1);
+  const int FW = 4 / (4 / WI);
+  const int wi = wave % WI, wf = wave / WI;
+  const int lr = lane & 15, lk = lane >> 4;
+  float* dst0 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst0 * (size_t)P + soff;
+  float* dst1 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + soff;
+  for (int it = wi; it < T; it += WI) {
+    f4 acc[NMAT][4];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[m][f] = f4{0.f, 0.f, 0.f, 0.f};
+    const size_t arow = (size_t)(it * 16 + lr) * Kpad + 8 * lk;
+    for (int k0 = 0; k0 < Kpad; k0 += 32) {
+      const b8 ah0 = *(const b8*)(A0h + arow + k0);
+      const b8 al0 = *(const b8*)(A0l + arow + k0);
+      b8 ah1 = ah0, al1 = al0;
+      if (NMAT > 1) {
+        ah1 = *(const b8*)(A1h + arow + k0);
+        al1 = *(const b8*)(A1l + arow + k0);
+      }
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if (f < FW) {
+          const int col = (wf * FW + f) * 16 + lr;
+          const b8 bh = *(const b8*)(thi + col * RS + k0 + 8 * lk);
+          const b8 bl = *(const b8*)(tlo + col * RS + k0 + 8 * lk);
+          if (INNER) {
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, ah0, acc[0][f], 0, 0, 0);
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, ah0, acc[0][f], 0, 0, 0);
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, al0, acc[0][f], 0, 0, 0);
+            if (NMAT > 1) {
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, ah1, acc[NMAT - 1][f], 0, 0, 0);
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, ah1, acc[NMAT - 1][f], 0, 0, 0);
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, al1, acc[NMAT - 1][f], 0, 0, 0);
+            }
+          } else {
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh, acc[0][f], 0, 0, 0);
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl, acc[0][f], 0, 0, 0);
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh, acc[0][f], 0, 0, 0);
+            if (NMAT > 1) {
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh, acc[NMAT - 1][f], 0, 0, 0);
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl, acc[NMAT - 1][f], 0, 0, 0);
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh, acc[NMAT - 1][f], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if (f < FW) {
+        const int cf = (wf * FW + f) * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 4 * lk + v;
+          if (INNER) {
+            const int line = c0 + cf + row, i = it * 16 + lr;
+            if (line < inner && i < N) {
+              dst0[(size_t)line * N + i] = acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)line * N + i] = acc[NMAT - 1][f][v];
+            }
+          } else {
+            const int i = it * 16 + row, c = c0 + cf + lr;
+            if (i < N && c < inner) {
+              dst0[(size_t)i * inner + c] = acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)i * inner + c] = acc[NMAT - 1][f][v];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+static void geometry(int axis, const int n[3], int* inner, int* outer, int* slab) {
+  if (axis == 0) {
+    *inner = n[1] * n[2];
+    *outer = 1;
+    *slab = 0;
+  } else if (axis == 1) {
+    *inner = n[0];
+    *outer = n[2];
+    *slab = n[1] * n[0];
+  } else {
+    *inner = n[0] * n[1];
+    *outer = 1;
+    *slab = 0;
+  }
+}
+
+size_t mixed_lds_bytes(int prec, int npad) {
+  if (prec == GRMHD_MIX_FP32) return (size_t)npad * F32_STRIDE * sizeof(float) + MT_COLS * sizeof(double);
+  const int kpad = round_up(npad, 32);
+  return (size_t)2 * MT_COLS * (kpad + BF_PAD) * 2 + MT_COLS * sizeof(double);
+}
+
+hipError_t set_mixed_kernel_attributes() {
+  const int max_lds = 160 * 1024;
+  const void* ks[] = {(const void*)k_contract_f32<1, true>,  (const void*)k_contract_f32<2, true>,
+                      (const void*)k_contract_f32<1, false>, (const void*)k_contract_f32<2, false>,
+                      (const void*)k_contract_bf3<1, true>,  (const void*)k_contract_bf3<2, true>,
+                      (const void*)k_contract_bf3<1, false>, (const void*)k_contract_bf3<2, false>};
+  for (const void* k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskList& tl, const Bases& B,
+                                 const MixedOps& op0, const MixedOps& op1, const int n[3],
+                                 const int npad[3], long long P, hipStream_t s) {
+  if (tl.n <= 0) return hipSuccess;
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2) return hipErrorInvalidValue;
+  const int N = n[axis], Npad = npad[axis];
+  int inner, outer, slab;
+  geometry(axis, n, &inner, &outer, &slab);
+  dim3 grid((inner + MT_COLS - 1) / MT_COLS, outer, tl.n);
+  const size_t lds = mixed_lds_bytes(prec, Npad);
+  if (prec == GRMHD_MIX_FP32) {
+#define L32(NM, IN)                                                                                    \
+  hipLaunchKernelGGL((k_contract_f32<NM, IN>), grid, dim3(256), lds, s, tl, B, op0.f32, op1.f32, N, Npad, \
+                     inner, slab, P)
+    if (axis == 0) {
+      if (nmat == 1) L32(1, true); else L32(2, true);
+    } else {
+      if (nmat == 1) L32(1, false); else L32(2, false);
+    }
+#undef L32
+  } else if (prec == GRMHD_MIX_BF16X3) {
+    const int Kpad = round_up(Npad, 32);
+#define LBF(NM, IN)                                                                                     \
+  hipLaunchKernelGGL((k_contract_bf3<NM, IN>), grid, dim3(256), lds, s, tl, B, op0.bhi, op0.blo, op1.bhi, \
+                     op1.blo, N, Npad, Kpad, inner, slab, P)
+    if (axis == 0) {
+      if (nmat == 1) LBF(1, true); else LBF(2, true);
+    } else {
+      if (nmat == 1) LBF(1, false); else LBF(2, false);
+    }
+#undef LBF
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace grmhd

@@ -64,6 +64,24 @@ struct Bases {
   double* b[4];
 };
 
+// Reduced-precision contraction task: input may be FP64 or FP32, output FP32.
+struct MixedTask {
+  int src_sel, src, src_f32;
+  int dst_sel, dst0, dst1;
+};
+struct MixedTaskList {
+  int n;
+  MixedTask t[MAX_TASKS];
+};
+// One operator in the reduced-precision forms: FP32 transposed AT[k][i]
+// (padded like the FP64 one) and BF16 high/low parts of A[i][k], row-major,
+// i padded to 16 and k padded to 32.
+struct MixedOps {
+  const float* f32;
+  const __bf16* bhi;
+  const __bf16* blo;
+};
+
 struct PointParams {
   int nr, nth, nph;
   long long P;
@@ -80,6 +98,10 @@ struct Operators {
   std::vector<double> at[3][3];   // [axis][op]
   std::vector<double> r, th, ph;  // nodes
   std::vector<double> wr, wth;    // quadrature weights (d r, d theta)
+  // reduced-precision copies of the derivative operators (D1, D2 per axis)
+  std::vector<float> at32[3][2];
+  std::vector<uint16_t> bhi[3][2], blo[3][2];  // bf16 bit patterns, [npad][kpad]
+  int kpad[3];
   double Lc, Lh, Tc, Th;
   double dt;
 };
@@ -95,19 +117,30 @@ int host_initial_data(const grmhd_grid& g, const grmhd_phys& ph, const Operators
 hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
                            const double* AT0, const double* AT1, const int n[3],
                            const int npad[3], long long P, hipStream_t s);
+hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskList& tl, const Bases& B,
+                                 const MixedOps& op0, const MixedOps& op1, const int n[3],
+                                 const int npad[3], long long P, hipStream_t s);
+hipError_t set_mixed_kernel_attributes();
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
                            const double* rnode, const PointParams& pp, hipStream_t s);
-// mode 0: out = L(U_s); 1..4: classic RK4 stage s (see kernels.hip)
-hipError_t launch_rhs_rk(int mode, const double* Us, const double* scr, const double* prim,
+// mode 0: out = L(U_s); 1..4: classic RK4 stage s.  der: derivative arrays
+// (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
+hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Un, double* acc, double* out,
                          double dt, const PointParams& pp, hipStream_t s);
+// Hamiltonian constraint from FP64 derivative arrays into H (P doubles)
+hipError_t launch_ham(const double* U, const double* der, const double* prim, double* H,
+                      const PointParams& pp, hipStream_t s);
 hipError_t launch_k0(const double* U, const double* scr, double* K0, const PointParams& pp,
                      hipStream_t s);
 // Per-block partial reductions for diagnostics: writes nblocks x 8 doubles.
+// [0] rest mass, [1] entropy, [2] fails, [3] non-finite, [4] max|div B|,
+// [5] min alpha, [6] max W, [7] sum H^2 w, [8] max|H|, [9] sum w
+constexpr int DIAG_Q = 10;
 hipError_t launch_diag_partials(const double* U, const double* prim, const double* fail,
-                                const double* scr, const double* wr, const double* wth,
-                                double gamma_ad, const PointParams& pp, double* partials,
-                                int* nblocks, hipStream_t s);
+                                const double* scr, const double* H, const double* wr,
+                                const double* wth, double gamma_ad, const PointParams& pp,
+                                double* partials, int* nblocks, hipStream_t s);
 int diag_partials_blocks(long long P);
 hipError_t set_kernel_attributes();
 

@@ -15,6 +15,8 @@
 // zero-padded to a multiple of 16 for the MFMA contraction kernels.
 #include <math.h>
 
+#include <string.h>
+
 #include <algorithm>
 
 #include "grmhd_internal.h"
@@ -136,6 +138,38 @@ void store_transposed(const std::vector<ld>& A, int n, int npad, std::vector<dou
     for (int k = 0; k < n; ++k) (*out)[(size_t)k * npad + i] = (double)A[(size_t)i * n + k];
 }
 
+// bf16 (1 sign, 8 exponent, 7 mantissa bits) by round-to-nearest-even of a float
+uint16_t to_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double from_bf16(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return (double)x;
+}
+
+// Reduced-precision copies: FP32 transposed AT[k][i] and the BF16 split
+// A = hi + lo (hi = bf16(A), lo = bf16(A - hi)), row-major, k padded to kpad.
+void store_mixed(const std::vector<ld>& A, int n, int npad, int kpad, std::vector<float>* at32,
+                 std::vector<uint16_t>* bhi, std::vector<uint16_t>* blo) {
+  at32->assign((size_t)npad * npad, 0.0f);
+  bhi->assign((size_t)npad * kpad, 0);
+  blo->assign((size_t)npad * kpad, 0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double a = (double)A[(size_t)i * n + k];
+      (*at32)[(size_t)k * npad + i] = (float)a;
+      const uint16_t h = to_bf16((float)a);
+      (*bhi)[(size_t)i * kpad + k] = h;
+      (*blo)[(size_t)i * kpad + k] = to_bf16((float)(a - from_bf16(h)));
+    }
+}
+
 }  // namespace
 
 void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
@@ -143,6 +177,7 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
   for (int a = 0; a < 3; ++a) {
     ops->n[a] = n[a];
     ops->npad[a] = round_up(n[a], 16);
+    ops->kpad[a] = round_up(n[a], 32);
   }
   // nodes, computed in double exactly as x_j = cos(j pi/(N-1)), r = exp(Lc + Lh x)
   ops->Lc = 0.5 * (log(g.r_in) + log(g.r_out));
@@ -174,6 +209,8 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     }
     store_transposed(R1, nn, ops->npad[0], &ops->at[0][OP_D1]);
     store_transposed(R2, nn, ops->npad[0], &ops->at[0][OP_D2]);
+    store_mixed(R1, nn, ops->npad[0], ops->kpad[0], &ops->at32[0][0], &ops->bhi[0][0], &ops->blo[0][0]);
+    store_mixed(R2, nn, ops->npad[0], ops->kpad[0], &ops->at32[0][1], &ops->bhi[0][1], &ops->blo[0][1]);
     store_transposed(cheb_filter(nn, g.filt_alpha, g.filt_order), nn, ops->npad[0], &ops->at[0][OP_FILT]);
   }
   // polar: affine map
@@ -186,13 +223,18 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     for (auto& v : D2) v /= Th * Th;
     store_transposed(D1, nn, ops->npad[1], &ops->at[1][OP_D1]);
     store_transposed(D2, nn, ops->npad[1], &ops->at[1][OP_D2]);
+    store_mixed(D1, nn, ops->npad[1], ops->kpad[1], &ops->at32[1][0], &ops->bhi[1][0], &ops->blo[1][0]);
+    store_mixed(D2, nn, ops->npad[1], ops->kpad[1], &ops->at32[1][1], &ops->bhi[1][1], &ops->blo[1][1]);
     store_transposed(cheb_filter(nn, g.filt_alpha, g.filt_order), nn, ops->npad[1], &ops->at[1][OP_FILT]);
   }
   // azimuthal: Fourier
   {
     int nn = g.nph;
-    store_transposed(fourier_op(nn, 1, 0, 0), nn, ops->npad[2], &ops->at[2][OP_D1]);
-    store_transposed(fourier_op(nn, 2, 0, 0), nn, ops->npad[2], &ops->at[2][OP_D2]);
+    const std::vector<ld> F1 = fourier_op(nn, 1, 0, 0), F2 = fourier_op(nn, 2, 0, 0);
+    store_transposed(F1, nn, ops->npad[2], &ops->at[2][OP_D1]);
+    store_transposed(F2, nn, ops->npad[2], &ops->at[2][OP_D2]);
+    store_mixed(F1, nn, ops->npad[2], ops->kpad[2], &ops->at32[2][0], &ops->bhi[2][0], &ops->blo[2][0]);
+    store_mixed(F2, nn, ops->npad[2], ops->kpad[2], &ops->at32[2][1], &ops->bhi[2][1], &ops->blo[2][1]);
     store_transposed(fourier_op(nn, 3, g.filt_alpha, g.filt_order), nn, ops->npad[2], &ops->at[2][OP_FILT]);
   }
   // quadrature weights for dr and dtheta

@@ -173,6 +173,103 @@ __device__ __forceinline__ double rnode_floor(const double* rn, int j, double sc
   return scale * pow(rn[j], ex);
 }
 
+// Conformal Christoffels from dgt[a][s] = d_a gt_s:
+// Gl_ijk = (d_j gt_ik + d_k gt_ij - d_i gt_jk)/2, Gu^i_jk = gt^il Gl_ljk,
+// Gd^i = gt^jk Gu^i_jk.
+__device__ __forceinline__ void christoffel(const Sym& gtu, const double dgt[3][6], double Gl[3][6],
+                                            double Gu[3][6], double Gd[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = jj; kk < 3; ++kk)
+        Gl[i][S6(jj, kk)] = 0.5 * (dgt[jj][S6(i, kk)] + dgt[kk][S6(i, jj)] - dgt[i][S6(jj, kk)]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) Gu[i][s] = gtu(i, 0) * Gl[0][s] + gtu(i, 1) * Gl[1][s] + gtu(i, 2) * Gl[2][s];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) t += gtu(jj, kk) * Gu[i][S6(jj, kk)];
+    Gd[i] = t;
+  }
+}
+
+// Ricci tensor of the conformal decomposition, R_ij = Rt_ij + Rphi_ij:
+//   Rt_ij = -1/2 gt^lm d_l d_m gt_ij + gt_k(i d_j) Gt^k + Gd^k Gl_(ij)k
+//           + gt^lm (Gu^k_li Gl_jkm + Gu^k_lj Gl_ikm + Gu^k_im Gl_klj)
+//   Rphi_ij = -2 Dt_i Dt_j phi - 2 gt_ij Dt^l Dt_l phi + 4 d_i phi d_j phi
+//             - 4 gt_ij d^l phi d_l phi
+// DD(a, b, s): d_a d_b of second-derivative field s (phi 0, gt 1..6).
+template <typename Acc>
+__device__ __forceinline__ void ricci(const Sym& gt, const Sym& gtu, const double Gl[3][6],
+                                      const double Gu[3][6], const double Gd[3], const double dGt[3][3],
+                                      const double dphi[3], Acc DD, Sym& R) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) R.m[s] = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int m = l; m < 3; ++m) {
+      const double w = (l == m ? -0.5 : -1.0) * gtu(l, m);  // symmetric in l, m
+#pragma unroll
+      for (int s = 0; s < 6; ++s) R.m[s] += w * DD(l, m, 1 + s);
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = i; jj < 3; ++jj) {
+      double t = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) {
+        t += 0.5 * (gt(kk, i) * dGt[jj][kk] + gt(kk, jj) * dGt[i][kk]);
+        t += 0.5 * Gd[kk] * (Gl[i][S6(jj, kk)] + Gl[jj][S6(i, kk)]);
+      }
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          double q = 0.0;
+#pragma unroll
+          for (int kk = 0; kk < 3; ++kk)
+            q += Gu[kk][S6(l, i)] * Gl[jj][S6(kk, m)] + Gu[kk][S6(l, jj)] * Gl[i][S6(kk, m)] +
+                 Gu[kk][S6(i, m)] * Gl[kk][S6(l, jj)];
+          t += gtu(l, m) * q;
+        }
+      R.m[S6(i, jj)] += t;
+    }
+  double DDphi[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = i; jj < 3; ++jj)
+      DDphi[S6(i, jj)] = DD(i, jj, 0) - (Gu[0][S6(i, jj)] * dphi[0] + Gu[1][S6(i, jj)] * dphi[1] +
+                                         Gu[2][S6(i, jj)] * dphi[2]);
+  double lap = 0.0, grad2 = 0.0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      lap += gtu(l, m) * DDphi[S6(l, m)];
+      grad2 += gtu(l, m) * dphi[l] * dphi[m];
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = i; jj < 3; ++jj) {
+      const int s = S6(i, jj);
+      R.m[s] += -2.0 * DDphi[s] - 2.0 * gt.m[s] * lap + 4.0 * dphi[i] * dphi[jj] - 4.0 * gt.m[s] * grad2;
+    }
+}
+
+// derivative array offsets relative to the first-derivative block
+constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1;
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -248,10 +345,20 @@ __global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
 
 // ---------------------------------------------------------------------------
 // Second-derivative field index s: phi 0, gt 1..6, alpha 7, beta 8..10.
+//
+// The kernel finishes one group of right-hand sides at a time and applies the
+// RK4 stage update to it at once (phi, gt, gauge; Valencia; K and A-tilde;
+// Gamma-tilde and the driver), with compiler scheduling barriers between the
+// phases so that each phase's loads are issued where they are consumed and
+// the live register set stays small.
+//
 // Us, Un, acc and out may alias (in-place stages): no restrict on them; every
 // element is read and written by the same thread.
-__global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
-                                                const double* __restrict__ scr,
+#define PHASE() __asm__ __volatile__("" ::: "memory")
+
+template <typename DT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rhs_rk(int mode, const double* Us,
+                                                const DT* __restrict__ der,
                                                 const double* __restrict__ prim,
                                                 const double* __restrict__ K0p,
                                                 const double* Un, double* acc, double* out,
@@ -261,17 +368,39 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
   if (idx >= P) return;
   const int j = (int)(idx % pp.nr);
   const int k = (int)((idx / pp.nr) % pp.nth);
+  const bool frozen = (j == 0 || k == 0 || k == pp.nth - 1);
 #define LU(f) Us[(size_t)(f) * P + idx]
-#define LS(f) scr[(size_t)(f) * P + idx]
-#define D1(a, f) LS(SC_D1 + 21 * (a) + (f))
-  // second derivative d_a d_b of field s
+#define LS(g) ((double)der[(size_t)(g) * P + idx])
+#define D1(a, f) LS(21 * (a) + (f))
   auto DD = [&](int a, int b, int s) -> double {
-    if (a == b) return LS(SC_D2 + 11 * a + s);
+    if (a == b) return LS(O_D2 + 11 * a + s);
     const int lo = a < b ? a : b, hi = a < b ? b : a;
     const int m = (lo == 0) ? (hi == 1 ? 0 : 1) : 2;
-    return LS(SC_MX + 11 * m + s);
+    return LS(O_MX + 11 * m + s);
+  };
+  // classic RK4 stage update of field f with right-hand side kf
+  // mode 0: out = k; 1: acc = k/6, out = Un + dt/2 k; 2: acc += k/3, out = Un + dt/2 k;
+  // 3: acc += k/3, out = Un + dt k; 4: out = Un + dt (acc + k/6)
+  auto emit = [&](int f, double kf) {
+    if (frozen) kf = 0.0;
+    const size_t e = (size_t)f * P + idx;
+    if (mode == 0) {
+      out[e] = kf;
+    } else if (mode == 1) {
+      acc[e] = kf / 6.0;
+      out[e] = Un[e] + 0.5 * dt * kf;
+    } else if (mode == 2) {
+      acc[e] += kf / 3.0;
+      out[e] = Un[e] + 0.5 * dt * kf;
+    } else if (mode == 3) {
+      acc[e] += kf / 3.0;
+      out[e] = Un[e] + dt * kf;
+    } else {
+      out[e] = Un[e] + dt * (acc[e] + kf / 6.0);
+    }
   };
 
+  // ---- phase 1: conformal metric, gauge, first derivatives ---------------------
   const double phi = LU(0);
   Sym gt, At;
 #pragma unroll
@@ -280,135 +409,140 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
     At.m[s] = LU(7 + s);
   }
   const double K = LU(13);
-  const double Gt[3] = {LU(14), LU(15), LU(16)};
   const double alpha = LU(17);
   const double beta[3] = {LU(18), LU(19), LU(20)};
-  const double Bd[3] = {LU(21), LU(22), LU(23)};
-
+  const double K0 = K0p[idx];
   const double detgt = det_sym(gt);
   const Sym gtu = inv_sym(gt, detgt);
   const double e4 = exp(4.0 * phi), em4 = 1.0 / e4;
   const double sqrtg = e4 * exp(2.0 * phi) * sqrt(detgt);
-
-  double dphi[3], dal[3], dK[3];
+  double dphi[3], dal[3], dK[3], dbeta[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     dphi[a] = D1(a, 0);
     dal[a] = D1(a, 17);
     dK[a] = D1(a, 13);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dbeta[a][i] = D1(a, 18 + i);
   }
-  double dbeta[3][3];  // [a][i] = d_a beta^i
+  const double divb = dbeta[0][0] + dbeta[1][1] + dbeta[2][2];
+  PHASE();
+
+  // ---- phase 2: Christoffels; phi, gt_ij, alpha, beta right-hand sides ---------
+  double Gl[3][6], Gu[3][6], Gd[3];
+  double dgt[3][6];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) dbeta[a][i] = D1(a, 18 + i);
-  const double divb = dbeta[0][0] + dbeta[1][1] + dbeta[2][2];
-
-  // conformal Christoffels: Gl_ijk = (d_j gt_ik + d_k gt_ij - d_i gt_jk)/2 ; Gu^i_jk
-  double Gl[3][6], Gu[3][6];
-  double adv_gt[6];
-  {
-    double dgt[3][6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int s = 0; s < 6; ++s) dgt[a][s] = D1(a, 1 + s);
-#pragma unroll
-    for (int s = 0; s < 6; ++s) adv_gt[s] = beta[0] * dgt[0][s] + beta[1] * dgt[1][s] + beta[2] * dgt[2][s];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-        for (int kk = jj; kk < 3; ++kk)
-          Gl[i][S6(jj, kk)] = 0.5 * (dgt[jj][S6(i, kk)] + dgt[kk][S6(i, jj)] - dgt[i][S6(jj, kk)]);
-  }
+    for (int s = 0; s < 6; ++s) dgt[a][s] = D1(a, 1 + s);
+  christoffel(gtu, dgt, Gl, Gu, Gd);
+  emit(0, -alpha * K / 6.0 + dot3(beta, dphi) + divb / 6.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int s = 0; s < 6; ++s) Gu[i][s] = gtu(i, 0) * Gl[0][s] + gtu(i, 1) * Gl[1][s] + gtu(i, 2) * Gl[2][s];
-  double Gd[3];
+    for (int jj = i; jj < 3; ++jj) {
+      const int s = S6(i, jj);
+      double lie = 0.0;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) s += gtu(jj, kk) * Gu[i][S6(jj, kk)];
-    Gd[i] = s;
-  }
-
-  // ---- Ricci tensor R_ij = Rt_ij + Rphi_ij ----------------------------------
-  Sym R;
+      for (int kk = 0; kk < 3; ++kk) lie += gt(i, kk) * dbeta[jj][kk] + gt(jj, kk) * dbeta[i][kk];
+      const double adv = beta[0] * dgt[0][s] + beta[1] * dgt[1][s] + beta[2] * dgt[2][s];
+      emit(1 + s, -2.0 * alpha * At.m[s] + adv + lie - (2.0 / 3.0) * gt.m[s] * divb);
+    }
+  emit(17, dot3(beta, dal) - 2.0 * alpha * (pp.gauge_k0 ? (K - K0) : K));
   {
-    double dGt[3][3];  // [a][i] = d_a Gt^i
+    const double Bd[3] = {LU(21), LU(22), LU(23)};
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 3; ++i) emit(18 + i, 0.75 * Bd[i]);
+  }
+  PHASE();
+
+  // ---- phase 3: matter; Valencia right-hand sides ------------------------------
+  const double isg = 1.0 / sqrtg;
+  const double Em = (LU(28) + LU(24)) * isg;
+  const double Sl[3] = {LU(25) * isg, LU(26) * isg, LU(27) * isg};
+  Sym gam, gamu;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) dGt[a][i] = D1(a, 14 + i);
-    // -1/2 gt^{lm} d_l d_m gt_ij
-#pragma unroll
-    for (int s = 0; s < 6; ++s) R.m[s] = 0.0;
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const double w = -0.5 * gtu(l, m);
-#pragma unroll
-        for (int s = 0; s < 6; ++s) R.m[s] += w * DD(l, m, 1 + s);
-      }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = i; jj < 3; ++jj) {
-        double t = 0.0;
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-          // gt_k(i d_j) Gt^k
-          t += 0.5 * (gt(kk, i) * dGt[jj][kk] + gt(kk, jj) * dGt[i][kk]);
-          // Gd^k Gl_(ij)k
-          t += 0.5 * Gd[kk] * (Gl[i][S6(jj, kk)] + Gl[jj][S6(i, kk)]);
-        }
-        // gt^{lm} (Gu^k_li Gl_jkm + Gu^k_lj Gl_ikm + Gu^k_im Gl_klj)
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            double q = 0.0;
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk)
-              q += Gu[kk][S6(l, i)] * Gl[jj][S6(kk, m)] + Gu[kk][S6(l, jj)] * Gl[i][S6(kk, m)] +
-                   Gu[kk][S6(i, m)] * Gl[kk][S6(l, jj)];
-            t += gtu(l, m) * q;
-          }
-        R.m[S6(i, jj)] += t;
-      }
-    // conformal-factor part
-    double DDphi[6];
+  for (int s = 0; s < 6; ++s) {
+    gam.m[s] = e4 * gt.m[s];
+    gamu.m[s] = em4 * gtu.m[s];
+  }
+  Sym Sij;
+  {
+    const double rho = prim[idx], p = prim[(size_t)P + idx];
+    const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
+    const Mag m = magnetic(v, B, gam);
+    const double h = 1.0 + p / rho * pp.gamma_ad / (pp.gamma_ad - 1.0);
+    const double cw = (rho * h + m.b2) * m.W * m.W;
+    const double ps = p + 0.5 * m.b2;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int jj = i; jj < 3; ++jj)
-        DDphi[S6(i, jj)] = DD(i, jj, 0) - (Gu[0][S6(i, jj)] * dphi[0] + Gu[1][S6(i, jj)] * dphi[1] +
-                                           Gu[2][S6(i, jj)] * dphi[2]);
-    double lap = 0.0, grad2 = 0.0;
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        lap += gtu(l, m) * DDphi[S6(l, m)];
-        grad2 += gtu(l, m) * dphi[l] * dphi[m];
-      }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = i; jj < 3; ++jj) {
-        const int s = S6(i, jj);
-        R.m[s] += -2.0 * DDphi[s] - 2.0 * gt.m[s] * lap + 4.0 * dphi[i] * dphi[jj] - 4.0 * gt.m[s] * grad2;
-      }
+        Sij.m[S6(i, jj)] = cw * m.vl[i] * m.vl[jj] + ps * gam.m[S6(i, jj)] - m.bl[i] * m.bl[jj];
   }
+  double Str = 0.0;
+  {
+    double Sup[3][3];  // S^{kl} = gamma^{ki} gamma^{lj} S_ij
+    double t[3][3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+        t[kk][jj] = gamu(kk, 0) * Sij(0, jj) + gamu(kk, 1) * Sij(1, jj) + gamu(kk, 2) * Sij(2, jj);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) Sup[kk][l] = t[kk][0] * gamu(l, 0) + t[kk][1] * gamu(l, 1) + t[kk][2] * gamu(l, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Str += t[i][i];
+    // Sbar_{S_j} = -E d_j alpha + S_k d_j beta^k + (alpha/2) S^{kl} d_j gamma_kl,
+    // d_j gamma_kl = e^{4 phi} (d_j gt_kl + 4 gt_kl d_j phi)
+    double src[3];
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      double tt = -Em * dal[jj];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) tt += Sl[kk] * dbeta[jj][kk];
+      double q = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) q += Sup[kk][l] * e4 * (dgt[jj][S6(kk, l)] + 4.0 * gt(kk, l) * dphi[jj]);
+      src[jj] = tt + 0.5 * alpha * q;
+    }
+    // Sbar_tau = alpha S^{kl} K_kl - S^k d_k alpha, K_kl = e^{4 phi} (A_kl + gt_kl K/3)
+    double srcT = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) srcT += Sup[kk][l] * e4 * (At(kk, l) + gt(kk, l) * K / 3.0);
+    srcT *= alpha;
+    double Su[3];
+    mv(gamu, Sl, Su);
+    srcT -= dot3(Su, dal);
+    PHASE();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      double r = -(LS(O_DF + v) + LS(O_DF + 8 + v) + LS(O_DF + 16 + v));
+      if (v >= 1 && v <= 3) r += sqrtg * src[v - 1];
+      if (v == 4) r += sqrtg * srcT;
+      emit(24 + v, r);
+    }
+  }
+  PHASE();
 
-  // ---- D_i D_j alpha with the physical Christoffels --------------------------
+  // ---- phase 4: Ricci tensor R_ij = Rt_ij + Rphi_ij ---------------------------
+  Sym R;
+  double dGt[3][3];  // [a][i] = d_a Gt^i
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dGt[a][i] = D1(a, 14 + i);
+  ricci(gt, gtu, Gl, Gu, Gd, dGt, dphi, DD, R);
+  PHASE();
+
+  // ---- phase 5: D_i D_j alpha, A-tilde contractions, K and A-tilde -------------
   double DDa[6];
   {
     double dphiu[3];
@@ -434,14 +568,12 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
 #pragma unroll
     for (int m = 0; m < 3; ++m) trDDa += gtu(l, m) * DDa[S6(l, m)];
   trDDa *= em4;
-
-  // ---- A-tilde contractions ------------------------------------------------------
-  double Amix[3][3];  // A_ik gt^kl  (mixed A_i^l)
+  double Amix[3][3];  // A_ik gt^kl
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int l = 0; l < 3; ++l) Amix[i][l] = At(i, 0) * gtu(0, l) + At(i, 1) * gtu(1, l) + At(i, 2) * gtu(2, l);
-  Sym Atu;  // gt^ik gt^jl A_kl
+  Sym Atu;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -452,64 +584,7 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) AA += At(i, jj) * Atu(i, jj);
-
-  // ---- matter: E = tau + D, S_j, S_ij from the recovered primitives -------------
-  const double isg = 1.0 / sqrtg;
-  const double Em = (LU(28) + LU(24)) * isg;
-  const double Sl[3] = {LU(25) * isg, LU(26) * isg, LU(27) * isg};
-  Sym gam, gamu;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    gam.m[s] = e4 * gt.m[s];
-    gamu.m[s] = em4 * gtu.m[s];
-  }
-  Sym Sij;
-  {
-    const double rho = prim[idx], p = prim[(size_t)P + idx];
-    const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
-    const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
-    const Mag m = magnetic(v, B, gam);
-    const double h = 1.0 + p / rho * pp.gamma_ad / (pp.gamma_ad - 1.0);
-    const double cw = (rho * h + m.b2) * m.W * m.W;
-    const double ps = p + 0.5 * m.b2;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = i; jj < 3; ++jj)
-        Sij.m[S6(i, jj)] = cw * m.vl[i] * m.vl[jj] + ps * gam.m[S6(i, jj)] - m.bl[i] * m.bl[jj];
-  }
-  double Sup[3][3];  // S^{kl} = gamma^{ki} gamma^{lj} S_ij
-  {
-    double t[3][3];
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj) t[kk][jj] = gamu(kk, 0) * Sij(0, jj) + gamu(kk, 1) * Sij(1, jj) + gamu(kk, 2) * Sij(2, jj);
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int l = 0; l < 3; ++l) Sup[kk][l] = t[kk][0] * gamu(l, 0) + t[kk][1] * gamu(l, 1) + t[kk][2] * gamu(l, 2);
-  }
-  double Str = 0.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) Str += gamu(i, jj) * Sij(i, jj);
-
-  double rhs[32];
-  // ---- BSSN ------------------------------------------------------------------------
-  rhs[0] = -alpha * K / 6.0 + dot3(beta, dphi) + divb / 6.0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int jj = i; jj < 3; ++jj) {
-      const int s = S6(i, jj);
-      double lie = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) lie += gt(i, kk) * dbeta[jj][kk] + gt(jj, kk) * dbeta[i][kk];
-      rhs[1 + s] = -2.0 * alpha * At.m[s] + adv_gt[s] + lie - (2.0 / 3.0) * gt.m[s] * divb;
-    }
-  rhs[13] = -trDDa + alpha * (AA + K * K / 3.0) + 4.0 * PI * alpha * (Em + Str) + dot3(beta, dK);
+  emit(13, -trDDa + alpha * (AA + K * K / 3.0) + 4.0 * PI * alpha * (Em + Str) + dot3(beta, dK));
   {
     double X[6];
 #pragma unroll
@@ -524,17 +599,20 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
 #pragma unroll
       for (int jj = i; jj < 3; ++jj) {
         const int s = S6(i, jj);
-        double AAij = At(i, 0) * Amix[jj][0] + At(i, 1) * Amix[jj][1] + At(i, 2) * Amix[jj][2];
+        const double AAij = At(i, 0) * Amix[jj][0] + At(i, 1) * Amix[jj][1] + At(i, 2) * Amix[jj][2];
         double lie = 0.0, adv = 0.0;
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
           lie += At(i, kk) * dbeta[jj][kk] + At(jj, kk) * dbeta[i][kk];
           adv += beta[kk] * D1(kk, 7 + s);
         }
-        rhs[7 + s] = em4 * (X[s] - gt.m[s] * trX / 3.0) + alpha * (K * At.m[s] - 2.0 * AAij) + adv + lie -
-                     (2.0 / 3.0) * At.m[s] * divb;
+        emit(7 + s, em4 * (X[s] - gt.m[s] * trX / 3.0) + alpha * (K * At.m[s] - 2.0 * AAij) + adv + lie -
+                        (2.0 / 3.0) * At.m[s] * divb);
       }
   }
+  PHASE();
+
+  // ---- phase 6: Gamma-tilde and the Gamma-driver ---------------------------------
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double t = 0.0;
@@ -543,7 +621,7 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
       t += -2.0 * Atu(i, jj) * dal[jj];
       t += 2.0 * alpha * (6.0 * Atu(i, jj) * dphi[jj] - (2.0 / 3.0) * gtu(i, jj) * dK[jj]);
       t += -16.0 * PI * alpha * gtu(i, jj) * Sl[jj];
-      t += beta[jj] * D1(jj, 14 + i) - Gd[jj] * dbeta[jj][i];
+      t += beta[jj] * dGt[jj][i] - Gd[jj] * dbeta[jj][i];
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
         t += 2.0 * alpha * Gu[i][S6(jj, kk)] * Atu(jj, kk);
@@ -551,87 +629,73 @@ __global__ __launch_bounds__(256) void k_rhs_rk(int mode, const double* Us,
         t += gtu(i, jj) * DD(jj, kk, 8 + kk) / 3.0;
       }
     }
-    rhs[14 + i] = t + (2.0 / 3.0) * Gd[i] * divb;
-  }
-  const double K0 = K0p[idx];
-  rhs[17] = dot3(beta, dal) - 2.0 * alpha * (pp.gauge_k0 ? (K - K0) : K);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    rhs[18 + i] = 0.75 * Bd[i];
-    rhs[21 + i] = rhs[14 + i] - pp.eta * Bd[i];
-  }
-  if (pp.cowling) {
-#pragma unroll
-    for (int f = 0; f < 24; ++f) rhs[f] = 0.0;
-  }
-
-  // ---- Valencia: -d_a(alpha sqrt(gamma) F^a) + sqrt(gamma) Sbar -----------------
-  {
-    double src[3];
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      double t = -Em * dal[jj];
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) t += Sl[kk] * dbeta[jj][kk];
-      double q = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          const double dgam = e4 * (D1(jj, 1 + S6(kk, l)) + 4.0 * gt(kk, l) * dphi[jj]);
-          q += Sup[kk][l] * dgam;
-        }
-      src[jj] = t + 0.5 * alpha * q;
-    }
-    double srcT = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int l = 0; l < 3; ++l) srcT += Sup[kk][l] * e4 * (At(kk, l) + gt(kk, l) * K / 3.0);
-    srcT *= alpha;
-    double Su[3];
-    mv(gamu, Sl, Su);
-    srcT -= dot3(Su, dal);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const double div = LS(SC_DF + v) + LS(SC_DF + 8 + v) + LS(SC_DF + 16 + v);
-      rhs[24 + v] = -div;
-    }
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) rhs[25 + jj] += sqrtg * src[jj];
-    rhs[28] += sqrtg * srcT;
+    const double rGt = t + (2.0 / 3.0) * Gd[i] * divb;
+    emit(14 + i, rGt);
+    emit(21 + i, rGt - pp.eta * LU(21 + i));
   }
 #undef D1
 #undef LS
+#undef LU
+}
+#undef PHASE
 
-  // ---- boundary freeze: r_out nodes and theta end nodes ---------------------------
-  if (j == 0 || k == 0 || k == pp.nth - 1) {
+// ---------------------------------------------------------------------------
+// Hamiltonian constraint H = e^{-4 phi} gt^ij R_ij + 2/3 K^2 - A_ij A^ij - 16 pi E
+// with E = tau + D, from FP64 derivative arrays.
+__global__ __launch_bounds__(256) void k_ham(const double* __restrict__ U, const double* __restrict__ der,
+                                             double* __restrict__ H, PointParams pp) {
+  const long long P = pp.P;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P) return;
+#define LU(f) U[(size_t)(f) * P + idx]
+#define LS(g) der[(size_t)(g) * P + idx]
+  auto DD = [&](int a, int b, int s) -> double {
+    if (a == b) return LS(O_D2 + 11 * a + s);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int m = (lo == 0) ? (hi == 1 ? 0 : 1) : 2;
+    return LS(O_MX + 11 * m + s);
+  };
+  const double phi = LU(0);
+  Sym gt, At;
 #pragma unroll
-    for (int f = 0; f < 32; ++f) rhs[f] = 0.0;
+  for (int s = 0; s < 6; ++s) {
+    gt.m[s] = LU(1 + s);
+    At.m[s] = LU(7 + s);
   }
-
-  // ---- output / classic RK4 stage --------------------------------------------------
-  // mode 0: out = k; 1: acc = k/6, out = Un + dt/2 k; 2: acc += k/3, out = Un + dt/2 k;
-  // 3: acc += k/3, out = Un + dt k; 4: out = Un + dt (acc + k/6)
+  const double K = LU(13);
+  const double detgt = det_sym(gt);
+  const Sym gtu = inv_sym(gt, detgt);
+  const double em4 = exp(-4.0 * phi);
+  const double sqrtg = exp(6.0 * phi) * sqrt(detgt);
+  double dgt[3][6], dphi[3], dGt[3][3];
 #pragma unroll
-  for (int f = 0; f < 32; ++f) {
-    const size_t e = (size_t)f * P + idx;
-    const double kf = rhs[f];
-    if (mode == 0) {
-      out[e] = kf;
-    } else if (mode == 1) {
-      acc[e] = kf / 6.0;
-      out[e] = Un[e] + 0.5 * dt * kf;
-    } else if (mode == 2) {
-      acc[e] += kf / 3.0;
-      out[e] = Un[e] + 0.5 * dt * kf;
-    } else if (mode == 3) {
-      acc[e] += kf / 3.0;
-      out[e] = Un[e] + dt * kf;
-    } else {
-      out[e] = Un[e] + dt * (acc[e] + kf / 6.0);
+  for (int a = 0; a < 3; ++a) {
+    dphi[a] = LS(21 * a);
+#pragma unroll
+    for (int s2 = 0; s2 < 6; ++s2) dgt[a][s2] = LS(21 * a + 1 + s2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dGt[a][i] = LS(21 * a + 14 + i);
+  }
+  double Gl[3][6], Gu[3][6], Gd[3];
+  christoffel(gtu, dgt, Gl, Gu, Gd);
+  Sym R;
+  ricci(gt, gtu, Gl, Gu, Gd, dGt, dphi, DD, R);
+  double trR = 0.0, AA = 0.0;
+  double Amix[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) Amix[i][l] = At(i, 0) * gtu(0, l) + At(i, 1) * gtu(1, l) + At(i, 2) * gtu(2, l);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      trR += gtu(i, jj) * R(i, jj);
+      AA += Amix[i][jj] * Amix[jj][i];
     }
-  }
+  const double E = (LU(28) + LU(24)) / sqrtg;
+  H[idx] = em4 * trR + (2.0 / 3.0) * K * K - AA - 16.0 * PI * E;
+#undef LS
 #undef LU
 }
 
@@ -648,21 +712,24 @@ __global__ __launch_bounds__(256) void k_k0(const double* __restrict__ U, const 
 }
 
 // ---------------------------------------------------------------------------
-// Diagnostics partials per block (fixed-order tree; no floating-point atomics):
-// [0] sum sqrt(g) D w, [1] sum rho s sqrt(g) w, [2] fails, [3] non-finite count,
-// [4] max |div B| (from scratch d1 slots of sqrt(g)B), [5] min alpha, [6] max W
+// Diagnostics partials per block (fixed-order tree; no floating-point atomics),
+// DIAG_Q values per block: [0] sum sqrt(g) D w, [1] sum rho s sqrt(g) w,
+// [2] fails, [3] non-finite count, [4] max |div B| (scratch first-derivative
+// slots of sqrt(g) B^a), [5] min alpha, [6] max W, [7] sum H^2 w, [8] max |H|,
+// [9] sum w.
 constexpr int DIAG_THREADS = 256;
 
 __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict__ U,
                                                        const double* __restrict__ prim,
                                                        const double* __restrict__ fail,
                                                        const double* __restrict__ scr,
+                                                       const double* __restrict__ H,
                                                        const double* __restrict__ wr,
                                                        const double* __restrict__ wth, double G,
                                                        PointParams pp, double* __restrict__ partials) {
-  __shared__ double sh[7][DIAG_THREADS];
+  __shared__ double sh[DIAG_Q][DIAG_THREADS];
   const long long P = pp.P;
-  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0};
+  double v[DIAG_Q] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0};
   for (long long idx = (long long)blockIdx.x * DIAG_THREADS + threadIdx.x; idx < P;
        idx += (long long)gridDim.x * DIAG_THREADS) {
     const int j = (int)(idx % pp.nr), k = (int)((idx / pp.nr) % pp.nth);
@@ -688,8 +755,12 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
     double vv[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]}, vl[3];
     mv(gam, vv, vl);
     v[6] = fmax(v[6], 1.0 / sqrt(1.0 - dot3(vv, vl)));
+    const double h = H[idx];
+    v[7] += h * h * w;
+    v[8] = fmax(v[8], fabs(h));
+    v[9] += w;
   }
-  for (int q = 0; q < 7; ++q) sh[q][threadIdx.x] = v[q];
+  for (int q = 0; q < DIAG_Q; ++q) sh[q][threadIdx.x] = v[q];
   __syncthreads();
   for (int half = DIAG_THREADS / 2; half > 0; half >>= 1) {
     if ((int)threadIdx.x < half) {
@@ -697,11 +768,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
       sh[4][threadIdx.x] = fmax(sh[4][threadIdx.x], sh[4][threadIdx.x + half]);
       sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + half]);
       sh[6][threadIdx.x] = fmax(sh[6][threadIdx.x], sh[6][threadIdx.x + half]);
+      sh[7][threadIdx.x] += sh[7][threadIdx.x + half];
+      sh[8][threadIdx.x] = fmax(sh[8][threadIdx.x], sh[8][threadIdx.x + half]);
+      sh[9][threadIdx.x] += sh[9][threadIdx.x + half];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int q = 0; q < 7; ++q) partials[(size_t)blockIdx.x * 8 + q] = sh[q][0];
+    for (int q = 0; q < DIAG_Q; ++q) partials[(size_t)blockIdx.x * DIAG_Q + q] = sh[q][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -713,12 +787,23 @@ hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_rk(int mode, const double* Us, const double* scr, const double* prim,
+hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Un, double* acc, double* out, double dt,
                          const PointParams& pp, hipStream_t s) {
   if (mode < 0 || mode > 4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rhs_rk, dim3(nblk(pp.P)), dim3(256), 0, s, mode, Us, scr, prim, K0, Un, acc,
-                     out, dt, pp);
+  if (der_f32)
+    hipLaunchKernelGGL(k_rhs_rk<float>, dim3(nblk(pp.P)), dim3(256), 0, s, mode, Us, (const float*)der, prim,
+                       K0, Un, acc, out, dt, pp);
+  else
+    hipLaunchKernelGGL(k_rhs_rk<double>, dim3(nblk(pp.P)), dim3(256), 0, s, mode, Us, (const double*)der,
+                       prim, K0, Un, acc, out, dt, pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_ham(const double* U, const double* der, const double* prim, double* H,
+                      const PointParams& pp, hipStream_t s) {
+  (void)prim;
+  hipLaunchKernelGGL(k_ham, dim3(nblk(pp.P)), dim3(256), 0, s, U, der, H, pp);
   return hipGetLastError();
 }
 
@@ -734,12 +819,12 @@ int diag_partials_blocks(long long P) {
 }
 
 hipError_t launch_diag_partials(const double* U, const double* prim, const double* fail,
-                                const double* scr, const double* wr, const double* wth,
-                                double gamma_ad, const PointParams& pp, double* partials,
-                                int* nblocks, hipStream_t s) {
+                                const double* scr, const double* H, const double* wr, const double* wth,
+                                double gamma_ad, const PointParams& pp, double* partials, int* nblocks,
+                                hipStream_t s) {
   const int nb = diag_partials_blocks(pp.P);
   *nblocks = nb;
-  hipLaunchKernelGGL(k_diag, dim3(nb), dim3(DIAG_THREADS), 0, s, U, prim, fail, scr, wr, wth, gamma_ad,
+  hipLaunchKernelGGL(k_diag, dim3(nb), dim3(DIAG_THREADS), 0, s, U, prim, fail, scr, H, wr, wth, gamma_ad,
                      pp, partials);
   return hipGetLastError();
 }
