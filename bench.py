@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-t-scale", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -196,6 +198,15 @@ def main():
     }
     if not args.no_mixed:
         out["mixed_precision"] = mixed_forms(w, K, out["value"], Solver, make_grid, make_phys, torch)
+    if not args.no_serving:
+        from paper_2508_18221_amd.serve import run_stream
+        jobs = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale)
+        out["serving"] = {"stream": "256 jobs, Poisson arrivals 4/s, a~U[0,0.95], beta~logU[10,1000], "
+                                    "grids {16^3, 32x32x64, 48x48x96, 64x64x128}, Michel+field, "
+                                    f"T~U[10,100] M scaled by {args.serve_t_scale:g}, HBM budget 200 GB",
+                          "t_scale": args.serve_t_scale}
+        for name, prec in (("fp64", 0), ("fp32", 1)):
+            out["serving"][name] = run_stream(jobs, prec=prec, budget=200e9)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

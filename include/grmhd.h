@@ -160,6 +160,24 @@ int grmhd_rhs(grmhd_ctx* ctx, const double* dev_U, double* dev_dUdt);
  * when enabled.  Async. */
 int grmhd_step(grmhd_ctx* ctx, int32_t nsteps);
 
+/* nsteps RK4 steps (+ filter) of n contexts of one grid class, each kernel
+ * launched once for all of them (continuous batching; up to 32 jobs per
+ * launch, larger n is split).  The contexts must share grid sizes, precision,
+ * the kernel parameters (Gamma, eta, cowling, gauge_k0, floors), the stream
+ * and the offset between their scratch and resident buffers; r_in, the spin,
+ * the initial data and dt may differ.  Each job's arithmetic is the same
+ * as when stepped alone (bitwise).  Async. */
+int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps);
+
+/* Override the time step (e.g. dt = T / ceil(T / dt) to land on an end time). */
+int grmhd_set_dt(grmhd_ctx* ctx, double dt);
+
+/* Move the context to another stream (waits for the old one). */
+int grmhd_set_stream(grmhd_ctx* ctx, void* hip_stream);
+
+/* Host only: the CFL time step of a grid without creating a context. */
+int grmhd_time_step(const grmhd_grid* grid, double cfl, double* dt);
+
 /* Reductions over the current state (FP64 derivatives whatever the context's
  * precision; uses the scratch buffer, so call it between steps).  Syncs. */
 int grmhd_diagnostics(grmhd_ctx* ctx, grmhd_diag* out);
@@ -184,6 +202,60 @@ int grmhd_apply_operator(grmhd_ctx* ctx, int32_t axis, int32_t op,
  * 24..31).  Async. */
 int grmhd_con2prim(grmhd_ctx* ctx, const double* dev_U, double* dev_prim,
                    double* dev_flux);
+
+/* ---- served form: continuous-batching job server ------------------------- */
+
+typedef struct grmhd_server grmhd_server;
+
+typedef struct {
+  int64_t id;
+  int32_t state;            /* 0 queued, 1 running, 2 done, 3 rejected       */
+  int32_t nr, nth, nph, prec;
+  int64_t steps_done, steps_total;
+  double dt;                /* T / steps_total                               */
+  double t_arrival, t_admit, t_done;  /* server clock, seconds               */
+  double latency;           /* t_done - t_arrival (done jobs), else -1       */
+  size_t bytes;             /* device footprint (resident + scratch)         */
+} grmhd_job_info;
+
+typedef struct {
+  int64_t submitted, completed, rejected, running, queued;
+  double p50_latency, p99_latency, mean_latency;  /* completed jobs, seconds  */
+  double point_stage_updates;  /* completed work: sum over jobs of 4 P steps */
+  double wall;              /* first submission to last completion, seconds  */
+  double busy;              /* seconds spent inside ticks                    */
+  size_t bytes_in_use, bytes_peak;
+} grmhd_server_summary;
+
+/* A server that places jobs in the caller's device arena (dev_arena,
+ * arena_bytes = the memory budget; 256-byte aligned) and steps jobs of one
+ * grid class together, at most max_batch per launch sequence.  Each grid
+ * class runs on a stream of its own (default priority); hip_stream is the
+ * fallback.  dev_arena NULL: dry run, no device work (each job step completes
+ * at once), for exercising the scheduling logic without a GPU. */
+int grmhd_server_create(void* dev_arena, size_t arena_bytes, int32_t max_batch, void* hip_stream,
+                        grmhd_server** out);
+int grmhd_server_destroy(grmhd_server* srv);
+
+/* Queue a job that evolves (grid, phys) from its initial data to t_end; the
+ * arrival time is the server clock now.  keep_state: copy the final state to
+ * host memory at completion (grmhd_server_result).  A job larger than the
+ * whole budget is rejected (GRMHD_E_BUDGET). */
+int grmhd_server_submit(grmhd_server* srv, const grmhd_grid* grid, const grmhd_phys* phys,
+                        grmhd_prec prec, double t_end, int32_t keep_state, int64_t* job_id);
+
+/* Admit queued jobs in arrival order while they fit, advance every running
+ * job by one RK4 step (one batched launch sequence per grid class), retire
+ * finished jobs and free their memory.  n_pending: queued + running after the
+ * tick.  Syncs. */
+int grmhd_server_tick(grmhd_server* srv, int32_t* n_pending);
+
+int grmhd_server_poll(grmhd_server* srv, int64_t job_id, grmhd_job_info* out);
+/* Final state of a finished job submitted with keep_state (n = 32 P). */
+int grmhd_server_result(grmhd_server* srv, int64_t job_id, double* host_U, size_t n);
+int grmhd_server_stats(grmhd_server* srv, grmhd_server_summary* out);
+double grmhd_server_clock(const grmhd_server* srv);
+const char* grmhd_server_last_error(void);
 
 /* ---- timing ---------------------------------------------------------------- */
 

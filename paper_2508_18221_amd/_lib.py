@@ -39,6 +39,22 @@ class Diag(ctypes.Structure):
                 ("ham_l2", ctypes.c_double), ("ham_linf", ctypes.c_double)]
 
 
+class JobInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("state", ctypes.c_int32), ("nr", ctypes.c_int32),
+                ("nth", ctypes.c_int32), ("nph", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("steps_done", ctypes.c_int64), ("steps_total", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("latency", ctypes.c_double), ("bytes", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("queued", ctypes.c_int64), ("p50_latency", ctypes.c_double),
+                ("p99_latency", ctypes.c_double), ("mean_latency", ctypes.c_double),
+                ("point_stage_updates", ctypes.c_double), ("wall", ctypes.c_double), ("busy", ctypes.c_double),
+                ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t)]
+
+
 _P = ctypes.POINTER
 _dp = _P(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -61,6 +77,20 @@ SIGNATURES = {
     "grmhd_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_int32]),
     "grmhd_con2prim": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "grmhd_profile_step": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.c_int32, _P(ctypes.c_int32)]),
+    "grmhd_step_batch": (ctypes.c_int, [_P(_vp), ctypes.c_int32, ctypes.c_int32]),
+    "grmhd_set_dt": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "grmhd_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "grmhd_time_step": (ctypes.c_int, [_P(Grid), ctypes.c_double, _dp]),
+    "grmhd_server_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int32, _vp, _P(_vp)]),
+    "grmhd_server_destroy": (ctypes.c_int, [_vp]),
+    "grmhd_server_submit": (ctypes.c_int, [_vp, _P(Grid), _P(Phys), ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_int32, _P(ctypes.c_int64)]),
+    "grmhd_server_tick": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
+    "grmhd_server_poll": (ctypes.c_int, [_vp, ctypes.c_int64, _P(JobInfo)]),
+    "grmhd_server_result": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, ctypes.c_size_t]),
+    "grmhd_server_stats": (ctypes.c_int, [_vp, _P(ServerStats)]),
+    "grmhd_server_clock": (ctypes.c_double, [_vp]),
+    "grmhd_server_last_error": (ctypes.c_char_p, []),
 }
 
 KERNEL_KINDS = ["c2p_flux", "deriv_r2", "deriv_r1", "deriv_t2", "deriv_t1", "deriv_p2", "deriv_p1",
@@ -76,6 +106,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_18221_amd.build`")
+    # PyTorch wheels ship their own HIP runtime.  Device memory and streams
+    # handed to the library come from that runtime, so the library must bind
+    # to the same copy: load torch first, and the dynamic loader resolves
+    # libamdhip64.so.7 to the already-loaded runtime instead of a second one.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -93,4 +128,11 @@ def check(rc):
     if rc != 0:
         msg = load().grmhd_last_error().decode(errors="replace")
         raise GrmhdError(f"grmhd error {rc}: {msg}")
+    return rc
+
+
+def check_server(rc):
+    if rc != 0:
+        msg = load().grmhd_server_last_error().decode(errors="replace")
+        raise GrmhdError(f"grmhd server error {rc}: {msg}")
     return rc

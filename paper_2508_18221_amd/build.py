@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgrmhd.so")
-SOURCES = ["contract.hip", "contract_mixed.hip", "pointwise.hip", "operators.cpp", "init_data.cpp", "abi.cpp"]
+SOURCES = ["contract.hip", "contract_mixed.hip", "pointwise.hip", "operators.cpp", "init_data.cpp", "abi.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -123,6 +123,14 @@ namespace {
 
 double* sf(grmhd_ctx* c, int f) { return c->scr + (size_t)f * c->L.P; }
 
+JobSet single(const grmhd_ctx* c) {
+  JobSet js;
+  js.n = 1;
+  js.d[0] = 0;
+  js.dt[0] = c->dt;
+  return js;
+}
+
 // Optional event recorder: an event after every launch, tagged with its kind.
 struct Recorder {
   std::vector<hipEvent_t> ev;
@@ -141,9 +149,9 @@ struct Recorder {
   } while (0)
 
 hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const TaskList& tl,
-                    const Bases& B) {
+                    const Bases& B, const JobSet& js) {
   return launch_contract(axis, nmat, tl, B, c->mats[axis][op0], c->mats[axis][op1], c->ops.n,
-                         c->ops.npad, (long long)c->L.P, c->stream);
+                         c->ops.npad, (long long)c->L.P, js, c->stream);
 }
 
 void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = 0) {
@@ -170,7 +178,7 @@ void addm(MixedTaskList& tl, int ssel, int src, int f32, int dsel, int d0, int d
 // block of the scratch buffer (field g of the block at float offset g P).
 // Selectors: 0 = stage input state (FP64), 1 = FP32 derivative block,
 // 2 = scratch (FP64 fluxes).  Derivative indices are relative to SC_D1.
-int mixed_derivs(grmhd_ctx* c, const double* Uin, Recorder* rec) {
+int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
   Bases B;
   B.b[0] = const_cast<double*>(Uin);
   B.b[1] = sf(c, SC_D1);
@@ -190,17 +198,17 @@ int mixed_derivs(grmhd_ctx* c, const double* Uin, Recorder* rec) {
     }
     for (int v = 0; v < 8; ++v) addm(t1, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
     HIPCHK(launch_contract_mixed(c->prec, a, 2, t2, B, c->mops[a][0], c->mops[a][1], c->ops.n, c->ops.npad,
-                                 (long long)c->L.P, c->stream));
+                                 (long long)c->L.P, js, c->stream));
     MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
     HIPCHK(launch_contract_mixed(c->prec, a, 1, t1, B, c->mops[a][0], c->mops[a][0], c->ops.n, c->ops.npad,
-                                 (long long)c->L.P, c->stream));
+                                 (long long)c->L.P, js, c->stream));
     MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
   }
   return GRMHD_OK;
 }
 
 // FP64 derivative passes (selectors: 0 = stage input state, 1 = scratch).
-int fp64_derivs(grmhd_ctx* c, const double* Uin, Recorder* rec) {
+int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
   Bases B;
   B.b[0] = const_cast<double*>(Uin);
   B.b[1] = c->scr;
@@ -218,27 +226,30 @@ int fp64_derivs(grmhd_ctx* c, const double* Uin, Recorder* rec) {
       for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + 21 + D2_FIELD[s], 1, SC_MX + 22 + s);
     }
     for (int v = 0; v < 8; ++v) add(t1, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
-    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, t2, B));
+    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, t2, B, js));
     MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
-    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, t1, B));
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, t1, B, js));
     MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
   }
   return GRMHD_OK;
 }
 
-int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, Recorder* rec = nullptr) {
-  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, c->stream));
+// One RHS evaluation (+ RK stage update for mode >= 1) of the jobs in js,
+// addressed through context c (the first job).
+int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSet& js,
+             Recorder* rec = nullptr) {
+  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, js, c->stream));
   MARK(rec, GRMHD_K_C2P_FLUX);
   const bool mixed = c->prec != GRMHD_FP64;
-  int rc = mixed ? mixed_derivs(c, Uin, rec) : fp64_derivs(c, Uin, rec);
+  int rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
   if (rc) return rc;
-  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->dt,
-                       c->pp, c->stream));
+  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->pp,
+                       js, c->stream));
   MARK(rec, GRMHD_K_RHS_RK);
   return GRMHD_OK;
 }
 
-int filter_state(grmhd_ctx* c, Recorder* rec = nullptr) {
+int filter_state(grmhd_ctx* c, const JobSet& js, Recorder* rec = nullptr) {
   Bases B;
   B.b[0] = c->U;
   B.b[1] = c->scr;
@@ -251,20 +262,27 @@ int filter_state(grmhd_ctx* c, Recorder* rec = nullptr) {
     TaskList tl;
     tl.n = 0;
     for (int f = 0; f < NF; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
-    HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B));
+    HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B, js));
     MARK(rec, GRMHD_K_FILTER_R + a);
   }
   return GRMHD_OK;
 }
 
-int one_step(grmhd_ctx* c, Recorder* rec) {
+// One classic RK4 step (+ filter) of the jobs in js, addressed through c.
+int rk4_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   double* Us = sf(c, SC_US);
   int rc;
-  if ((rc = rhs_eval(c, c->U, 1, Us, rec))) return rc;
-  if ((rc = rhs_eval(c, Us, 2, Us, rec))) return rc;
-  if ((rc = rhs_eval(c, Us, 3, Us, rec))) return rc;
-  if ((rc = rhs_eval(c, Us, 4, c->U, rec))) return rc;
-  if (c->grid.filter_on && (rc = filter_state(c, rec))) return rc;
+  if ((rc = rhs_eval(c, c->U, 1, Us, js, rec))) return rc;
+  if ((rc = rhs_eval(c, Us, 2, Us, js, rec))) return rc;
+  if ((rc = rhs_eval(c, Us, 3, Us, js, rec))) return rc;
+  if ((rc = rhs_eval(c, Us, 4, c->U, js, rec))) return rc;
+  if (c->grid.filter_on && (rc = filter_state(c, js, rec))) return rc;
+  return GRMHD_OK;
+}
+
+int one_step(grmhd_ctx* c, Recorder* rec) {
+  int rc = rk4_step(c, single(c), rec);
+  if (rc) return rc;
   c->t += c->dt;
   c->step += 1;
   return GRMHD_OK;
@@ -272,7 +290,7 @@ int one_step(grmhd_ctx* c, Recorder* rec) {
 
 int prime_guesses(grmhd_ctx* c) {
   HIPCHK(hipMemsetAsync(c->prim, 0, 5 * c->L.P * sizeof(double), c->stream));
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->rnode, c->pp, c->stream));
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->rnode, c->pp, single(c), c->stream));
   return GRMHD_OK;
 }
 
@@ -286,7 +304,7 @@ int compute_k0(grmhd_ctx* c) {
     TaskList tl;
     tl.n = 0;
     add(tl, 0, 17, 1, SC_D1 + 21 * a + 17);
-    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B));
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, single(c)));
   }
   HIPCHK(launch_k0(c->U, c->scr, c->K0, c->pp, c->stream));
   return GRMHD_OK;
@@ -329,9 +347,10 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->res = (char*)dev_resident;
   c->scr = (double*)dev_scratch;
   c->stream = (hipStream_t)hip_stream;
-  if (hipGetDevice(&c->device) != hipSuccess) {
+  const hipError_t ge = hipGetDevice(&c->device);
+  if (ge != hipSuccess) {
     delete c;
-    return fail(GRMHD_E_DEVICE, "hipGetDevice failed");
+    return fail(GRMHD_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(ge));
   }
   build_operators(*grid, phys->cfl, &c->ops);
   const size_t P = c->L.P;
@@ -460,7 +479,7 @@ int grmhd_state_ptr(grmhd_ctx* c, double** dev_U, double** dev_K0) {
 int grmhd_rhs(grmhd_ctx* c, const double* dev_U, double* dev_dUdt) {
   if (!c || !dev_U || !dev_dUdt) return fail(GRMHD_E_ARG, "null argument");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
-  return rhs_eval(c, dev_U, 0, dev_dUdt);
+  return rhs_eval(c, dev_U, 0, dev_dUdt, single(c));
 }
 
 int grmhd_step(grmhd_ctx* c, int32_t nsteps) {
@@ -471,6 +490,70 @@ int grmhd_step(grmhd_ctx* c, int32_t nsteps) {
     int rc = one_step(c, nullptr);
     if (rc) return rc;
   }
+  return GRMHD_OK;
+}
+
+int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {
+  if (!ctxs || n < 1 || nsteps < 0) return fail(GRMHD_E_ARG, "need n >= 1 contexts and nsteps >= 0");
+  const grmhd_ctx* c0 = ctxs[0];
+  for (int j = 0; j < n; ++j) {
+    const grmhd_ctx* c = ctxs[j];
+    if (!c) return fail(GRMHD_E_ARG, "null context in batch");
+    if (!c->have_state) return fail(GRMHD_E_STATE, "context in batch has no state");
+    const bool same = c->grid.nr == c0->grid.nr && c->grid.nth == c0->grid.nth && c->grid.nph == c0->grid.nph &&
+                      c->grid.filter_on == c0->grid.filter_on && c->prec == c0->prec &&
+                      c->pp.gamma_ad == c0->pp.gamma_ad && c->pp.eta == c0->pp.eta &&
+                      c->pp.cowling == c0->pp.cowling && c->pp.gauge_k0 == c0->pp.gauge_k0 &&
+                      c->pp.rho_floor == c0->pp.rho_floor && c->pp.p_floor == c0->pp.p_floor &&
+                      c->stream == c0->stream &&
+                      ((const char*)c->scr - c->res) == ((const char*)c0->scr - c0->res);
+    if (!same)
+      return fail(GRMHD_E_ARG,
+                  "batched contexts need the same grid sizes, precision, kernel parameters, stream and "
+                  "scratch-to-resident offset");
+  }
+  for (int j0 = 0; j0 < n; j0 += MAXB) {
+    const int m = (n - j0 < MAXB) ? n - j0 : MAXB;
+    grmhd_ctx* c = ctxs[j0];
+    JobSet js;
+    js.n = m;
+    for (int j = 0; j < m; ++j) {
+      js.d[j] = (long long)(ctxs[j0 + j]->res - c->res);
+      js.dt[j] = ctxs[j0 + j]->dt;
+    }
+    for (int s = 0; s < nsteps; ++s) {
+      int rc = rk4_step(c, js, nullptr);
+      if (rc) return rc;
+    }
+    for (int j = 0; j < m; ++j) {
+      ctxs[j0 + j]->t += nsteps * ctxs[j0 + j]->dt;
+      ctxs[j0 + j]->step += nsteps;
+    }
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_set_dt(grmhd_ctx* c, double dt) {
+  if (!c || !(dt > 0.0)) return fail(GRMHD_E_ARG, "need a context and dt > 0");
+  c->dt = dt;
+  return GRMHD_OK;
+}
+
+int grmhd_set_stream(grmhd_ctx* c, void* hip_stream) {
+  if (!c) return fail(GRMHD_E_ARG, "null context");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(GRMHD_E_DEVICE, hipGetErrorString(e));
+  c->stream = (hipStream_t)hip_stream;
+  return GRMHD_OK;
+}
+
+int grmhd_time_step(const grmhd_grid* grid, double cfl, double* dt) {
+  int rc = validate_grid(grid);
+  if (rc) return rc;
+  if (!dt || !(cfl > 0.0)) return fail(GRMHD_E_ARG, "need dt output and cfl > 0");
+  Operators ops;
+  build_operators(*grid, cfl, &ops);
+  *dt = ops.dt;
   return GRMHD_OK;
 }
 
@@ -519,8 +602,8 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
   // (into the accumulator slot, free between steps); then d_i (sqrt(gamma) B^i)
   // into free first-derivative slots
   int rc = GRMHD_OK;
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, c->stream));
-  if ((rc = fp64_derivs(c, c->U, nullptr))) return rc;
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, single(c), c->stream));
+  if ((rc = fp64_derivs(c, c->U, single(c), nullptr))) return rc;
   double* H = sf(c, SC_ACC);
   HIPCHK(launch_ham(c->U, sf(c, SC_D1), c->prim, H, c->pp, c->stream));
   Bases B;
@@ -532,7 +615,7 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     TaskList tl;
     tl.n = 0;
     add(tl, 0, 29 + a, 1, SC_D1 + 21 * a + a);
-    hipError_t e = contract(c, a, 1, OP_D1, OP_D1, tl, B);
+    hipError_t e = contract(c, a, 1, OP_D1, OP_D1, tl, B, single(c));
     if (e != hipSuccess) return fail(GRMHD_E_DEVICE, hipGetErrorString(e));
   }
   int nb = 0;
@@ -587,7 +670,7 @@ int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* d
     TaskList tl;
     tl.n = 0;
     for (int f = f0; f < nfields && f < f0 + MAX_TASKS; ++f) add(tl, 0, f, 1, f);
-    HIPCHK(contract(c, axis, 1, o, o, tl, B));
+    HIPCHK(contract(c, axis, 1, o, o, tl, B, single(c)));
   }
   return GRMHD_OK;
 }
@@ -595,7 +678,7 @@ int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* d
 int grmhd_con2prim(grmhd_ctx* c, const double* dev_U, double* dev_prim, double* dev_flux) {
   if (!c || !dev_U || !dev_prim) return fail(GRMHD_E_ARG, "null argument");
   // guesses come from the context's last recovery; results also stored there
-  HIPCHK(launch_c2p_flux(dev_U, c->prim, c->fail, dev_flux, c->rnode, c->pp, c->stream));
+  HIPCHK(launch_c2p_flux(dev_U, c->prim, c->fail, dev_flux, c->rnode, c->pp, single(c), c->stream));
   HIPCHK(hipMemcpyAsync(dev_prim, c->prim, 5 * c->L.P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return GRMHD_OK;
 }

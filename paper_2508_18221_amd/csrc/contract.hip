@@ -38,16 +38,19 @@ template <int NMAT, bool INNER>
 __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
                                                   const double* __restrict__ AT0,
                                                   const double* __restrict__ AT1, int N, int Npad,
-                                                  int inner, int slab, long long P) {
+                                                  int inner, int slab, long long P, JobSet js) {
   extern __shared__ double tile[];  // [Npad][LDS_STRIDE]
-  const Task tk = tl.t[blockIdx.z];
+  const Task tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];  // this job's buffer offset
+  AT0 = shift_ptr(AT0, jd);
+  AT1 = shift_ptr(AT1, jd);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int c0 = blockIdx.x * TILE_COLS;
   const size_t off = (size_t)blockIdx.y * (size_t)slab;
-  const double* __restrict__ src = B.b[tk.src_sel] + (size_t)tk.src * (size_t)P + off;
-  double* __restrict__ dst0 = B.b[tk.dst_sel] + (size_t)tk.dst0 * (size_t)P + off;
-  double* __restrict__ dst1 = B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + off;
+  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
+  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
+  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + off;
 
   // ---- stage the input tile ------------------------------------------------
   // LOADS independent global loads per thread are issued before any of them
@@ -202,9 +205,9 @@ hipError_t set_kernel_attributes() {
 
 hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
                            const double* AT0, const double* AT1, const int n[3],
-                           const int npad[3], long long P, hipStream_t s) {
+                           const int npad[3], long long P, const JobSet& js, hipStream_t s) {
   if (tl.n <= 0) return hipSuccess;
-  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2)
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
     return hipErrorInvalidValue;
   const int N = n[axis], Npad = npad[axis];
   int inner, outer, slab;
@@ -221,22 +224,22 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
     outer = 1;
     slab = 0;
   }
-  dim3 grid((inner + TILE_COLS - 1) / TILE_COLS, outer, tl.n);
+  dim3 grid((inner + TILE_COLS - 1) / TILE_COLS, outer, tl.n * js.n);
   const size_t lds = lds_bytes(Npad);
   if (axis == 0) {
     if (nmat == 1)
       hipLaunchKernelGGL((k_contract<1, true>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P);
+                         inner, slab, P, js);
     else
       hipLaunchKernelGGL((k_contract<2, true>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P);
+                         inner, slab, P, js);
   } else {
     if (nmat == 1)
       hipLaunchKernelGGL((k_contract<1, false>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P);
+                         inner, slab, P, js);
     else
       hipLaunchKernelGGL((k_contract<2, false>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P);
+                         inner, slab, P, js);
   }
   return hipGetLastError();
 }

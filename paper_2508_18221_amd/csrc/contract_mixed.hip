@@ -29,9 +29,9 @@ constexpr int F32_STRIDE = 80;   // floats per tile row: 4 rows cover 64 banks o
 constexpr int BF_PAD = 8;        // bf16 padding per tile row (rows 4 banks apart)
 
 __device__ __forceinline__ double load_in(const MixedTask& t, const Bases& B, long long P,
-                                          size_t off) {
-  if (t.src_f32) return (double)(((const float*)B.b[t.src_sel]) + (size_t)t.src * (size_t)P)[off];
-  return (B.b[t.src_sel] + (size_t)t.src * (size_t)P)[off];
+                                          long long jd, size_t off) {
+  if (t.src_f32) return (double)(((const float*)shift_ptr(B.b[t.src_sel], jd)) + (size_t)t.src * (size_t)P)[off];
+  return (shift_ptr(B.b[t.src_sel], jd) + (size_t)t.src * (size_t)P)[off];
 }
 
 // Element (k, c) of the tile of this workgroup, as an offset inside one field.
@@ -46,17 +46,20 @@ template <int NMAT, bool INNER>
 __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
                                                       const float* __restrict__ AT0,
                                                       const float* __restrict__ AT1, int N, int Npad,
-                                                      int inner, int slab, long long P) {
+                                                      int inner, int slab, long long P, JobSet js) {
   extern __shared__ float tf[];  // [Npad][F32_STRIDE] + 64 doubles of line offsets
   double* shift = (double*)(tf + (size_t)Npad * F32_STRIDE);
-  const MixedTask tk = tl.t[blockIdx.z];
+  const MixedTask tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  AT0 = shift_ptr(AT0, jd);
+  AT1 = shift_ptr(AT1, jd);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c0 = blockIdx.x * MT_COLS;
   const size_t soff = (size_t)blockIdx.y * (size_t)slab;
   const int ncols = min(MT_COLS, inner - c0);
   if (threadIdx.x < MT_COLS)
     shift[threadIdx.x] =
-        threadIdx.x < ncols ? load_in(tk, B, P, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
+        threadIdx.x < ncols ? load_in(tk, B, P, jd, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
   __syncthreads();
   constexpr int LOADS = 16;
   const int total = Npad * MT_COLS;
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
       const int e = e0 + q * 256;
       int k, c;
       if (INNER) { c = e / Npad; k = e - c * Npad; } else { k = e >> 6; c = e & 63; }
-      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
+      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, jd, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
                                                : 0.0;
     }
 #pragma unroll
@@ -86,8 +89,8 @@ __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
   const int FW = 4 / (4 / WI);
   const int wi = wave % WI, wf = wave / WI;
   const int lr = lane & 15, lk = lane >> 4;
-  float* dst0 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst0 * (size_t)P + soff;
-  float* dst1 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + soff;
+  float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
+  float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
   for (int it = wi; it < T; it += WI) {
     f4 acc[NMAT][4];
 #pragma unroll
@@ -152,20 +155,25 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
                                                       const __bf16* __restrict__ A0l,
                                                       const __bf16* __restrict__ A1h,
                                                       const __bf16* __restrict__ A1l, int N, int Npad,
-                                                      int Kpad, int inner, int slab, long long P) {
+                                                      int Kpad, int inner, int slab, long long P, JobSet js) {
   extern __shared__ __bf16 tb[];  // hi [64][Kpad + BF_PAD], lo [64][Kpad + BF_PAD], 64 doubles
   const int RS = Kpad + BF_PAD;
   __bf16* thi = tb;
   __bf16* tlo = tb + (size_t)MT_COLS * RS;
   double* shift = (double*)(tb + (size_t)2 * MT_COLS * RS);
-  const MixedTask tk = tl.t[blockIdx.z];
+  const MixedTask tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  A0h = shift_ptr(A0h, jd);
+  A0l = shift_ptr(A0l, jd);
+  A1h = shift_ptr(A1h, jd);
+  A1l = shift_ptr(A1l, jd);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c0 = blockIdx.x * MT_COLS;
   const size_t soff = (size_t)blockIdx.y * (size_t)slab;
   const int ncols = min(MT_COLS, inner - c0);
   if (threadIdx.x < MT_COLS)
     shift[threadIdx.x] =
-        threadIdx.x < ncols ? load_in(tk, B, P, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
+        threadIdx.x < ncols ? load_in(tk, B, P, jd, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
   __syncthreads();
   constexpr int LOADS = 16;
   const int total = Kpad * MT_COLS;
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
       const int e = e0 + q * 256;
       int k, c;
       if (INNER) { c = e / Kpad; k = e - c * Kpad; } else { k = e >> 6; c = e & 63; }
-      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
+      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, jd, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
                                                : 0.0;
     }
 #pragma unroll
@@ -198,8 +206,8 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
   const int FW = 4 / (4 / WI);
   const int wi = wave % WI, wf = wave / WI;
   const int lr = lane & 15, lk = lane >> 4;
-  float* dst0 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst0 * (size_t)P + soff;
-  float* dst1 = (float*)B.b[tk.dst_sel] + (size_t)tk.dst1 * (size_t)P + soff;
+  float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
+  float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
   for (int it = wi; it < T; it += WI) {
     f4 acc[NMAT][4];
 #pragma unroll
@@ -307,18 +315,19 @@ hipError_t set_mixed_kernel_attributes() {
 
 hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskList& tl, const Bases& B,
                                  const MixedOps& op0, const MixedOps& op1, const int n[3],
-                                 const int npad[3], long long P, hipStream_t s) {
+                                 const int npad[3], long long P, const JobSet& js, hipStream_t s) {
   if (tl.n <= 0) return hipSuccess;
-  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2) return hipErrorInvalidValue;
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
+    return hipErrorInvalidValue;
   const int N = n[axis], Npad = npad[axis];
   int inner, outer, slab;
   geometry(axis, n, &inner, &outer, &slab);
-  dim3 grid((inner + MT_COLS - 1) / MT_COLS, outer, tl.n);
+  dim3 grid((inner + MT_COLS - 1) / MT_COLS, outer, tl.n * js.n);
   const size_t lds = mixed_lds_bytes(prec, Npad);
   if (prec == GRMHD_MIX_FP32) {
 #define L32(NM, IN)                                                                                    \
   hipLaunchKernelGGL((k_contract_f32<NM, IN>), grid, dim3(256), lds, s, tl, B, op0.f32, op1.f32, N, Npad, \
-                     inner, slab, P)
+                     inner, slab, P, js)
     if (axis == 0) {
       if (nmat == 1) L32(1, true); else L32(2, true);
     } else {
@@ -329,7 +338,7 @@ hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskLi
     const int Kpad = round_up(Npad, 32);
 #define LBF(NM, IN)                                                                                     \
   hipLaunchKernelGGL((k_contract_bf3<NM, IN>), grid, dim3(256), lds, s, tl, B, op0.bhi, op0.blo, op1.bhi, \
-                     op1.blo, N, Npad, Kpad, inner, slab, P)
+                     op1.blo, N, Npad, Kpad, inner, slab, P, js)
     if (axis == 0) {
       if (nmat == 1) LBF(1, true); else LBF(2, true);
     } else {

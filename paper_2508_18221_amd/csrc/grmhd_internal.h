@@ -82,6 +82,21 @@ struct MixedOps {
   const __bf16* blo;
 };
 
+// Jobs advanced by one launch (same grid class, same buffer layout): byte
+// offset of job j's buffers from job 0's (its resident and scratch blocks
+// move together) and its time step.  A single context is n = 1, d = 0.
+constexpr int MAXB = 32;
+struct JobSet {
+  int n;
+  long long d[MAXB];
+  double dt[MAXB];
+};
+
+template <class T>
+__host__ __device__ inline T* shift_ptr(T* p, long long d) {
+  return (T*)((char*)p + d);
+}
+
 struct PointParams {
   int nr, nth, nph;
   long long P;
@@ -116,18 +131,18 @@ int host_initial_data(const grmhd_grid& g, const grmhd_phys& ph, const Operators
 // Contraction along axis (0 r, 1 theta, 2 phi) with nmat = 1 or 2 matrices.
 hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
                            const double* AT0, const double* AT1, const int n[3],
-                           const int npad[3], long long P, hipStream_t s);
+                           const int npad[3], long long P, const JobSet& js, hipStream_t s);
 hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskList& tl, const Bases& B,
                                  const MixedOps& op0, const MixedOps& op1, const int n[3],
-                                 const int npad[3], long long P, hipStream_t s);
+                                 const int npad[3], long long P, const JobSet& js, hipStream_t s);
 hipError_t set_mixed_kernel_attributes();
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
-                           const double* rnode, const PointParams& pp, hipStream_t s);
+                           const double* rnode, const PointParams& pp, const JobSet& js, hipStream_t s);
 // mode 0: out = L(U_s); 1..4: classic RK4 stage s.  der: derivative arrays
 // (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Un, double* acc, double* out,
-                         double dt, const PointParams& pp, hipStream_t s);
+                         const PointParams& pp, const JobSet& js, hipStream_t s);
 // Hamiltonian constraint from FP64 derivative arrays into H (P doubles)
 hipError_t launch_ham(const double* U, const double* der, const double* prim, double* H,
                       const PointParams& pp, hipStream_t s);

@@ -277,10 +277,19 @@ __global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
                                                   double* __restrict__ prim,
                                                   double* __restrict__ fail,
                                                   double* __restrict__ flux,
-                                                  const double* __restrict__ rnode, PointParams pp) {
+                                                  const double* __restrict__ rnode, PointParams pp,
+                                                  JobSet js) {
   const long long P = pp.P;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= P) return;
+  {  // this job's buffers
+    const long long jd = js.d[blockIdx.y];
+    U = shift_ptr(U, jd);
+    prim = shift_ptr(prim, jd);
+    fail = shift_ptr(fail, jd);
+    rnode = shift_ptr(rnode, jd);
+    if (flux != nullptr) flux = shift_ptr(flux, jd);
+  }
   const int j = (int)(idx % pp.nr);
 #define LD(f) U[(size_t)(f) * P + idx]
   const double phi = LD(0);
@@ -362,10 +371,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                 const double* __restrict__ prim,
                                                 const double* __restrict__ K0p,
                                                 const double* Un, double* acc, double* out,
-                                                double dt, PointParams pp) {
+                                                PointParams pp, JobSet js) {
   const long long P = pp.P;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= P) return;
+  const double dt = js.dt[blockIdx.y];
+  {  // this job's buffers
+    const long long jd = js.d[blockIdx.y];
+    Us = shift_ptr(Us, jd);
+    der = shift_ptr(der, jd);
+    prim = shift_ptr(prim, jd);
+    K0p = shift_ptr(K0p, jd);
+    Un = shift_ptr(Un, jd);
+    acc = shift_ptr(acc, jd);
+    out = shift_ptr(out, jd);
+  }
   const int j = (int)(idx % pp.nr);
   const int k = (int)((idx / pp.nr) % pp.nth);
   const bool frozen = (j == 0 || k == 0 || k == pp.nth - 1);
@@ -782,21 +802,22 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
 static inline unsigned nblk(long long P) { return (unsigned)((P + 255) / 256); }
 
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
-                           const double* rnode, const PointParams& pp, hipStream_t s) {
-  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P)), dim3(256), 0, s, U, prim, fail, flux, rnode, pp);
+                           const double* rnode, const PointParams& pp, const JobSet& js, hipStream_t s) {
+  if (js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, prim, fail, flux, rnode, pp, js);
   return hipGetLastError();
 }
 
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
-                         const double* K0, const double* Un, double* acc, double* out, double dt,
-                         const PointParams& pp, hipStream_t s) {
-  if (mode < 0 || mode > 4) return hipErrorInvalidValue;
+                         const double* K0, const double* Un, double* acc, double* out,
+                         const PointParams& pp, const JobSet& js, hipStream_t s) {
+  if (mode < 0 || mode > 4 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
   if (der_f32)
-    hipLaunchKernelGGL(k_rhs_rk<float>, dim3(nblk(pp.P)), dim3(256), 0, s, mode, Us, (const float*)der, prim,
-                       K0, Un, acc, out, dt, pp);
+    hipLaunchKernelGGL(k_rhs_rk<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, (const float*)der,
+                       prim, K0, Un, acc, out, pp, js);
   else
-    hipLaunchKernelGGL(k_rhs_rk<double>, dim3(nblk(pp.P)), dim3(256), 0, s, mode, Us, (const double*)der,
-                       prim, K0, Un, acc, out, dt, pp);
+    hipLaunchKernelGGL(k_rhs_rk<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us,
+                       (const double*)der, prim, K0, Un, acc, out, pp, js);
   return hipGetLastError();
 }
 

@@ -7,7 +7,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import Grid, Phys, Diag, check, NFIELDS
+from ._lib import Grid, Phys, Diag, JobInfo, ServerStats, check, check_server, NFIELDS
 
 
 def make_grid(nr, nth, nph, r_in=1.8, r_out=20.0, th_min=0.05, th_max=np.pi - 0.05,
@@ -39,8 +39,12 @@ class Solver:
         res, scr = ctypes.c_size_t(), ctypes.c_size_t()
         check(lib.grmhd_query_bytes(ctypes.byref(grid), prec, ctypes.byref(res), ctypes.byref(scr)))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.resident = torch.empty(res.value, dtype=torch.uint8, device="cuda")
-        self.scratch = torch.empty(scr.value, dtype=torch.uint8, device="cuda")
+        # one block: resident buffer, then scratch (contexts laid out alike can
+        # be stepped together by step_batch)
+        rb = (res.value + 255) // 256 * 256
+        self.block = torch.empty(rb + scr.value, dtype=torch.uint8, device="cuda")
+        self.resident = self.block[:rb]
+        self.scratch = self.block[rb:]
         ctx = ctypes.c_void_p()
         check(lib.grmhd_create(ctypes.byref(grid), ctypes.byref(phys), prec, _ptr(self.resident),
                                _ptr(self.scratch), ctypes.c_void_p(self.stream.cuda_stream),
@@ -116,6 +120,9 @@ class Solver:
         check(self.lib.grmhd_profile_step(self.ctx, int(nsteps), ms, n, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_KINDS)}
 
+    def set_dt(self, dt):
+        check(self.lib.grmhd_set_dt(self.ctx, float(dt)))
+
     @property
     def dt(self):
         return self.lib.grmhd_dt(self.ctx)
@@ -123,3 +130,75 @@ class Solver:
     @property
     def time(self):
         return self.lib.grmhd_time(self.ctx)
+
+
+def step_batch(solvers, nsteps=1):
+    """Advance same-class solvers together, one launch per kernel for all."""
+    lib = _lib.load()
+    arr = (ctypes.c_void_p * len(solvers))(*[s.ctx.value for s in solvers])
+    check(lib.grmhd_step_batch(arr, len(solvers), int(nsteps)))
+
+
+class Server:
+    """Continuous-batching job server over a device arena of `budget` bytes
+    (allocated here with PyTorch).  budget = 0 or dry=True: no device work."""
+
+    def __init__(self, budget, max_batch=32, dry=False):
+        lib = _lib.load()
+        self.lib = lib
+        self.arena = None
+        ptr = None
+        if not dry:
+            import torch
+            self.arena = torch.empty(int(budget), dtype=torch.uint8, device="cuda")
+            ptr = ctypes.c_void_p(self.arena.data_ptr())
+            stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        else:
+            stream = None
+        srv = ctypes.c_void_p()
+        check_server(lib.grmhd_server_create(ptr, int(budget), int(max_batch), stream, ctypes.byref(srv)))
+        self.srv = srv
+
+    def close(self):
+        if self.srv:
+            self.lib.grmhd_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, grid, phys, t_end, prec=_lib.GRMHD_FP64, keep_state=False):
+        jid = ctypes.c_int64()
+        rc = self.lib.grmhd_server_submit(self.srv, ctypes.byref(grid), ctypes.byref(phys), int(prec),
+                                          float(t_end), int(keep_state), ctypes.byref(jid))
+        if rc == -5:   # over budget: the job is recorded as rejected
+            return jid.value
+        check_server(rc)
+        return jid.value
+
+    def tick(self):
+        n = ctypes.c_int32()
+        check_server(self.lib.grmhd_server_tick(self.srv, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, job_id):
+        info = JobInfo()
+        check_server(self.lib.grmhd_server_poll(self.srv, int(job_id), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in JobInfo._fields_}
+
+    def result(self, job_id, shape):
+        U = np.empty((NFIELDS,) + tuple(shape))
+        check_server(self.lib.grmhd_server_result(self.srv, int(job_id),
+                                                  U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), U.size))
+        return U
+
+    def stats(self):
+        st = ServerStats()
+        check_server(self.lib.grmhd_server_stats(self.srv, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def clock(self):
+        return self.lib.grmhd_server_clock(self.srv)

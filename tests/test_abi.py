@@ -48,3 +48,17 @@ def test_query_bytes_and_validation_on_host():
     assert lib.grmhd_query_bytes(ctypes.byref(small), 0, ctypes.byref(res), ctypes.byref(scr)) == -1
     with pytest.raises(Exception):
         _lib.check(lib.grmhd_query_bytes(ctypes.byref(bad), 0, ctypes.byref(res), ctypes.byref(scr)))
+
+
+def test_library_shares_torch_hip_runtime():
+    """The library must bind to the HIP runtime that allocated the device
+    memory and streams it is handed (PyTorch ships its own copy); a second
+    runtime in the process sees no device."""
+    import subprocess
+    import sys
+    code = ("from paper_2508_18221_amd import _lib; _lib.load(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
+                         cwd=str(__import__("pathlib").Path(__file__).resolve().parents[1])).stdout
+    libs = eval(out.strip().splitlines()[-1])
+    assert len(libs) == 1, libs

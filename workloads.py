@@ -58,3 +58,24 @@ def smooth_fields(grid_r, grid_th, grid_ph, nfields, seed):
         m = rng.integers(0, 4)
         out.append((1.0 / (R + c)) * np.cos(a * T + b) * (1.0 + 0.3 * np.cos(m * Ph + rng.uniform(0, 6))))
     return np.array(out)
+
+
+# ---- served job stream --------------------------------------------------------
+SERVED_GRIDS = [(16, 16, 16), (32, 32, 64), (48, 48, 96), (64, 64, 128)]
+
+
+def served_stream(n_jobs=256, rate=4.0, seed=2508, t_scale=1.0):
+    """Seeded job stream: Poisson arrivals at `rate` jobs/s; per job spin
+    a ~ U[0, 0.95], plasma beta ~ logU[10, 1000], a grid drawn uniformly from
+    SERVED_GRIDS, end time T ~ U[10, 100] M times t_scale, and its own
+    perturbation seed."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_jobs)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    jobs = []
+    for i in range(n_jobs):
+        jobs.append(dict(arrival=float(arrivals[i]), a=float(rng.uniform(0.0, 0.95)),
+                         beta=float(10 ** rng.uniform(1.0, 3.0)),
+                         grid=SERVED_GRIDS[int(rng.integers(0, len(SERVED_GRIDS)))],
+                         T=float(rng.uniform(10.0, 100.0) * t_scale), seed=int(rng.integers(1, 2 ** 62))))
+    return jobs
