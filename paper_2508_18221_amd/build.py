@@ -19,6 +19,9 @@ SOURCES = ["contract.hip", "contract_mixed.hip", "pointwise.hip", "operators.cpp
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: no per-loop-trip copies
+         # through the accumulation registers
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", INCLUDE, "-I", CSRC]
 
 

@@ -42,7 +42,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct Layout {
   size_t P;
-  size_t res_fields, mats[3][3], rnode, wr, wth, partials, res_total;
+  size_t res_fields, mats[3][3], floors, wr, wth, partials, res_total;
   size_t m32[3][2], mhi[3][2], mlo[3][2];  // reduced-precision operators (D1, D2)
   size_t scr_total;
 };
@@ -84,8 +84,8 @@ Layout layout(const grmhd_grid& g) {
       off += align256(np * kp * 2);
     }
   }
-  L.rnode = off;
-  off += align256((size_t)g.nr * sizeof(double));
+  L.floors = off;  // rho floor then p floor at each radial node
+  off += align256((size_t)2 * g.nr * sizeof(double));
   L.wr = off;
   off += align256((size_t)g.nr * sizeof(double));
   L.wth = off;
@@ -112,7 +112,8 @@ struct grmhd_ctx {
   double *U, *K0, *prim, *fail;
   const double* mats[3][3];
   MixedOps mops[3][2];
-  double *rnode, *wr, *wth, *partials;
+  double *floors, *wr, *wth, *partials;
+  std::vector<double> floor_host;
   PointParams pp;
   double dt, t;
   int64_t step;
@@ -238,7 +239,7 @@ int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec
 // addressed through context c (the first job).
 int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSet& js,
              Recorder* rec = nullptr) {
-  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, js, c->stream));
+  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, c->stream));
   MARK(rec, GRMHD_K_C2P_FLUX);
   const bool mixed = c->prec != GRMHD_FP64;
   int rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
@@ -290,7 +291,7 @@ int one_step(grmhd_ctx* c, Recorder* rec) {
 
 int prime_guesses(grmhd_ctx* c) {
   HIPCHK(hipMemsetAsync(c->prim, 0, 5 * c->L.P * sizeof(double), c->stream));
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->rnode, c->pp, single(c), c->stream));
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->floors, c->pp, single(c), c->stream));
   return GRMHD_OK;
 }
 
@@ -353,6 +354,12 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
     return fail(GRMHD_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(ge));
   }
   build_operators(*grid, phys->cfl, &c->ops);
+  // atmosphere floors rho_floor r^-3/2 and p_floor r^-5/2 at the radial nodes
+  c->floor_host.resize(2 * (size_t)grid->nr);
+  for (int j = 0; j < grid->nr; ++j) {
+    c->floor_host[j] = phys->rho_floor * pow(c->ops.r[j], -1.5);
+    c->floor_host[grid->nr + j] = phys->p_floor * pow(c->ops.r[j], -2.5);
+  }
   const size_t P = c->L.P;
   double* rf = (double*)(c->res + c->L.res_fields);
   c->U = rf + (size_t)RS_U * P;
@@ -367,7 +374,7 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
       c->mops[a][o].bhi = (const __bf16*)(c->res + c->L.mhi[a][o]);
       c->mops[a][o].blo = (const __bf16*)(c->res + c->L.mlo[a][o]);
     }
-  c->rnode = (double*)(c->res + c->L.rnode);
+  c->floors = (double*)(c->res + c->L.floors);
   c->wr = (double*)(c->res + c->L.wr);
   c->wth = (double*)(c->res + c->L.wth);
   c->partials = (double*)(c->res + c->L.partials);
@@ -403,7 +410,8 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
       e = hipMemcpyAsync((void*)c->mats[a][o], c->ops.at[a][o].data(), c->ops.at[a][o].size() * sizeof(double),
                          hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->rnode, c->ops.r.data(), grid->nr * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    e = hipMemcpyAsync(c->floors, c->floor_host.data(), c->floor_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->wr, c->ops.wr.data(), grid->nr * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
@@ -602,7 +610,7 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
   // (into the accumulator slot, free between steps); then d_i (sqrt(gamma) B^i)
   // into free first-derivative slots
   int rc = GRMHD_OK;
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, sf(c, SC_FLUX), c->rnode, c->pp, single(c), c->stream));
+  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, single(c), c->stream));
   if ((rc = fp64_derivs(c, c->U, single(c), nullptr))) return rc;
   double* H = sf(c, SC_ACC);
   HIPCHK(launch_ham(c->U, sf(c, SC_D1), c->prim, H, c->pp, c->stream));
@@ -678,7 +686,7 @@ int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* d
 int grmhd_con2prim(grmhd_ctx* c, const double* dev_U, double* dev_prim, double* dev_flux) {
   if (!c || !dev_U || !dev_prim) return fail(GRMHD_E_ARG, "null argument");
   // guesses come from the context's last recovery; results also stored there
-  HIPCHK(launch_c2p_flux(dev_U, c->prim, c->fail, dev_flux, c->rnode, c->pp, single(c), c->stream));
+  HIPCHK(launch_c2p_flux(dev_U, c->prim, c->fail, dev_flux, c->floors, c->pp, single(c), c->stream));
   HIPCHK(hipMemcpyAsync(dev_prim, c->prim, 5 * c->L.P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return GRMHD_OK;
 }

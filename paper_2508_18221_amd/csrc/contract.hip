@@ -26,7 +26,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int TILE_COLS = 64;
 constexpr int LDS_STRIDE = 72;  // doubles: rows 16 banks apart, so the 4 rows a
                                 // fragment read touches hit each bank twice
-constexpr int KC = 8;           // k-steps (of 4) of operator fragments held in registers
+constexpr int KC = 4;           // k-steps (of 4) of operator fragments held in registers
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -34,7 +34,7 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 
 // INNER = true : r axis (tile columns are r-lines, output rows are lines)
 // INNER = false: theta / phi axes (tile columns are contiguous inner points)
-template <int NMAT, bool INNER>
+template <int NMAT, bool INNER, int WI>
 __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
                                                   const double* __restrict__ AT0,
                                                   const double* __restrict__ AT1, int N, int Npad,
@@ -99,59 +99,61 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
   __syncthreads();
 
   // ---- work split: i-tiles (operator rows) x column fragments ---------------
+  // WI waves along the operator rows, 4 / WI along the 64 tile columns; each
+  // wave owns FW = WI fragments of 16 columns.  Everything inside the k loop
+  // is compile-time shaped, so the MFMAs issue back to back on independent
+  // accumulators instead of one at a time behind branches.
+  constexpr int FW = WI;
   const int T = Npad >> 4;
-  const int WI = T >= 4 ? 4 : (T >= 2 ? 2 : 1);
-  const int FW = 4 / (4 / WI);  // fragments per wave: 4, 2, 1 for WI = 4, 2, 1
   const int wi = wave % WI, wf = wave / WI;
   const int lr = lane & 15, lk = lane >> 4;
 
-  const int nks = Npad >> 2;  // k-steps
+  const int nks = Npad >> 2;  // k-steps of 4; a multiple of KC since Npad % 16 == 0
   for (int it = wi; it < T; it += WI) {
-    d4 acc[NMAT][4];
+    d4 acc[NMAT][FW];
 #pragma unroll
     for (int m = 0; m < NMAT; ++m)
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[m][f] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int f = 0; f < FW; ++f) acc[m][f] = d4{0.0, 0.0, 0.0, 0.0};
     const double* __restrict__ a0p = AT0 + (size_t)lk * Npad + it * 16 + lr;
     const double* __restrict__ a1p = (NMAT > 1 ? AT1 : AT0) + (size_t)lk * Npad + it * 16 + lr;
     const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
-    // operator fragments for KC k-steps live in registers; the next chunk is
-    // requested before the current one is consumed (one L2 latency per chunk)
-    double a[NMAT][KC], an[NMAT][KC];
+    // operator fragments of one chunk (KC k-steps) live in registers; the next
+    // chunk is requested before the current one is consumed
+    double a[NMAT][KC];
 #pragma unroll
     for (int q = 0; q < KC; ++q) {
-      const bool ok = q < nks;
-      a[0][q] = ok ? a0p[(size_t)(4 * q) * Npad] : 0.0;
-      if (NMAT > 1) a[NMAT - 1][q] = ok ? a1p[(size_t)(4 * q) * Npad] : 0.0;
+      a[0][q] = a0p[(size_t)(4 * q) * Npad];
+      if (NMAT > 1) a[NMAT - 1][q] = a1p[(size_t)(4 * q) * Npad];
     }
     for (int kc = 0; kc < nks; kc += KC) {
+      // the last chunk re-requests itself: an in-bounds dummy prefetch
+      const int kn = (kc + KC < nks) ? kc + KC : kc;
+      double an[NMAT][KC];
 #pragma unroll
       for (int q = 0; q < KC; ++q) {
-        const bool ok = kc + KC + q < nks;
-        an[0][q] = ok ? a0p[(size_t)(4 * (kc + KC + q)) * Npad] : 0.0;
-        if (NMAT > 1) an[NMAT - 1][q] = ok ? a1p[(size_t)(4 * (kc + KC + q)) * Npad] : 0.0;
+        an[0][q] = a0p[(size_t)(4 * (kn + q)) * Npad];
+        if (NMAT > 1) an[NMAT - 1][q] = a1p[(size_t)(4 * (kn + q)) * Npad];
       }
+      double b[KC][FW];
 #pragma unroll
-      for (int q = 0; q < KC; ++q) {
-        if (kc + q < nks) {
-          const int k0 = 4 * (kc + q);
+      for (int q = 0; q < KC; ++q)
 #pragma unroll
-          for (int f = 0; f < 4; ++f) {
-            if (f < FW) {
-              const double b = tp[k0 * LDS_STRIDE + f * 16];
-              if (INNER) {
-                // D[line][i] = sum_k tile^T[line][k] AT[k][i]
-                acc[0][f] = mfma_f64(b, a[0][q], acc[0][f]);
-                if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(b, a[NMAT - 1][q], acc[NMAT - 1][f]);
-              } else {
-                // D[i][c] = sum_k A[i][k] tile[k][c]
-                acc[0][f] = mfma_f64(a[0][q], b, acc[0][f]);
-                if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(a[NMAT - 1][q], b, acc[NMAT - 1][f]);
-              }
-            }
+        for (int f = 0; f < FW; ++f) b[q][f] = tp[(4 * (kc + q)) * LDS_STRIDE + f * 16];
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+#pragma unroll
+        for (int f = 0; f < FW; ++f) {
+          if (INNER) {
+            // D[line][i] = sum_k tile^T[line][k] AT[k][i]
+            acc[0][f] = mfma_f64(b[q][f], a[0][q], acc[0][f]);
+            if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(b[q][f], a[NMAT - 1][q], acc[NMAT - 1][f]);
+          } else {
+            // D[i][c] = sum_k A[i][k] tile[k][c]
+            acc[0][f] = mfma_f64(a[0][q], b[q][f], acc[0][f]);
+            if (NMAT > 1) acc[NMAT - 1][f] = mfma_f64(a[NMAT - 1][q], b[q][f], acc[NMAT - 1][f]);
           }
         }
-      }
 #pragma unroll
       for (int q = 0; q < KC; ++q) {
         a[0][q] = an[0][q];
@@ -160,8 +162,8 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
     }
     // ---- store ------------------------------------------------------------
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if (f < FW) {
+    for (int f = 0; f < FW; ++f) {
+      {
         const int cf = (wf * FW + f) * 16;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -187,20 +189,42 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
 
 static size_t lds_bytes(int npad) { return (size_t)npad * LDS_STRIDE * sizeof(double); }
 
-hipError_t set_kernel_attributes() {
+template <int NMAT, bool INNER, int WI>
+static hipError_t set_attr() {
   const int max_lds = 256 * LDS_STRIDE * (int)sizeof(double);  // npad <= 256
-  hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)k_contract<1, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute((const void*)k_contract<2, true>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute((const void*)k_contract<1, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_lds)) != hipSuccess)
-    return e;
-  return hipFuncSetAttribute((const void*)k_contract<2, false>,
+  return hipFuncSetAttribute((const void*)k_contract<NMAT, INNER, WI>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+template <int NMAT, bool INNER>
+static hipError_t set_attr_wi() {
+  hipError_t e = set_attr<NMAT, INNER, 1>();
+  if (e == hipSuccess) e = set_attr<NMAT, INNER, 2>();
+  if (e == hipSuccess) e = set_attr<NMAT, INNER, 4>();
+  return e;
+}
+
+hipError_t set_kernel_attributes() {
+  hipError_t e = set_attr_wi<1, true>();
+  if (e == hipSuccess) e = set_attr_wi<2, true>();
+  if (e == hipSuccess) e = set_attr_wi<1, false>();
+  if (e == hipSuccess) e = set_attr_wi<2, false>();
+  return e;
+}
+
+template <int NMAT, bool INNER>
+static void launch_wi(int T, dim3 grid, size_t lds, hipStream_t s, const TaskList& tl, const Bases& B,
+                      const double* AT0, const double* AT1, int N, int Npad, int inner, int slab,
+                      long long P, const JobSet& js) {
+  if (T >= 4)
+    hipLaunchKernelGGL((k_contract<NMAT, INNER, 4>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                       inner, slab, P, js);
+  else if (T >= 2)
+    hipLaunchKernelGGL((k_contract<NMAT, INNER, 2>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                       inner, slab, P, js);
+  else
+    hipLaunchKernelGGL((k_contract<NMAT, INNER, 1>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+                       inner, slab, P, js);
 }
 
 hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
@@ -226,20 +250,13 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
   }
   dim3 grid((inner + TILE_COLS - 1) / TILE_COLS, outer, tl.n * js.n);
   const size_t lds = lds_bytes(Npad);
+  const int T = Npad >> 4;
   if (axis == 0) {
-    if (nmat == 1)
-      hipLaunchKernelGGL((k_contract<1, true>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P, js);
-    else
-      hipLaunchKernelGGL((k_contract<2, true>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P, js);
+    if (nmat == 1) launch_wi<1, true>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+    else launch_wi<2, true>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
   } else {
-    if (nmat == 1)
-      hipLaunchKernelGGL((k_contract<1, false>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P, js);
-    else
-      hipLaunchKernelGGL((k_contract<2, false>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
-                         inner, slab, P, js);
+    if (nmat == 1) launch_wi<1, false>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+    else launch_wi<2, false>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
   }
   return hipGetLastError();
 }

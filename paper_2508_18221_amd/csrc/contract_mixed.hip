@@ -27,6 +27,7 @@ typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 constexpr int MT_COLS = 64;
 constexpr int F32_STRIDE = 80;   // floats per tile row: 4 rows cover 64 banks once
 constexpr int BF_PAD = 8;        // bf16 padding per tile row (rows 4 banks apart)
+constexpr int KC32 = 4;          // FP32 form: k-steps (of 4) of operator fragments per chunk
 
 __device__ __forceinline__ double load_in(const MixedTask& t, const Bases& B, long long P,
                                           long long jd, size_t off) {
@@ -42,7 +43,7 @@ __device__ __forceinline__ size_t elem(int k, int c, int c0, int N, int inner, s
 }
 
 // ---------------------------------------------------------------------------
-template <int NMAT, bool INNER>
+template <int NMAT, bool INNER, int WI>
 __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
                                                       const float* __restrict__ AT0,
                                                       const float* __restrict__ AT1, int N, int Npad,
@@ -85,42 +86,64 @@ __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
   }
   __syncthreads();
   const int T = Npad >> 4;
-  const int WI = T >= 4 ? 4 : (T >= 2 ? 2 : 1);
-  const int FW = 4 / (4 / WI);
+  constexpr int FW = WI;  // 16-column fragments per wave; WI waves along the rows
   const int wi = wave % WI, wf = wave / WI;
   const int lr = lane & 15, lk = lane >> 4;
   float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
   float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
   for (int it = wi; it < T; it += WI) {
-    f4 acc[NMAT][4];
+    f4 acc[NMAT][FW];
 #pragma unroll
     for (int m = 0; m < NMAT; ++m)
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[m][f] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int f = 0; f < FW; ++f) acc[m][f] = f4{0.f, 0.f, 0.f, 0.f};
     const float* a0p = AT0 + (size_t)lk * Npad + it * 16 + lr;
     const float* a1p = (NMAT > 1 ? AT1 : AT0) + (size_t)lk * Npad + it * 16 + lr;
     const float* tp = tf + lk * F32_STRIDE + wf * FW * 16 + lr;
-#pragma unroll 4
-    for (int k0 = 0; k0 < Npad; k0 += 4) {
-      const float a0 = a0p[(size_t)k0 * Npad];
-      const float a1 = (NMAT > 1) ? a1p[(size_t)k0 * Npad] : 0.f;
+    // operator fragments of KC k-steps in registers, the next chunk requested
+    // before the current one is consumed (the last chunk re-requests itself)
+    const int nks = Npad >> 2;  // a multiple of KC32 since Npad % 16 == 0
+    float a[NMAT][KC32];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        if (f < FW) {
-          const float b = tp[k0 * F32_STRIDE + f * 16];
+    for (int q = 0; q < KC32; ++q) {
+      a[0][q] = a0p[(size_t)(4 * q) * Npad];
+      if (NMAT > 1) a[NMAT - 1][q] = a1p[(size_t)(4 * q) * Npad];
+    }
+    for (int kc = 0; kc < nks; kc += KC32) {
+      const int kn = (kc + KC32 < nks) ? kc + KC32 : kc;
+      float an[NMAT][KC32], b[KC32][FW];
+#pragma unroll
+      for (int q = 0; q < KC32; ++q) {
+        an[0][q] = a0p[(size_t)(4 * (kn + q)) * Npad];
+        if (NMAT > 1) an[NMAT - 1][q] = a1p[(size_t)(4 * (kn + q)) * Npad];
+      }
+#pragma unroll
+      for (int q = 0; q < KC32; ++q)
+#pragma unroll
+        for (int f = 0; f < FW; ++f) b[q][f] = tp[(4 * (kc + q)) * F32_STRIDE + f * 16];
+#pragma unroll
+      for (int q = 0; q < KC32; ++q)
+#pragma unroll
+        for (int f = 0; f < FW; ++f) {
           if (INNER) {
-            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a0, acc[0][f], 0, 0, 0);
-            if (NMAT > 1) acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b, a1, acc[NMAT - 1][f], 0, 0, 0);
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][f], a[0][q], acc[0][f], 0, 0, 0);
+            if (NMAT > 1)
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[q][f], a[NMAT - 1][q], acc[NMAT - 1][f], 0, 0, 0);
           } else {
-            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][f], 0, 0, 0);
-            if (NMAT > 1) acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[NMAT - 1][f], 0, 0, 0);
+            acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0][q], b[q][f], acc[0][f], 0, 0, 0);
+            if (NMAT > 1)
+              acc[NMAT - 1][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[NMAT - 1][q], b[q][f], acc[NMAT - 1][f], 0, 0, 0);
           }
         }
+#pragma unroll
+      for (int q = 0; q < KC32; ++q) {
+        a[0][q] = an[0][q];
+        if (NMAT > 1) a[NMAT - 1][q] = an[NMAT - 1][q];
       }
     }
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if (f < FW) {
+    for (int f = 0; f < FW; ++f) {
+      {
         const int cf = (wf * FW + f) * 16;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -149,7 +172,7 @@ __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
 // high and low parts in two arrays.  The tile is stored column-major
 // (tile[c][k], k contiguous) so each lane reads 8 consecutive k with one
 // 16-byte load, for both the r axis and the theta/phi axes.
-template <int NMAT, bool INNER>
+template <int NMAT, bool INNER, int WI>
 __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
                                                       const __bf16* __restrict__ A0h,
                                                       const __bf16* __restrict__ A0l,
@@ -202,18 +225,17 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
   }
   __syncthreads();
   const int T = Npad >> 4;
-  const int WI = T >= 4 ? 4 : (T >= 2 ? 2 : 1);
-  const int FW = 4 / (4 / WI);
+  constexpr int FW = WI;  // 16-column fragments per wave; WI waves along the rows
   const int wi = wave % WI, wf = wave / WI;
   const int lr = lane & 15, lk = lane >> 4;
   float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
   float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
   for (int it = wi; it < T; it += WI) {
-    f4 acc[NMAT][4];
+    f4 acc[NMAT][FW];
 #pragma unroll
     for (int m = 0; m < NMAT; ++m)
 #pragma unroll
-      for (int f = 0; f < 4; ++f) acc[m][f] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int f = 0; f < FW; ++f) acc[m][f] = f4{0.f, 0.f, 0.f, 0.f};
     const size_t arow = (size_t)(it * 16 + lr) * Kpad + 8 * lk;
     for (int k0 = 0; k0 < Kpad; k0 += 32) {
       const b8 ah0 = *(const b8*)(A0h + arow + k0);
@@ -224,8 +246,8 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
         al1 = *(const b8*)(A1l + arow + k0);
       }
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        if (f < FW) {
+      for (int f = 0; f < FW; ++f) {
+        {
           const int col = (wf * FW + f) * 16 + lr;
           const b8 bh = *(const b8*)(thi + col * RS + k0 + 8 * lk);
           const b8 bl = *(const b8*)(tlo + col * RS + k0 + 8 * lk);
@@ -252,8 +274,8 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
       }
     }
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if (f < FW) {
+    for (int f = 0; f < FW; ++f) {
+      {
         const int cf = (wf * FW + f) * 16;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -300,17 +322,25 @@ size_t mixed_lds_bytes(int prec, int npad) {
   return (size_t)2 * MT_COLS * (kpad + BF_PAD) * 2 + MT_COLS * sizeof(double);
 }
 
-hipError_t set_mixed_kernel_attributes() {
+template <int NMAT, bool INNER>
+static hipError_t set_mixed_attr() {
   const int max_lds = 160 * 1024;
-  const void* ks[] = {(const void*)k_contract_f32<1, true>,  (const void*)k_contract_f32<2, true>,
-                      (const void*)k_contract_f32<1, false>, (const void*)k_contract_f32<2, false>,
-                      (const void*)k_contract_bf3<1, true>,  (const void*)k_contract_bf3<2, true>,
-                      (const void*)k_contract_bf3<1, false>, (const void*)k_contract_bf3<2, false>};
+  const void* ks[] = {(const void*)k_contract_f32<NMAT, INNER, 1>, (const void*)k_contract_f32<NMAT, INNER, 2>,
+                      (const void*)k_contract_f32<NMAT, INNER, 4>, (const void*)k_contract_bf3<NMAT, INNER, 1>,
+                      (const void*)k_contract_bf3<NMAT, INNER, 2>, (const void*)k_contract_bf3<NMAT, INNER, 4>};
   for (const void* k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t set_mixed_kernel_attributes() {
+  hipError_t e = set_mixed_attr<1, true>();
+  if (e == hipSuccess) e = set_mixed_attr<2, true>();
+  if (e == hipSuccess) e = set_mixed_attr<1, false>();
+  if (e == hipSuccess) e = set_mixed_attr<2, false>();
+  return e;
 }
 
 hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskList& tl, const Bases& B,
@@ -324,27 +354,42 @@ hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskLi
   geometry(axis, n, &inner, &outer, &slab);
   dim3 grid((inner + MT_COLS - 1) / MT_COLS, outer, tl.n * js.n);
   const size_t lds = mixed_lds_bytes(prec, Npad);
+  const int T = Npad >> 4;
   if (prec == GRMHD_MIX_FP32) {
-#define L32(NM, IN)                                                                                    \
-  hipLaunchKernelGGL((k_contract_f32<NM, IN>), grid, dim3(256), lds, s, tl, B, op0.f32, op1.f32, N, Npad, \
+#define L32W(NM, IN, W)                                                                                  \
+  hipLaunchKernelGGL((k_contract_f32<NM, IN, W>), grid, dim3(256), lds, s, tl, B, op0.f32, op1.f32, N, Npad, \
                      inner, slab, P, js)
+#define L32(NM, IN)                        \
+  do {                                      \
+    if (T >= 4) L32W(NM, IN, 4);             \
+    else if (T >= 2) L32W(NM, IN, 2);        \
+    else L32W(NM, IN, 1);                    \
+  } while (0)
     if (axis == 0) {
       if (nmat == 1) L32(1, true); else L32(2, true);
     } else {
       if (nmat == 1) L32(1, false); else L32(2, false);
     }
 #undef L32
+#undef L32W
   } else if (prec == GRMHD_MIX_BF16X3) {
     const int Kpad = round_up(Npad, 32);
-#define LBF(NM, IN)                                                                                     \
-  hipLaunchKernelGGL((k_contract_bf3<NM, IN>), grid, dim3(256), lds, s, tl, B, op0.bhi, op0.blo, op1.bhi, \
+#define LBFW(NM, IN, W)                                                                                  \
+  hipLaunchKernelGGL((k_contract_bf3<NM, IN, W>), grid, dim3(256), lds, s, tl, B, op0.bhi, op0.blo, op1.bhi, \
                      op1.blo, N, Npad, Kpad, inner, slab, P, js)
+#define LBF(NM, IN)                        \
+  do {                                      \
+    if (T >= 4) LBFW(NM, IN, 4);             \
+    else if (T >= 2) LBFW(NM, IN, 2);        \
+    else LBFW(NM, IN, 1);                    \
+  } while (0)
     if (axis == 0) {
       if (nmat == 1) LBF(1, true); else LBF(2, true);
     } else {
       if (nmat == 1) LBF(1, false); else LBF(2, false);
     }
 #undef LBF
+#undef LBFW
   } else {
     return hipErrorInvalidValue;
   }

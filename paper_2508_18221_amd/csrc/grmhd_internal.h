@@ -136,8 +136,9 @@ hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskLi
                                  const MixedOps& op0, const MixedOps& op1, const int n[3],
                                  const int npad[3], long long P, const JobSet& js, hipStream_t s);
 hipError_t set_mixed_kernel_attributes();
+// floors: rho floor at the nr radial nodes, then the p floor
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
-                           const double* rnode, const PointParams& pp, const JobSet& js, hipStream_t s);
+                           const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s);
 // mode 0: out = L(U_s); 1..4: classic RK4 stage s.  der: derivative arrays
 // (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,

@@ -90,24 +90,26 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
   double lo = 0.0, hi = G * Ec + B2 + 1e-300;
   // residual f and derivative; returns false where v^2 >= 1 (Z below range)
   auto resid = [&](double Z, double& f, double& fp) -> bool {
-    const double a = Z + B2;
-    const double Z2 = Z * Z, a2 = a * a;
-    const double v2 = (Z2 * S2 + (2.0 * Z + B2) * BS2) / (Z2 * a2);
+    const double iZ = 1.0 / Z, ia = 1.0 / (Z + B2);
+    const double iZ2 = iZ * iZ, ia2 = ia * ia;
+    const double v2 = (S2 + (2.0 * Z + B2) * BS2 * iZ2) * ia2;
     if (!(v2 < 1.0) || !(Z > 0.0)) return false;
     const double iw2 = 1.0 - v2, sq = sqrt(iw2);
-    const double dv2 = -2.0 * S2 / (a2 * a) - 2.0 * BS2 * (3.0 * Z2 + 3.0 * Z * B2 + B2 * B2) / (Z2 * Z * a2 * a);
+    const double dv2 = -2.0 * ia2 * ia * (S2 + BS2 * (3.0 * Z * Z + 3.0 * Z * B2 + B2 * B2) * iZ2 * iZ);
     const double p = gf * (Z * iw2 - Dc * sq);
-    const double dp = gf * (iw2 - Z * dv2 + Dc * dv2 / (2.0 * sq));
-    f = Z + B2 - p - 0.5 * B2 * iw2 - 0.5 * BS2 / Z2 - Ec;
-    fp = 1.0 - dp + 0.5 * B2 * dv2 + BS2 / (Z2 * Z);
+    const double dp = gf * (iw2 - Z * dv2 + 0.5 * Dc * dv2 / sq);
+    f = Z + B2 - p - 0.5 * B2 * iw2 - 0.5 * BS2 * iZ2 - Ec;
+    fp = 1.0 - dp + 0.5 * B2 * dv2 + BS2 * iZ2 * iZ;
     return true;
   };
   double f, fp;
-  for (int w = 0; w < 8; ++w) {  // make sure the upper end has f >= 0
-    if (resid(hi, f, fp) && f >= 0.0) break;
+  bool upper = false;
+  for (int w = 0; w <= 8; ++w) {  // make sure the upper end has f >= 0 (up to 8 doublings)
+    upper = resid(hi, f, fp) && f >= 0.0;
+    if (upper || w == 8) break;
     hi *= 2.0;
   }
-  if (!(resid(hi, f, fp) && f >= 0.0)) bad = true;
+  if (!upper) bad = true;
   double Z = (zguess > lo && zguess < hi) ? zguess : 0.5 * (lo + hi);
   if (!bad) {
     for (int it = 0; it < 200; ++it) {
@@ -167,10 +169,6 @@ __device__ __forceinline__ Mag magnetic(const double* v, const double* B, const 
   for (int i = 0; i < 3; ++i) m.bl[i] = Bl[i] / m.W + m.W * Bv * m.vl[i];
   m.b2 = B2 / (m.W * m.W) + Bv * Bv;
   return m;
-}
-
-__device__ __forceinline__ double rnode_floor(const double* rn, int j, double scale, double ex) {
-  return scale * pow(rn[j], ex);
 }
 
 // Conformal Christoffels from dgt[a][s] = d_a gt_s:
@@ -273,11 +271,11 @@ constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1;
 }  // namespace
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_c2p_flux(const double* __restrict__ U,
                                                   double* __restrict__ prim,
                                                   double* __restrict__ fail,
                                                   double* __restrict__ flux,
-                                                  const double* __restrict__ rnode, PointParams pp,
+                                                  const double* __restrict__ floors, PointParams pp,
                                                   JobSet js) {
   const long long P = pp.P;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -287,7 +285,7 @@ __global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
     U = shift_ptr(U, jd);
     prim = shift_ptr(prim, jd);
     fail = shift_ptr(fail, jd);
-    rnode = shift_ptr(rnode, jd);
+    floors = shift_ptr(floors, jd);
     if (flux != nullptr) flux = shift_ptr(flux, jd);
   }
   const int j = (int)(idx % pp.nr);
@@ -298,9 +296,9 @@ __global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
   for (int s = 0; s < 6; ++s) gt.m[s] = LD(1 + s);
   const double alpha = LD(17);
   double beta[3] = {LD(18), LD(19), LD(20)};
-  const double e4 = exp(4.0 * phi);
+  const double e2 = exp(2.0 * phi), e4 = e2 * e2;
   const double detgt = det_sym(gt);
-  const double sqrtg = exp(6.0 * phi) * sqrt(detgt);
+  const double sqrtg = e4 * e2 * sqrt(detgt);
   Sym gam;
 #pragma unroll
   for (int s = 0; s < 6; ++s) gam.m[s] = e4 * gt.m[s];
@@ -321,8 +319,7 @@ __global__ __launch_bounds__(256) void k_c2p_flux(const double* __restrict__ U,
     if (rg > 0.0 && pg > 0.0 && v2 < 1.0)
       zg = (rg + pg * pp.gamma_ad / (pp.gamma_ad - 1.0)) / (1.0 - v2);
   }
-  const double rho_fl = rnode_floor(rnode, j, pp.rho_floor, -1.5);
-  const double p_fl = rnode_floor(rnode, j, pp.p_floor, -2.5);
+  const double rho_fl = floors[j], p_fl = floors[pp.nr + j];
   C2POut c = con2prim(D, S, tau, B, gam, gamu, pp.gamma_ad, rho_fl, p_fl, zg);
   prim[idx] = c.rho;
   prim[(size_t)P + idx] = c.p;
@@ -802,9 +799,9 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
 static inline unsigned nblk(long long P) { return (unsigned)((P + 255) / 256); }
 
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
-                           const double* rnode, const PointParams& pp, const JobSet& js, hipStream_t s) {
+                           const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s) {
   if (js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, prim, fail, flux, rnode, pp, js);
+  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, prim, fail, flux, floors, pp, js);
   return hipGetLastError();
 }
 
