@@ -42,7 +42,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct Layout {
   size_t P;
-  size_t res_fields, mats[3][3], floors, wr, wth, partials, res_total;
+  size_t res_fields, mats[3][3], fmat[3][3], gr, floors, wr, wth, partials, res_total;
   size_t m32[3][2], mhi[3][2], mlo[3][2];  // reduced-precision operators (D1, D2)
   size_t scr_total;
 };
@@ -84,6 +84,15 @@ Layout layout(const grmhd_grid& g) {
       off += align256(np * kp * 2);
     }
   }
+  for (int a = 0; a < 3; ++a) {  // folded operators (even N only)
+    const size_t hp = (size_t)round_up(n[a] / 2, 16);
+    for (int o = 0; o < 3; ++o) {
+      L.fmat[a][o] = off;
+      if (n[a] % 2 == 0) off += align256(2 * hp * hp * sizeof(double));
+    }
+  }
+  L.gr = off;  // radial row scales of the folded operators
+  off += align256((size_t)3 * g.nr * sizeof(double));
   L.floors = off;  // rho floor then p floor at each radial node
   off += align256((size_t)2 * g.nr * sizeof(double));
   L.wr = off;
@@ -111,6 +120,8 @@ struct grmhd_ctx {
   int device;
   double *U, *K0, *prim, *fail;
   const double* mats[3][3];
+  FoldOp fop[3][3];
+  const double* gr;
   MixedOps mops[3][2];
   double *floors, *wr, *wth, *partials;
   std::vector<double> floor_host;
@@ -149,8 +160,17 @@ struct Recorder {
     if (rec) HIPCHK((rec)->mark((k), c->stream));                  \
   } while (0)
 
+// Line contractions with operators op0 (and op1 when nmat = 2).  Even N uses
+// the folded kernel (half the MFMA work); it needs the first derivative
+// beside a radial second derivative, so a lone radial D2 takes the full form.
 hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const TaskList& tl,
                     const Bases& B, const JobSet& js) {
+  const bool pair_ok = nmat == 1 ? !(axis == 0 && op0 == OP_D2) : (op0 == OP_D1 && op1 == OP_D2);
+  if (c->ops.fold[axis] && pair_ok) {
+    const double* g10 = (axis == 0 && nmat == 2) ? c->gr + 2 * (size_t)c->grid.nr : nullptr;
+    return launch_contract_fold(axis, nmat, tl, B, c->fop[axis][op0], c->fop[axis][op1], g10, c->ops.n,
+                                c->ops.hpad, (long long)c->L.P, js, c->stream);
+  }
   return launch_contract(axis, nmat, tl, B, c->mats[axis][op0], c->mats[axis][op1], c->ops.n,
                          c->ops.npad, (long long)c->L.P, js, c->stream);
 }
@@ -375,6 +395,16 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
       c->mops[a][o].blo = (const __bf16*)(c->res + c->L.mlo[a][o]);
     }
   c->floors = (double*)(c->res + c->L.floors);
+  c->gr = (const double*)(c->res + c->L.gr);
+  for (int a = 0; a < 3; ++a)
+    for (int o = 0; o < 3; ++o) {
+      FoldOp& f = c->fop[a][o];
+      f.et = (const double*)(c->res + c->L.fmat[a][o]);
+      f.sigma = o == OP_D1 ? -1.0 : 1.0;
+      f.g = nullptr;
+      if (a == 0 && o == OP_D1) f.g = c->gr;
+      if (a == 0 && o == OP_D2) f.g = c->gr + grid->nr;
+    }
   c->wr = (double*)(c->res + c->L.wr);
   c->wth = (double*)(c->res + c->L.wth);
   c->partials = (double*)(c->res + c->L.partials);
@@ -394,6 +424,15 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->have_state = false;
   hipError_t e = set_kernel_attributes();
   if (e == hipSuccess) e = set_mixed_kernel_attributes();
+  if (e == hipSuccess) e = set_fold_kernel_attributes();
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    for (int o = 0; o < 3 && e == hipSuccess; ++o)
+      if (c->ops.fold[a])
+        e = hipMemcpyAsync((void*)c->fop[a][o].et, c->ops.fmat[a][o].data(),
+                           c->ops.fmat[a][o].size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && c->ops.fold[0])
+    e = hipMemcpyAsync((void*)c->gr, c->ops.gr.data(), c->ops.gr.size() * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream);
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
     for (int o = 0; o < 2 && e == hipSuccess; ++o) {
       e = hipMemcpyAsync((void*)c->mops[a][o].f32, c->ops.at32[a][o].data(), c->ops.at32[a][o].size() * 4,

@@ -261,4 +261,258 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
   return hipGetLastError();
 }
 
+
+// ===========================================================================
+// Even/odd folded contractions.
+//
+// Every line operator here is centro-symmetric, A[N-1-i][N-1-k] = sigma A[i][k]
+// (sigma = -1 for first derivatives, +1 for second derivatives and filters):
+// Chebyshev collocation on Gauss-Lobatto nodes, which are symmetric about the
+// interval centre, and Fourier circulants, whose entries depend on (i - k)
+// mod N only.  For even N and rows i < H = N/2, with s_k = u_k + u_{N-1-k},
+// d_k = u_k - u_{N-1-k} (k < H), E_ik = (A_ik + A_i,N-1-k)/2 and
+// O_ik = (A_ik - A_i,N-1-k)/2:
+//   (A u)_i = (E s)_i + (O d)_i,   (A u)_{N-1-i} = sigma ((E s)_i - (O d)_i),
+// two H x H products instead of one N x N: half the MFMA work.  The fold is
+// applied while the tile is staged in LDS (s rows on top, d rows below).
+//
+// Row scalings that break the symmetry (the radial log map) are applied in
+// the epilogue: out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u),
+// with A_0, A_1 the unmapped operators (g = null: unit scale, no coupling).
+// F0, F1: E^T (Hpad x Hpad, AT[k][i] = E[i][k], zero padded) followed by O^T.
+template <int NMAT, bool INNER, int WI>
+__global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, const double* __restrict__ F0,
+                                                       const double* __restrict__ F1,
+                                                       const double* __restrict__ G0,
+                                                       const double* __restrict__ G1,
+                                                       const double* __restrict__ G10, double sig0,
+                                                       double sig1, int N, int Hpad, int inner, int slab,
+                                                       long long P, JobSet js) {
+  extern __shared__ double tile[];  // [2 Hpad][LDS_STRIDE]: s rows, then d rows
+  constexpr int KCF = NMAT > 1 ? 2 : 4;  // k-steps of operator fragments per chunk
+  const Task tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  F0 = shift_ptr(F0, jd);
+  F1 = shift_ptr(F1, jd);
+  if (G0 != nullptr) G0 = shift_ptr(G0, jd);
+  if (G1 != nullptr) G1 = shift_ptr(G1, jd);
+  if (G10 != nullptr) G10 = shift_ptr(G10, jd);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int H = N >> 1;
+  const int c0 = blockIdx.x * TILE_COLS;
+  const size_t off = (size_t)blockIdx.y * (size_t)slab;
+  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
+  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
+  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + off;
+
+  // ---- stage and fold the input tile ----------------------------------------
+  constexpr int LOADS = 8;  // pairs per thread in flight
+  const int total = Hpad * TILE_COLS;
+  if (INNER) {
+    // 64 consecutive lines of N doubles; pair (k, N-1-k) of line `line`
+    const int ncols = min(TILE_COLS, inner - c0);
+    const double* __restrict__ s = src + (size_t)c0 * N;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double lo[LOADS], hi[LOADS];
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        const int line = e / Hpad, k = e - line * Hpad;
+        const bool ok = e < total && k < H && line < ncols;
+        lo[q] = ok ? s[(size_t)line * N + k] : 0.0;
+        hi[q] = ok ? s[(size_t)line * N + (N - 1 - k)] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) {
+          const int line = e / Hpad, k = e - line * Hpad;
+          tile[k * LDS_STRIDE + line] = lo[q] + hi[q];
+          tile[(Hpad + k) * LDS_STRIDE + line] = lo[q] - hi[q];
+        }
+      }
+    }
+  } else {
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double lo[LOADS], hi[LOADS];
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        const int k = e >> 6, c = e & 63;
+        const bool ok = e < total && k < H && c0 + c < inner;
+        lo[q] = ok ? src[(size_t)k * inner + c0 + c] : 0.0;
+        hi[q] = ok ? src[(size_t)(N - 1 - k) * inner + c0 + c] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) {
+          tile[(e >> 6) * LDS_STRIDE + (e & 63)] = lo[q] + hi[q];
+          tile[(Hpad + (e >> 6)) * LDS_STRIDE + (e & 63)] = lo[q] - hi[q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- MFMA: (E s) and (O d) for the H output rows of each pair --------------
+  constexpr int FW = WI;
+  const int T = Hpad >> 4;
+  const int wi = wave % WI, wf = wave / WI;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nks = Hpad >> 2;  // a multiple of 4, hence of KCF
+  const size_t hh = (size_t)Hpad * Hpad;
+  for (int it = wi; it < T; it += WI) {
+    d4 acc[NMAT][2][FW];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int f = 0; f < FW; ++f) acc[m][h][f] = d4{0.0, 0.0, 0.0, 0.0};
+    const double* __restrict__ ap[NMAT];
+    ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
+    if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
+    const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
+    double a[NMAT][2][KCF];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < KCF; ++q) a[m][h][q] = ap[m][h * hh + (size_t)(4 * q) * Hpad];
+    for (int kc = 0; kc < nks; kc += KCF) {
+      const int kn = (kc + KCF < nks) ? kc + KCF : kc;  // last chunk: in-bounds dummy prefetch
+      double an[NMAT][2][KCF];
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < KCF; ++q) an[m][h][q] = ap[m][h * hh + (size_t)(4 * (kn + q)) * Hpad];
+#pragma unroll
+      for (int q = 0; q < KCF; ++q) {
+        double b[2][FW];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * LDS_STRIDE + f * 16];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int f = 0; f < FW; ++f)
+#pragma unroll
+            for (int m = 0; m < NMAT; ++m) {
+              if (INNER) acc[m][h][f] = mfma_f64(b[h][f], a[m][h][q], acc[m][h][f]);
+              else acc[m][h][f] = mfma_f64(a[m][h][q], b[h][f], acc[m][h][f]);
+            }
+      }
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < KCF; ++q) a[m][h][q] = an[m][h][q];
+    }
+    // ---- unfold, scale, store ----------------------------------------------
+#pragma unroll
+    for (int f = 0; f < FW; ++f) {
+      const int cf = (wf * FW + f) * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = lk + 4 * v;  // D row within the 16x16 block
+        int i, col;
+        if (INNER) {
+          col = c0 + cf + row;
+          i = it * 16 + lr;
+        } else {
+          i = it * 16 + row;
+          col = c0 + cf + lr;
+        }
+        if (i < H && col < inner) {
+          const int im = N - 1 - i;
+          const double e0 = acc[0][0][f][v], o0 = acc[0][1][f][v];
+          const double y0 = e0 + o0, y0m = sig0 * (e0 - o0);
+          const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
+          const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
+          dst0[p] = G0 ? G0[i] * y0 : y0;
+          dst0[pm] = G0 ? G0[im] * y0m : y0m;
+          if (NMAT > 1) {
+            const double e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
+            const double y1 = e1 + o1, y1m = sig1 * (e1 - o1);
+            dst1[p] = (G1 ? G1[i] * y1 : y1) + (G10 ? G10[i] * y0 : 0.0);
+            dst1[pm] = (G1 ? G1[im] * y1m : y1m) + (G10 ? G10[im] * y0m : 0.0);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NMAT, bool INNER, int WI>
+static hipError_t set_fold_attr() {
+  const int max_lds = 256 * LDS_STRIDE * (int)sizeof(double);  // 2 Hpad <= 256
+  return hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+hipError_t set_fold_kernel_attributes() {
+  hipError_t e = hipSuccess;
+#define FA(NM, IN)                                          \
+  if (e == hipSuccess) e = set_fold_attr<NM, IN, 1>();      \
+  if (e == hipSuccess) e = set_fold_attr<NM, IN, 2>();      \
+  if (e == hipSuccess) e = set_fold_attr<NM, IN, 4>();
+  FA(1, true)
+  FA(2, true)
+  FA(1, false)
+  FA(2, false)
+#undef FA
+  return e;
+}
+
+hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
+                                const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
+                                long long P, const JobSet& js, hipStream_t s) {
+  if (tl.n <= 0) return hipSuccess;
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
+    return hipErrorInvalidValue;
+  const int N = n[axis], Hpad = hpad[axis];
+  if ((N & 1) || Hpad < N / 2 || (Hpad & 15) || 2 * Hpad > 256) return hipErrorInvalidValue;
+  int inner, slab, outer;
+  if (axis == 0) {
+    inner = n[1] * n[2];
+    outer = 1;
+    slab = 0;
+  } else if (axis == 1) {
+    inner = n[0];
+    outer = n[2];
+    slab = n[1] * n[0];
+  } else {
+    inner = n[0] * n[1];
+    outer = 1;
+    slab = 0;
+  }
+  dim3 grid((inner + TILE_COLS - 1) / TILE_COLS, outer, tl.n * js.n);
+  const size_t lds = (size_t)2 * Hpad * LDS_STRIDE * sizeof(double);
+  const int T = Hpad >> 4;
+#define LF(NM, IN, W)                                                                                     \
+  hipLaunchKernelGGL((k_contract_fold<NM, IN, W>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, op0.g, \
+                     op1.g, g10, op0.sigma, op1.sigma, N, Hpad, inner, slab, P, js)
+#define LFW(NM, IN)                 \
+  do {                              \
+    if (T >= 4) LF(NM, IN, 4);      \
+    else if (T >= 2) LF(NM, IN, 2); \
+    else LF(NM, IN, 1);             \
+  } while (0)
+  if (axis == 0) {
+    if (nmat == 1) LFW(1, true); else LFW(2, true);
+  } else {
+    if (nmat == 1) LFW(1, false); else LFW(2, false);
+  }
+#undef LFW
+#undef LF
+  return hipGetLastError();
+}
+
 }  // namespace grmhd

@@ -105,6 +105,14 @@ struct PointParams {
   double rho_floor, p_floor;
 };
 
+// A folded operator on the device (even N): E^T then O^T, each Hpad x Hpad,
+// its centro-symmetry sign, and an optional per-row scale (null: 1).
+struct FoldOp {
+  const double* et;
+  const double* g;
+  double sigma;
+};
+
 // Host-side operator set (built in long double, stored as double).
 struct Operators {
   int n[3];            // nr, nth, nph
@@ -117,6 +125,11 @@ struct Operators {
   std::vector<float> at32[3][2];
   std::vector<uint16_t> bhi[3][2], blo[3][2];  // bf16 bit patterns, [npad][kpad]
   int kpad[3];
+  // even/odd folded forms (even N): unmapped operators, E^T then O^T, [axis][op]
+  bool fold[3];
+  int hpad[3];                       // round_up(N/2, 16)
+  std::vector<double> fmat[3][3];
+  std::vector<double> gr;            // radial row scales g1, g2, g21 (nr each)
   double Lc, Lh, Tc, Th;
   double dt;
 };
@@ -136,6 +149,11 @@ hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskLi
                                  const MixedOps& op0, const MixedOps& op1, const int n[3],
                                  const int npad[3], long long P, const JobSet& js, hipStream_t s);
 hipError_t set_mixed_kernel_attributes();
+// Folded contraction (even N): out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u)
+hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
+                                const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
+                                long long P, const JobSet& js, hipStream_t s);
+hipError_t set_fold_kernel_attributes();
 // floors: rho floor at the nr radial nodes, then the p floor
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s);

@@ -170,6 +170,21 @@ void store_mixed(const std::vector<ld>& A, int n, int npad, int kpad, std::vecto
     }
 }
 
+// Even/odd fold of a centro-symmetric operator (even n): rows i < n/2,
+// E_ik = (A_ik + A_i,n-1-k)/2, O_ik = (A_ik - A_i,n-1-k)/2, stored transposed
+// and zero padded to hpad x hpad, E^T first.
+void store_fold(const std::vector<ld>& A, int n, int hpad, std::vector<double>* out) {
+  const int h = n / 2;
+  const size_t hh = (size_t)hpad * hpad;
+  out->assign(2 * hh, 0.0);
+  for (int i = 0; i < h; ++i)
+    for (int k = 0; k < h; ++k) {
+      const ld a = A[(size_t)i * n + k], b = A[(size_t)i * n + (n - 1 - k)];
+      (*out)[(size_t)k * hpad + i] = (double)(0.5L * (a + b));
+      (*out)[hh + (size_t)k * hpad + i] = (double)(0.5L * (a - b));
+    }
+}
+
 }  // namespace
 
 void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
@@ -178,6 +193,8 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     ops->n[a] = n[a];
     ops->npad[a] = round_up(n[a], 16);
     ops->kpad[a] = round_up(n[a], 32);
+    ops->fold[a] = (n[a] % 2 == 0);
+    ops->hpad[a] = round_up(n[a] / 2, 16);
   }
   // nodes, computed in double exactly as x_j = cos(j pi/(N-1)), r = exp(Lc + Lh x)
   ops->Lc = 0.5 * (log(g.r_in) + log(g.r_out));
@@ -211,7 +228,22 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     store_transposed(R2, nn, ops->npad[0], &ops->at[0][OP_D2]);
     store_mixed(R1, nn, ops->npad[0], ops->kpad[0], &ops->at32[0][0], &ops->bhi[0][0], &ops->blo[0][0]);
     store_mixed(R2, nn, ops->npad[0], ops->kpad[0], &ops->at32[0][1], &ops->bhi[0][1], &ops->blo[0][1]);
-    store_transposed(cheb_filter(nn, g.filt_alpha, g.filt_order), nn, ops->npad[0], &ops->at[0][OP_FILT]);
+    const std::vector<ld> Fr = cheb_filter(nn, g.filt_alpha, g.filt_order);
+    store_transposed(Fr, nn, ops->npad[0], &ops->at[0][OP_FILT]);
+    if (ops->fold[0]) {
+      // folded forms act with the unmapped D1, D2; the map enters as row
+      // scales: R1 u = g1 . D1 u, R2 u = g2 . D2 u + g21 . D1 u
+      store_fold(D1, nn, ops->hpad[0], &ops->fmat[0][OP_D1]);
+      store_fold(D2, nn, ops->hpad[0], &ops->fmat[0][OP_D2]);
+      store_fold(Fr, nn, ops->hpad[0], &ops->fmat[0][OP_FILT]);
+      ops->gr.resize(3 * (size_t)nn);
+      for (int i = 0; i < nn; ++i) {
+        const ld ri = (ld)ops->r[i];
+        ops->gr[i] = (double)(1.0L / (ri * Lh));
+        ops->gr[nn + i] = (double)(1.0L / (ri * ri * Lh * Lh));
+        ops->gr[2 * nn + i] = (double)(-1.0L / (ri * ri * Lh));
+      }
+    }
   }
   // polar: affine map
   {
@@ -225,7 +257,13 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     store_transposed(D2, nn, ops->npad[1], &ops->at[1][OP_D2]);
     store_mixed(D1, nn, ops->npad[1], ops->kpad[1], &ops->at32[1][0], &ops->bhi[1][0], &ops->blo[1][0]);
     store_mixed(D2, nn, ops->npad[1], ops->kpad[1], &ops->at32[1][1], &ops->bhi[1][1], &ops->blo[1][1]);
-    store_transposed(cheb_filter(nn, g.filt_alpha, g.filt_order), nn, ops->npad[1], &ops->at[1][OP_FILT]);
+    const std::vector<ld> Ft = cheb_filter(nn, g.filt_alpha, g.filt_order);
+    store_transposed(Ft, nn, ops->npad[1], &ops->at[1][OP_FILT]);
+    if (ops->fold[1]) {
+      store_fold(D1, nn, ops->hpad[1], &ops->fmat[1][OP_D1]);
+      store_fold(D2, nn, ops->hpad[1], &ops->fmat[1][OP_D2]);
+      store_fold(Ft, nn, ops->hpad[1], &ops->fmat[1][OP_FILT]);
+    }
   }
   // azimuthal: Fourier
   {
@@ -235,7 +273,13 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     store_transposed(F2, nn, ops->npad[2], &ops->at[2][OP_D2]);
     store_mixed(F1, nn, ops->npad[2], ops->kpad[2], &ops->at32[2][0], &ops->bhi[2][0], &ops->blo[2][0]);
     store_mixed(F2, nn, ops->npad[2], ops->kpad[2], &ops->at32[2][1], &ops->bhi[2][1], &ops->blo[2][1]);
-    store_transposed(fourier_op(nn, 3, g.filt_alpha, g.filt_order), nn, ops->npad[2], &ops->at[2][OP_FILT]);
+    const std::vector<ld> Fp = fourier_op(nn, 3, g.filt_alpha, g.filt_order);
+    store_transposed(Fp, nn, ops->npad[2], &ops->at[2][OP_FILT]);
+    if (ops->fold[2]) {
+      store_fold(F1, nn, ops->hpad[2], &ops->fmat[2][OP_D1]);
+      store_fold(F2, nn, ops->hpad[2], &ops->fmat[2][OP_D2]);
+      store_fold(Fp, nn, ops->hpad[2], &ops->fmat[2][OP_FILT]);
+    }
   }
   // quadrature weights for dr and dtheta
   {
