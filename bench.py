@@ -122,6 +122,39 @@ def mixed_forms(w, K, fp64_rate, Solver, make_grid, make_phys, torch):
     return out
 
 
+def traffic_probe(w, torch, Solver, make_grid, make_phys):
+    """Workload for the HBM traffic counters (run under rocprofv3 --pmc): one
+    plain device copy of 512 MiB (the counters' scale reference: 512 MiB read,
+    512 MiB written) followed by one FP64 RK4 step of the workload."""
+    n = 64 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]))
+    s.init_state()
+    s.step(1)
+    torch.cuda.synchronize()
+    s.close()
+    print(json.dumps({"traffic_probe": True, "copy_bytes_each_way": n * 8, "steps": 1}), flush=True)
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch of `kernel` measured with the FETCH_SIZE and
+    WRITE_SIZE counters (profiles/), reported only while the kernel source is
+    the one that was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_ks_michel_64x64x128.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2508_18221_amd", "csrc", rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +166,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-t-scale", type=float, default=1e-3)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one 512 MiB copy + one RK4 step, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -146,6 +181,9 @@ def main():
     import torch
     from paper_2508_18221_amd import Solver, make_grid, make_phys
     torch.cuda.set_device(0)
+    if args.traffic_probe:
+        traffic_probe(w, torch, Solver, make_grid, make_phys)
+        return
     s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]))
     g = w["grid"]
     P = g["nr"] * g["nth"] * g["nph"]
@@ -169,6 +207,7 @@ def main():
     per_step = {k: ms * cnt / args.profile_steps for k, (ms, cnt) in prof.items()}
     dom = max(per_step, key=per_step.get)
     rl = roofline(dom, prof[dom][0], P, costs)
+    rl["traffic"] = traffic_record(dom)
     kernels = {k: {"avg_ms": round(ms, 5), "launches_per_step": cnt // args.profile_steps,
                    "GB_per_s": round(costs[k][0] * P / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                    "TFLOP_per_s": round(costs[k][1] * P / (ms * 1e-3) / 1e12, 2) if ms > 0 else None}
