@@ -1,0 +1,67 @@
+"""Writes ks_michel_64x64x128_10steps.json: the oracle's state after 10 RK4
+steps (CFL 0.25, filter on) of the 64x64x128 Kerr-Schild a = 0.5 + magnetised
+Michel workload, at a fixed set of sampled grid points.
+
+Calls only the oracle and the seeded workload definition.  Run from the
+repository root (takes tens of minutes of CPU):
+
+    python tests/golden/make_ks_michel_64x64x128_samples.py
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+from oracle import evolve, spectral  # noqa: E402
+
+NAME = "ks_michel_64x64x128"
+STEPS = 10
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{NAME}_{STEPS}steps.json")
+
+
+def sample_points(nph, nth, nr, seed=7, n_random=256):
+    """(phi, theta, r) indices: seeded uniform interior points plus points on
+    and next to every boundary (r_out j = 0, r_in j = nr - 1, theta ends)."""
+    rng = np.random.default_rng(seed)
+    pts = set()
+    while len(pts) < n_random:
+        pts.add((int(rng.integers(nph)), int(rng.integers(nth)), int(rng.integers(nr))))
+    for j in (0, 1, nr // 2, nr - 2, nr - 1):
+        for k in (0, 1, nth // 2, nth - 2, nth - 1):
+            for l in (0, nph // 4, nph // 2 + 1):
+                pts.add((l, k, j))
+    return sorted(pts)
+
+
+def main():
+    w = workloads.WORKLOADS[NAME]
+    ga, pk, ik = workloads.oracle_kwargs(w)
+    g = spectral.Grid(*ga)
+    pb = evolve.Problem(g, **pk)
+    U0, K0, _ = evolve.initial_state(g, pb, **ik)
+    dt = pb.dt()
+    t0 = time.time()
+    U = U0
+    for n in range(STEPS):
+        U = pb.step(U, K0, dt)
+        print(f"step {n + 1}/{STEPS}  {time.time() - t0:.0f} s", flush=True)
+    pts = sample_points(*U.shape[1:])
+    idx = tuple(np.array(pts).T)
+    vals = U[(slice(None),) + idx].T  # (npoints, 32)
+    with open(OUT, "w") as f:
+        json.dump({"workload": NAME, "steps": STEPS, "dt": dt, "shape": list(U.shape),
+                   "points": pts, "values": [[float.hex(float(v)) for v in row] for row in vals],
+                   "field_norms_full": [float(np.sqrt(np.sum(U[q] ** 2))) for q in range(U.shape[0])]},
+                  f, separators=(",", ":"))
+    print(f"wrote {OUT}: {len(pts)} points")
+
+
+if __name__ == "__main__":
+    main()
