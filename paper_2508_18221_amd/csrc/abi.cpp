@@ -42,7 +42,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct Layout {
   size_t P;
-  size_t res_fields, mats[3][3], fmat[3][3], gr, floors, wr, wth, partials, res_total;
+  size_t res_fields, mats[3][3], fmat[3][3], fm32[3][2], gr, floors, wr, wth, partials, res_total;
   size_t m32[3][2], mhi[3][2], mlo[3][2];  // reduced-precision operators (D1, D2)
   size_t scr_total;
 };
@@ -91,6 +91,13 @@ Layout layout(const grmhd_grid& g) {
       if (n[a] % 2 == 0) off += align256(2 * hp * hp * sizeof(double));
     }
   }
+  for (int a = 0; a < 3; ++a) {  // FP32 folded D1, D2 (even N only)
+    const size_t hp = (size_t)round_up(n[a] / 2, 16);
+    for (int o = 0; o < 2; ++o) {
+      L.fm32[a][o] = off;
+      if (n[a] % 2 == 0) off += align256(2 * hp * hp * sizeof(float));
+    }
+  }
   L.gr = off;  // radial row scales of the folded operators
   off += align256((size_t)3 * g.nr * sizeof(double));
   L.floors = off;  // rho floor then p floor at each radial node
@@ -121,6 +128,7 @@ struct grmhd_ctx {
   double *U, *K0, *prim, *fail;
   const double* mats[3][3];
   FoldOp fop[3][3];
+  FoldOp32 fop32[3][2];
   const double* gr;
   MixedOps mops[3][2];
   double *floors, *wr, *wth, *partials;
@@ -218,6 +226,16 @@ int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* re
       for (int s = 0; s < ND2; ++s) addm(t1, 1, 21 + D2_FIELD[s], 1, 1, omx + 22 + s);
     }
     for (int v = 0; v < 8; ++v) addm(t1, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
+    if (c->prec == GRMHD_MIX_FP32 && c->ops.fold[a]) {  // folded FP32 form
+      const double* g10 = a == 0 ? c->gr + 2 * (size_t)c->grid.nr : nullptr;
+      HIPCHK(launch_contract_f32_fold(a, 2, t2, B, c->fop32[a][0], c->fop32[a][1], g10, c->ops.n, c->ops.hpad,
+                                      (long long)c->L.P, js, c->stream));
+      MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
+      HIPCHK(launch_contract_f32_fold(a, 1, t1, B, c->fop32[a][0], c->fop32[a][0], nullptr, c->ops.n,
+                                      c->ops.hpad, (long long)c->L.P, js, c->stream));
+      MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
+      continue;
+    }
     HIPCHK(launch_contract_mixed(c->prec, a, 2, t2, B, c->mops[a][0], c->mops[a][1], c->ops.n, c->ops.npad,
                                  (long long)c->L.P, js, c->stream));
     MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
@@ -404,6 +422,12 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
       f.g = nullptr;
       if (a == 0 && o == OP_D1) f.g = c->gr;
       if (a == 0 && o == OP_D2) f.g = c->gr + grid->nr;
+      if (o < 2) {
+        FoldOp32& f32 = c->fop32[a][o];
+        f32.et = (const float*)(c->res + c->L.fm32[a][o]);
+        f32.g = f.g;
+        f32.sigma = f.sigma;
+      }
     }
   c->wr = (double*)(c->res + c->L.wr);
   c->wth = (double*)(c->res + c->L.wth);
@@ -430,6 +454,11 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
       if (c->ops.fold[a])
         e = hipMemcpyAsync((void*)c->fop[a][o].et, c->ops.fmat[a][o].data(),
                            c->ops.fmat[a][o].size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    for (int o = 0; o < 2 && e == hipSuccess; ++o)
+      if (c->ops.fold[a])
+        e = hipMemcpyAsync((void*)c->fop32[a][o].et, c->ops.fmat32[a][o].data(),
+                           c->ops.fmat32[a][o].size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess && c->ops.fold[0])
     e = hipMemcpyAsync((void*)c->gr, c->ops.gr.data(), c->ops.gr.size() * sizeof(double),
                        hipMemcpyHostToDevice, c->stream);

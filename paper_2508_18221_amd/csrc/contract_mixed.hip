@@ -29,6 +29,12 @@ constexpr int F32_STRIDE = 80;   // floats per tile row: 4 rows cover 64 banks o
 constexpr int BF_PAD = 8;        // bf16 padding per tile row (rows 4 banks apart)
 constexpr int KC32 = 4;          // FP32 form: k-steps (of 4) of operator fragments per chunk
 
+// Start of the task's input field (FP32 or FP64 storage).
+template <class T>
+__device__ __forceinline__ const T* field_base(const MixedTask& t, const Bases& B, long long P, long long jd) {
+  return (const T*)shift_ptr(B.b[t.src_sel], jd) + (size_t)t.src * (size_t)P;
+}
+
 __device__ __forceinline__ double load_in(const MixedTask& t, const Bases& B, long long P,
                                           long long jd, size_t off) {
   if (t.src_f32) return (double)(((const float*)shift_ptr(B.b[t.src_sel], jd)) + (size_t)t.src * (size_t)P)[off];
@@ -62,28 +68,33 @@ __global__ __launch_bounds__(256) void k_contract_f32(MixedTaskList tl, Bases B,
     shift[threadIdx.x] =
         threadIdx.x < ncols ? load_in(tk, B, P, jd, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
   __syncthreads();
-  constexpr int LOADS = 16;
-  const int total = Npad * MT_COLS;
-  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
-    double v[LOADS];
+  // the input precision is uniform per task: one straight-line fill per type
+  auto fill = [&](const auto* __restrict__ fsrc) {
+    constexpr int LOADS = 16;
+    const int total = Npad * MT_COLS;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double v[LOADS];
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      const int e = e0 + q * 256;
-      int k, c;
-      if (INNER) { c = e / Npad; k = e - c * Npad; } else { k = e >> 6; c = e & 63; }
-      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, jd, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
-                                               : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      const int e = e0 + q * 256;
-      if (e < total) {
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
         int k, c;
         if (INNER) { c = e / Npad; k = e - c * Npad; } else { k = e >> 6; c = e & 63; }
-        tf[k * F32_STRIDE + c] = (float)v[q];
+        v[q] = (e < total && k < N && c < ncols) ? (double)fsrc[elem<INNER>(k, c, c0, N, inner, soff)] - shift[c]
+                                                 : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) {
+          int k, c;
+          if (INNER) { c = e / Npad; k = e - c * Npad; } else { k = e >> 6; c = e & 63; }
+          tf[k * F32_STRIDE + c] = (float)v[q];
+        }
       }
     }
-  }
+  };
+  if (tk.src_f32) fill(field_base<float>(tk, B, P, jd));
+  else fill(field_base<double>(tk, B, P, jd));
   __syncthreads();
   const int T = Npad >> 4;
   constexpr int FW = WI;  // 16-column fragments per wave; WI waves along the rows
@@ -198,31 +209,36 @@ __global__ __launch_bounds__(256) void k_contract_bf3(MixedTaskList tl, Bases B,
     shift[threadIdx.x] =
         threadIdx.x < ncols ? load_in(tk, B, P, jd, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
   __syncthreads();
-  constexpr int LOADS = 16;
-  const int total = Kpad * MT_COLS;
-  for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
-    double v[LOADS];
+  // the input precision is uniform per task: one straight-line fill per type
+  auto fill = [&](const auto* __restrict__ fsrc) {
+    constexpr int LOADS = 16;
+    const int total = Kpad * MT_COLS;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double v[LOADS];
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      const int e = e0 + q * 256;
-      int k, c;
-      if (INNER) { c = e / Kpad; k = e - c * Kpad; } else { k = e >> 6; c = e & 63; }
-      v[q] = (e < total && k < N && c < ncols) ? load_in(tk, B, P, jd, elem<INNER>(k, c, c0, N, inner, soff)) - shift[c]
-                                               : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      const int e = e0 + q * 256;
-      if (e < total) {
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
         int k, c;
         if (INNER) { c = e / Kpad; k = e - c * Kpad; } else { k = e >> 6; c = e & 63; }
-        const float x = (float)v[q];
-        const __bf16 h = (__bf16)x;
-        thi[c * RS + k] = h;
-        tlo[c * RS + k] = (__bf16)(x - (float)h);
+        v[q] = (e < total && k < N && c < ncols) ? (double)fsrc[elem<INNER>(k, c, c0, N, inner, soff)] - shift[c]
+                                                 : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) {
+          int k, c;
+          if (INNER) { c = e / Kpad; k = e - c * Kpad; } else { k = e >> 6; c = e & 63; }
+          const float x = (float)v[q];
+          const __bf16 h = (__bf16)x;
+          thi[c * RS + k] = h;
+          tlo[c * RS + k] = (__bf16)(x - (float)h);
+        }
       }
     }
-  }
+  };
+  if (tk.src_f32) fill(field_base<float>(tk, B, P, jd));
+  else fill(field_base<double>(tk, B, P, jd));
   __syncthreads();
   const int T = Npad >> 4;
   constexpr int FW = WI;  // 16-column fragments per wave; WI waves along the rows
@@ -322,6 +338,208 @@ size_t mixed_lds_bytes(int prec, int npad) {
   return (size_t)2 * MT_COLS * (kpad + BF_PAD) * 2 + MT_COLS * sizeof(double);
 }
 
+// ---------------------------------------------------------------------------
+// Folded FP32 form (even N): the even/odd split of the FP64 folded kernel
+// (centro-symmetric operators, two H x H products on s_k = u_k + u_{N-1-k}
+// and d_k = u_k - u_{N-1-k}).  The middle-node shift and the fold are done in
+// FP64; s and d are rounded to FP32 once, the products run on FP32 MFMA.
+// Row scales of the radial map are applied in the epilogue in FP64:
+// out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u).
+template <int NMAT, bool INNER, int WI>
+__global__ __launch_bounds__(256) void k_contract_f32_fold(MixedTaskList tl, Bases B, const float* __restrict__ F0,
+                                                           const float* __restrict__ F1,
+                                                           const double* __restrict__ G0,
+                                                           const double* __restrict__ G1,
+                                                           const double* __restrict__ G10, float sig0, float sig1,
+                                                           int N, int Hpad, int inner, int slab, long long P,
+                                                           JobSet js) {
+  extern __shared__ float tf[];  // [2 Hpad][F32_STRIDE]: s rows, d rows; then 64 doubles of line offsets
+  double* shift = (double*)(tf + (size_t)2 * Hpad * F32_STRIDE);
+  constexpr int KCF = NMAT > 1 ? 2 : 4;
+  const MixedTask tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  F0 = shift_ptr(F0, jd);
+  F1 = shift_ptr(F1, jd);
+  if (G0 != nullptr) G0 = shift_ptr(G0, jd);
+  if (G1 != nullptr) G1 = shift_ptr(G1, jd);
+  if (G10 != nullptr) G10 = shift_ptr(G10, jd);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int H = N >> 1;
+  const int c0 = blockIdx.x * MT_COLS;
+  const size_t soff = (size_t)blockIdx.y * (size_t)slab;
+  const int ncols = min(MT_COLS, inner - c0);
+  if (threadIdx.x < MT_COLS)
+    shift[threadIdx.x] =
+        threadIdx.x < ncols ? load_in(tk, B, P, jd, elem<INNER>(N / 2, threadIdx.x, c0, N, inner, soff)) : 0.0;
+  __syncthreads();
+  auto fill = [&](const auto* __restrict__ fsrc) {
+    constexpr int LOADS = 8;  // pairs per thread in flight
+    const int total = Hpad * MT_COLS;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
+      double lo[LOADS], hi[LOADS];
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        int k, c;
+        if (INNER) { c = e / Hpad; k = e - c * Hpad; } else { k = e >> 6; c = e & 63; }
+        const bool ok = e < total && k < H && c < ncols;
+        lo[q] = ok ? (double)fsrc[elem<INNER>(k, c, c0, N, inner, soff)] - shift[c] : 0.0;
+        hi[q] = ok ? (double)fsrc[elem<INNER>(N - 1 - k, c, c0, N, inner, soff)] - shift[c] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < LOADS; ++q) {
+        const int e = e0 + q * 256;
+        if (e < total) {
+          int k, c;
+          if (INNER) { c = e / Hpad; k = e - c * Hpad; } else { k = e >> 6; c = e & 63; }
+          tf[k * F32_STRIDE + c] = (float)(lo[q] + hi[q]);
+          tf[(Hpad + k) * F32_STRIDE + c] = (float)(lo[q] - hi[q]);
+        }
+      }
+    }
+  };
+  if (tk.src_f32) fill(field_base<float>(tk, B, P, jd));
+  else fill(field_base<double>(tk, B, P, jd));
+  __syncthreads();
+
+  constexpr int FW = WI;
+  const int T = Hpad >> 4;
+  const int wi = wave % WI, wf = wave / WI;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nks = Hpad >> 2;  // a multiple of 4, hence of KCF
+  const size_t hh = (size_t)Hpad * Hpad;
+  float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
+  float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
+  for (int it = wi; it < T; it += WI) {
+    f4 acc[NMAT][2][FW];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int f = 0; f < FW; ++f) acc[m][h][f] = f4{0.f, 0.f, 0.f, 0.f};
+    const float* __restrict__ ap[NMAT];
+    ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
+    if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
+    const float* tp = tf + lk * F32_STRIDE + wf * FW * 16 + lr;
+    float a[NMAT][2][KCF];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < KCF; ++q) a[m][h][q] = ap[m][h * hh + (size_t)(4 * q) * Hpad];
+    for (int kc = 0; kc < nks; kc += KCF) {
+      const int kn = (kc + KCF < nks) ? kc + KCF : kc;  // last chunk: in-bounds dummy prefetch
+      float an[NMAT][2][KCF];
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < KCF; ++q) an[m][h][q] = ap[m][h * hh + (size_t)(4 * (kn + q)) * Hpad];
+#pragma unroll
+      for (int q = 0; q < KCF; ++q) {
+        float b[2][FW];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * F32_STRIDE + f * 16];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int f = 0; f < FW; ++f)
+#pragma unroll
+            for (int m = 0; m < NMAT; ++m) {
+              if (INNER) acc[m][h][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[h][f], a[m][h][q], acc[m][h][f], 0, 0, 0);
+              else acc[m][h][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][h][q], b[h][f], acc[m][h][f], 0, 0, 0);
+            }
+      }
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < KCF; ++q) a[m][h][q] = an[m][h][q];
+    }
+#pragma unroll
+    for (int f = 0; f < FW; ++f) {
+      const int cf = (wf * FW + f) * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * lk + v;  // f32 accumulator row within the 16x16 block
+        int i, col;
+        if (INNER) {
+          col = c0 + cf + row;
+          i = it * 16 + lr;
+        } else {
+          i = it * 16 + row;
+          col = c0 + cf + lr;
+        }
+        if (i < H && col < inner) {
+          const int im = N - 1 - i;
+          const float e0 = acc[0][0][f][v], o0 = acc[0][1][f][v];
+          const float y0 = e0 + o0, y0m = sig0 * (e0 - o0);
+          const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
+          const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
+          dst0[p] = G0 ? (float)(G0[i] * (double)y0) : y0;
+          dst0[pm] = G0 ? (float)(G0[im] * (double)y0m) : y0m;
+          if (NMAT > 1) {
+            const float e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
+            const float y1 = e1 + o1, y1m = sig1 * (e1 - o1);
+            dst1[p] = (float)((G1 ? G1[i] * (double)y1 : (double)y1) + (G10 ? G10[i] * (double)y0 : 0.0));
+            dst1[pm] = (float)((G1 ? G1[im] * (double)y1m : (double)y1m) + (G10 ? G10[im] * (double)y0m : 0.0));
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NMAT, bool INNER>
+static hipError_t set_f32_fold_attr() {
+  const int max_lds = 160 * 1024;
+  const void* ks[] = {(const void*)k_contract_f32_fold<NMAT, INNER, 1>, (const void*)k_contract_f32_fold<NMAT, INNER, 2>,
+                      (const void*)k_contract_f32_fold<NMAT, INNER, 4>};
+  for (const void* k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl, const Bases& B,
+                                    const FoldOp32& op0, const FoldOp32& op1, const double* g10, const int n[3],
+                                    const int hpad[3], long long P, const JobSet& js, hipStream_t s) {
+  if (tl.n <= 0) return hipSuccess;
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
+    return hipErrorInvalidValue;
+  const int N = n[axis], Hpad = hpad[axis];
+  if ((N & 1) || Hpad < N / 2 || (Hpad & 15) || 2 * Hpad > 256) return hipErrorInvalidValue;
+  int inner, outer, slab;
+  geometry(axis, n, &inner, &outer, &slab);
+  dim3 grid((inner + MT_COLS - 1) / MT_COLS, outer, tl.n * js.n);
+  const size_t lds = (size_t)2 * Hpad * F32_STRIDE * sizeof(float) + MT_COLS * sizeof(double);
+  const int T = Hpad >> 4;
+#define LF(NM, IN, W)                                                                                        \
+  hipLaunchKernelGGL((k_contract_f32_fold<NM, IN, W>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, op0.g, \
+                     op1.g, g10, (float)op0.sigma, (float)op1.sigma, N, Hpad, inner, slab, P, js)
+#define LFW(NM, IN)                 \
+  do {                              \
+    if (T >= 4) LF(NM, IN, 4);      \
+    else if (T >= 2) LF(NM, IN, 2); \
+    else LF(NM, IN, 1);             \
+  } while (0)
+  if (axis == 0) {
+    if (nmat == 1) LFW(1, true); else LFW(2, true);
+  } else {
+    if (nmat == 1) LFW(1, false); else LFW(2, false);
+  }
+#undef LFW
+#undef LF
+  return hipGetLastError();
+}
+
 template <int NMAT, bool INNER>
 static hipError_t set_mixed_attr() {
   const int max_lds = 160 * 1024;
@@ -340,6 +558,10 @@ hipError_t set_mixed_kernel_attributes() {
   if (e == hipSuccess) e = set_mixed_attr<2, true>();
   if (e == hipSuccess) e = set_mixed_attr<1, false>();
   if (e == hipSuccess) e = set_mixed_attr<2, false>();
+  if (e == hipSuccess) e = set_f32_fold_attr<1, true>();
+  if (e == hipSuccess) e = set_f32_fold_attr<2, true>();
+  if (e == hipSuccess) e = set_f32_fold_attr<1, false>();
+  if (e == hipSuccess) e = set_f32_fold_attr<2, false>();
   return e;
 }
 

@@ -113,6 +113,14 @@ struct FoldOp {
   double sigma;
 };
 
+// FP32 folded operator (mixed-precision form): E^T then O^T in FP32, row
+// scale in FP64 (null: 1), sign.
+struct FoldOp32 {
+  const float* et;
+  const double* g;
+  double sigma;
+};
+
 // Host-side operator set (built in long double, stored as double).
 struct Operators {
   int n[3];            // nr, nth, nph
@@ -129,6 +137,7 @@ struct Operators {
   bool fold[3];
   int hpad[3];                       // round_up(N/2, 16)
   std::vector<double> fmat[3][3];
+  std::vector<float> fmat32[3][2];   // FP32 copies of the folded D1, D2
   std::vector<double> gr;            // radial row scales g1, g2, g21 (nr each)
   double Lc, Lh, Tc, Th;
   double dt;
@@ -154,6 +163,9 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
                                 const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
                                 long long P, const JobSet& js, hipStream_t s);
 hipError_t set_fold_kernel_attributes();
+hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl, const Bases& B,
+                                    const FoldOp32& op0, const FoldOp32& op1, const double* g10, const int n[3],
+                                    const int hpad[3], long long P, const JobSet& js, hipStream_t s);
 // floors: rho floor at the nr radial nodes, then the p floor
 hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s);

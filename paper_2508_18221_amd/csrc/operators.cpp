@@ -281,6 +281,13 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
       store_fold(Fp, nn, ops->hpad[2], &ops->fmat[2][OP_FILT]);
     }
   }
+  // FP32 copies of the folded derivative operators (mixed-precision form)
+  for (int a = 0; a < 3; ++a)
+    if (ops->fold[a])
+      for (int o = 0; o < 2; ++o) {
+        const std::vector<double>& src = ops->fmat[a][o];
+        ops->fmat32[a][o].assign(src.begin(), src.end());
+      }
   // quadrature weights for dr and dtheta
   {
     std::vector<ld> w = cc_weights(g.nr);
