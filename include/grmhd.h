@@ -85,6 +85,11 @@ typedef struct {
   int32_t filter_on;        /* 1: filter after every RK4 step                */
 } grmhd_grid;
 
+/* Initial-data kinds: magnetised Michel accretion (monopole field, density
+ * perturbation) or a Fishbone-Moncrief torus (constant u^t u_phi, one
+ * poloidal field loop, pressure perturbation). */
+enum { GRMHD_ID_MICHEL = 0, GRMHD_ID_TORUS = 1 };
+
 /* Physics and initial-data parameters. */
 typedef struct {
   double M, a;              /* black-hole mass and spin (Kerr-Schild)        */
@@ -98,6 +103,12 @@ typedef struct {
   double pert_amp;          /* rho -> rho (1 + pert_amp (2u - 1))            */
   uint64_t seed;            /* SplitMix64 seed of the perturbation           */
   double rho_floor, p_floor;/* atmosphere: rho_floor r^-1.5, p_floor r^-2.5  */
+  int32_t id_kind;          /* GRMHD_ID_MICHEL or GRMHD_ID_TORUS             */
+  double tor_r_in, tor_r_max;/* torus inner edge and pressure maximum (M)    */
+  double tor_rho_max;       /* torus density at the pressure maximum         */
+  double tor_atm;           /* atmosphere rho = tor_atm rho_max (r/r_max)^-1.5,
+                               at Eulerian rest on the torus isentrope       */
+  double tor_loop_cut;      /* A_phi = max(rho/rho_max - tor_loop_cut, 0)    */
 } grmhd_phys;
 
 /* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"). */

@@ -186,11 +186,19 @@ class Problem:
         return U
 
 
-def initial_state(grid, problem, r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, seed=1):
-    """Kerr-Schild BSSN data + magnetised Michel flow; returns (U, K0, matter)."""
-    from .initial_data import kerr_schild_bssn, michel_monopole
+def initial_state(grid, problem, r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, seed=1,
+                  id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-6,
+                  tor_loop_cut=0.2):
+    """Kerr-Schild BSSN data + magnetised Michel flow (id_kind "michel") or a
+    magnetised Fishbone-Moncrief torus ("torus"); returns (U, K0, matter)."""
+    from .initial_data import kerr_schild_bssn, michel_monopole, fm_torus
     f = kerr_schild_bssn(grid, problem.M, problem.a)
-    mat = michel_monopole(grid, f, problem.M, problem.a, problem.Gamma, r_c, rho_c, beta_min, pert_amp, seed)
+    if id_kind == "torus":
+        mat = fm_torus(grid, f, problem.M, problem.a, problem.Gamma, tor_r_in, tor_r_max, tor_rho_max,
+                       beta_min, pert_amp, seed, atm=tor_atm, a_cut=tor_loop_cut)
+    else:
+        mat = michel_monopole(grid, f, problem.M, problem.a, problem.Gamma, r_c, rho_c, beta_min, pert_amp,
+                              seed)
     U = pack(f, dict(sD=mat['sD'], sS=mat['sS'], stau=mat['stau'], sB=mat['sB']))
     return U, gauge_source_k0(grid, f), mat
 

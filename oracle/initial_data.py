@@ -188,3 +188,119 @@ def michel_monopole(grid, fields, M, a, Gamma, r_c, rho_c, beta_min, pert_amp, s
         rho = rho * (1.0 + pert_amp * (2.0 * u - 1.0))
     D, S, tau = prim_to_cons(rho, p, v, B, gam, Gamma)
     return dict(rho=rho, p=p, v=v, B=B, sD=sqrtg * D, sS=sqrtg * S, stau=sqrtg * tau, sB=sB, B0=B0)
+
+
+# ---- Fishbone-Moncrief torus ---------------------------------------------------
+#
+# Hydrostatic torus of constant ell = u^t u_phi around a Kerr hole (Fishbone &
+# Moncrief 1976), isentropic p = K rho^Gamma.  The velocity is purely
+# azimuthal, u = u^t (1, 0, 0, Omega); the components g_tt, g_tphi, g_phiphi
+# are the same in Boyer-Lindquist and Kerr-Schild coordinates and u^r = 0, so
+# u^t and u^phi carry over unchanged.
+#
+# Derivation used here (restated, not copied): with the ZAMO quantities
+# omega = -g_tphi/g_phiphi, alpha_Z^2 = omega^2 g_phiphi - g_tt and the
+# azimuthal speed V = sqrt(g_phiphi) (Omega - omega)/alpha_Z measured by the
+# ZAMO, ell = u^t u_phi = sqrt(g_phiphi) V / (alpha_Z (1 - V^2)), a quadratic
+# c V^2 + V - c = 0 in V with c = ell alpha_Z / sqrt(g_phiphi).  The Euler
+# equation of circular flow, d ln h = -d ln(-u_t) + Omega dl / (1 - Omega l)
+# with l = -u_phi/u_t, integrates at constant ell (l = ell/(1 + ell Omega)) to
+#   ln h = ln(1 + ell Omega) - ln(-u_t) - ell Omega + const,
+# the constant fixed by h = 1 at the inner edge (r_in, pi/2).  ell follows
+# from r_max: at the pressure maximum the flow is on the prograde circular
+# equatorial geodesic (Bardeen, Press & Teukolsky 1972), ell = u^t u_phi of
+# that orbit.
+
+class FMTorus:
+    def __init__(self, M, a, r_in, r_max, Gamma, rho_max):
+        self.M, self.a, self.r_in, self.r_max = M, a, r_in, r_max
+        self.Gamma, self.rho_max = Gamma, rho_max
+        self.ell = self.ell_circular(r_max)
+        self.lnh_in = 0.0
+        self.lnh_in = self.lnh(np.array(r_in), np.array(0.5 * np.pi))
+        h_max = np.exp(self.lnh(np.array(r_max), np.array(0.5 * np.pi)))
+        # rho_max = ((h - 1)(Gamma - 1)/(K Gamma))^(1/(Gamma - 1)) at the maximum
+        self.K = (h_max - 1.0) * (Gamma - 1.0) / (Gamma * rho_max ** (Gamma - 1.0))
+
+    def ell_circular(self, r):
+        """u^t u_phi of the prograde circular equatorial geodesic at r."""
+        M, a = self.M, self.a
+        sq = np.sqrt(r ** 1.5 - 3.0 * M * np.sqrt(r) + 2.0 * a * np.sqrt(M))
+        ut = (r ** 1.5 + a * np.sqrt(M)) / (r ** 0.75 * sq)
+        uphi_lo = np.sqrt(M) * (r * r - 2.0 * a * np.sqrt(M * r) + a * a) / (r ** 0.75 * sq)
+        return ut * uphi_lo
+
+    def velocity(self, r, th):
+        """u^t, u^phi (upper), Omega and u_t (lower) of the torus flow."""
+        g = ks.metric4(r, th, self.M, self.a)
+        gtt, gtp, gpp = g[0, 0], g[0, 3], g[3, 3]
+        omega = -gtp / gpp
+        alz = np.sqrt(omega * omega * gpp - gtt)
+        c = self.ell * alz / np.sqrt(gpp)
+        V = (np.sqrt(1.0 + 4.0 * c * c) - 1.0) / (2.0 * c)
+        ut = 1.0 / (alz * np.sqrt(1.0 - V * V))
+        Om = omega + alz * V / np.sqrt(gpp)
+        u_t = ut * (gtt + gtp * Om)
+        return ut, ut * Om, Om, u_t
+
+    def lnh(self, r, th):
+        _, _, Om, u_t = self.velocity(r, th)
+        return np.log(1.0 + self.ell * Om) - np.log(-u_t) - self.ell * Om - self.lnh_in
+
+    def density(self, r, th):
+        """rho of the torus (0 outside it: ln h <= 0 or r < r_in)."""
+        r, th = np.broadcast_arrays(np.asarray(r, dtype=float), np.asarray(th, dtype=float))
+        out = np.zeros(r.shape)
+        m = r >= self.r_in
+        lh = np.full(r.shape, -1.0)
+        lh[m] = self.lnh(r[m], th[m])
+        inside = lh > 0.0
+        hm1 = np.expm1(lh[inside])
+        out[inside] = (hm1 * (self.Gamma - 1.0) / (self.K * self.Gamma)) ** (1.0 / (self.Gamma - 1.0))
+        return out
+
+
+def fm_torus(grid, fields, M, a, Gamma, r_in, r_max, rho_max, beta_min, pert_amp, seed, atm=1e-6, a_cut=0.2):
+    """Magnetised Fishbone-Moncrief torus on the nodes (same return keys as
+    michel_monopole).
+
+    Readings (listed in the design doc): atmosphere rho = atm rho_max (r/r_max)^-3/2
+    at Eulerian rest on the same isentrope, rho = max(rho_torus, rho_atm);
+    one poloidal loop A_phi = max(rho_torus/rho_max - a_cut, 0) with the
+    densitised field sqrt(gamma) B^r = d_theta A_phi, sqrt(gamma) B^theta =
+    -d_r A_phi from the spectral derivatives (discrete div B = 0 because the
+    axis operators commute), scaled so that the minimum of 2p/b^2 over the
+    nodes where A_phi > 0 equals beta_min; pressure perturbation
+    p -> p (1 + A (2u - 1)) with the SplitMix64 stream of the density one."""
+    tor = FMTorus(M, a, r_in, r_max, Gamma, rho_max)
+    shape = grid.shape
+    R, TH = grid.R, grid.TH
+    rho_t = tor.density(R, TH)
+    rho_a = atm * rho_max * (R / r_max) ** -1.5
+    rho = np.maximum(rho_t, rho_a)
+    p = tor.K * rho ** Gamma
+    alpha, beta = fields['alpha'], fields['beta']
+    gam = np.exp(4.0 * fields['phi']) * fields['gt']
+    sqrtg = np.exp(6.0 * fields['phi']) * np.sqrt(det3(fields['gt']))
+    v = np.zeros((3,) + shape)
+    inside = rho_t > 0.0
+    ut, uph, _, _ = tor.velocity(R[inside], TH[inside])
+    W = alpha[inside] * ut
+    v[0][inside] = beta[0][inside] / alpha[inside]
+    v[1][inside] = beta[1][inside] / alpha[inside]
+    v[2][inside] = uph / W + beta[2][inside] / alpha[inside]
+    Aph = np.maximum(rho_t / rho_max - a_cut, 0.0)
+    sB = np.zeros((3,) + shape)
+    sB[0] = grid.d_th(Aph)
+    sB[1] = -grid.d_r(Aph)
+    _, _, _, b2 = magnetic(v, sB / sqrtg, gam)
+    loop = Aph > 0.0
+    B0 = np.sqrt(2.0 * np.min(p[loop] / b2[loop]) / beta_min)
+    sB *= B0
+    B = sB / sqrtg
+    if pert_amp != 0.0:
+        u = uniform01(seed, grid.npts).reshape(shape)
+        p = p * (1.0 + pert_amp * (2.0 * u - 1.0))
+    D, S, tau = prim_to_cons(rho, p, v, B, gam, Gamma)
+    return dict(rho=rho, p=p, v=v, B=B, sD=sqrtg * D, sS=sqrtg * S, stau=sqrtg * tau, sB=sB, B0=B0,
+                K=tor.K, ell=tor.ell)

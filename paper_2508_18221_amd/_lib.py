@@ -28,7 +28,9 @@ class Phys(ctypes.Structure):
                 ("cowling", ctypes.c_int32), ("gauge_k0", ctypes.c_int32),
                 ("r_c", ctypes.c_double), ("rho_c", ctypes.c_double), ("beta_min", ctypes.c_double),
                 ("pert_amp", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double)]
+                ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
+                ("id_kind", ctypes.c_int32), ("tor_r_in", ctypes.c_double), ("tor_r_max", ctypes.c_double),
+                ("tor_rho_max", ctypes.c_double), ("tor_atm", ctypes.c_double), ("tor_loop_cut", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):

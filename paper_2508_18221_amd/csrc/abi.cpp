@@ -378,6 +378,12 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
     return fail(GRMHD_E_ARG, "device buffers must be 256-byte aligned");
   if (!(phys->gamma_ad > 1.0) || !(phys->cfl > 0.0) || !(phys->M >= 0.0) || !(fabs(phys->a) <= phys->M))
     return fail(GRMHD_E_ARG, "need Gamma > 1, cfl > 0, M >= 0, |a| <= M");
+  if (phys->id_kind != GRMHD_ID_MICHEL && phys->id_kind != GRMHD_ID_TORUS)
+    return fail(GRMHD_E_ARG, "unknown initial-data kind");
+  if (phys->id_kind == GRMHD_ID_TORUS &&
+      !(phys->tor_r_in > 0.0 && phys->tor_r_max > phys->tor_r_in && phys->tor_rho_max > 0.0 &&
+        phys->tor_atm > 0.0 && phys->tor_loop_cut >= 0.0 && phys->tor_loop_cut < 1.0))
+    return fail(GRMHD_E_ARG, "torus needs 0 < r_in < r_max, rho_max > 0, atm > 0, 0 <= loop_cut < 1");
   grmhd_ctx* c = new grmhd_ctx();
   c->grid = *grid;
   c->phys = *phys;

@@ -241,45 +241,147 @@ int host_initial_data(const grmhd_grid& gr, const grmhd_phys& ph, const Operator
     for (size_t e = 0; e < PL; ++e) K0[e] = Kf[e] - betar[e] * dal[e] / (2.0 * alpha[e]);
   }
 
-  // ---- Michel matter + monopole ----
-  const Bondi mic(M, ph.gamma_ad, ph.r_c, ph.rho_c);
-  std::vector<double> rho1(nr), p1(nr), ur1(nr);
-  for (int j = 0; j < nr; ++j) {
-    const double r = ops.r[j];
-    const double T = mic.temperature(r);
-    rho1[j] = pow(T / mic.Kp, mic.n);
-    p1[j] = rho1[j] * T;
-    ur1[j] = -mic.C1 / (r * r * rho1[j]);
+  // ---- matter on the (theta, r) plane: rho, p, v^i (upper), densitised B^i ----
+  std::vector<double> rho_pl(PL), p_pl(PL), sqrtg(PL), v_pl[3], sB_pl[3];
+  for (int i = 0; i < 3; ++i) {
+    v_pl[i].assign(PL, 0.0);
+    sB_pl[i].assign(PL, 0.0);
   }
-  std::vector<double> vr(PL), sqrtg(PL), Br1(PL);
-  double min_pb = INFINITY;
-  for (int k = 0; k < nth; ++k)
+  std::vector<double> gm_pl[9];  // physical metric e^{4 phi} gt_ij
+  for (int c = 0; c < 9; ++c) gm_pl[c].assign(PL, 0.0);
+  for (size_t e = 0; e < PL; ++e) {
+    const double e4 = exp(4.0 * phi[e]);
+    double gtm[9];
+    for (int s = 0; s < 6; ++s) gtm[SI[s] * 3 + SJ[s]] = gtm[SJ[s] * 3 + SI[s]] = gt[s][e];
+    for (int c = 0; c < 9; ++c) gm_pl[c][e] = e4 * gtm[c];
+    sqrtg[e] = exp(6.0 * phi[e]) * sqrt(det3(gtm));
+  }
+  // b^2 of the field sB/sqrt(gamma) carried by velocity v at plane point e
+  auto bsq = [&](size_t e, const double* sBe, const double* ve) {
+    double vl[3], Bu[3], Bl[3];
+    for (int i = 0; i < 3; ++i) Bu[i] = sBe[i] / sqrtg[e];
+    for (int i = 0; i < 3; ++i) {
+      vl[i] = gm_pl[i * 3 + 0][e] * ve[0] + gm_pl[i * 3 + 1][e] * ve[1] + gm_pl[i * 3 + 2][e] * ve[2];
+      Bl[i] = gm_pl[i * 3 + 0][e] * Bu[0] + gm_pl[i * 3 + 1][e] * Bu[1] + gm_pl[i * 3 + 2][e] * Bu[2];
+    }
+    const double v2 = ve[0] * vl[0] + ve[1] * vl[1] + ve[2] * vl[2];
+    const double iW2 = 1.0 - v2;
+    const double Bv = Bu[0] * vl[0] + Bu[1] * vl[1] + Bu[2] * vl[2];
+    const double B2 = Bu[0] * Bl[0] + Bu[1] * Bl[1] + Bu[2] * Bl[2];
+    return B2 * iW2 + Bv * Bv;
+  };
+  double B0 = NAN;
+  const bool torus = ph.id_kind == GRMHD_ID_TORUS;
+  if (!torus) {
+    // Michel flow + monopole sqrt(gamma) B^r = B0 sin(theta)
+    const Bondi mic(M, ph.gamma_ad, ph.r_c, ph.rho_c);
+    std::vector<double> rho1(nr), p1(nr), ur1(nr);
     for (int j = 0; j < nr; ++j) {
-      const size_t e = (size_t)k * nr + j;
-      const double r = ops.r[j], th = ops.th[k];
+      const double r = ops.r[j];
+      const double T = mic.temperature(r);
+      rho1[j] = pow(T / mic.Kp, mic.n);
+      p1[j] = rho1[j] * T;
+      ur1[j] = -mic.C1 / (r * r * rho1[j]);
+    }
+    double min_pb = INFINITY;
+    for (int k = 0; k < nth; ++k)
+      for (int j = 0; j < nr; ++j) {
+        const size_t e = (size_t)k * nr + j;
+        const double r = ops.r[j], th = ops.th[k];
+        const double S = r * r + a * a * cos(th) * cos(th);
+        const double H = M * r / S;
+        // u^t from g_tt (u^t)^2 + 2 g_tr u^t u^r + g_rr (u^r)^2 = -1
+        const double gtt = -(1.0 - 2.0 * H), gtr = 2.0 * H, grr = 1.0 + 2.0 * H;
+        const double ur = ur1[j];
+        const double A = gtt, Bq = gtr * ur, C = grr * ur * ur + 1.0;
+        const double ut = C / (-Bq + sqrt(Bq * Bq - A * C));
+        const double W = alpha[e] * ut;
+        rho_pl[e] = rho1[j];
+        p_pl[e] = p1[j];
+        v_pl[0][e] = ur / W + betar[e] / alpha[e];
+        sB_pl[0][e] = sin(th);
+        const double sBe[3] = {sB_pl[0][e], 0.0, 0.0}, ve[3] = {v_pl[0][e], 0.0, 0.0};
+        min_pb = std::min(min_pb, p_pl[e] / bsq(e, sBe, ve));
+      }
+    B0 = sqrt(2.0 * min_pb / ph.beta_min);
+  } else {
+    // Fishbone-Moncrief torus of constant ell = u^t u_phi, isentropic
+    // p = K rho^Gamma, purely azimuthal flow; g_tt, g_tphi, g_phiphi (and
+    // hence u^t, u^phi) agree in Boyer-Lindquist and Kerr-Schild coordinates.
+    const double G = ph.gamma_ad;
+    const double sM = sqrt(M);
+    auto ell_of = [&](double r) {  // u^t u_phi, prograde circular equatorial geodesic
+      const double q = sqrt(pow(r, 1.5) - 3.0 * M * sqrt(r) + 2.0 * a * sM);
+      const double ut = (pow(r, 1.5) + a * sM) / (pow(r, 0.75) * q);
+      const double uphi = sM * (r * r - 2.0 * a * sqrt(M * r) + a * a) / (pow(r, 0.75) * q);
+      return ut * uphi;
+    };
+    const double ell = ell_of(ph.tor_r_max);
+    struct Flow { double ut, uph, lnh_raw; };
+    auto flow = [&](double r, double th) {
       const double S = r * r + a * a * cos(th) * cos(th);
       const double H = M * r / S;
-      // u^t from g_tt (u^t)^2 + 2 g_tr u^t u^r + g_rr (u^r)^2 = -1
-      const double gtt = -(1.0 - 2.0 * H), gtr = 2.0 * H, grr = 1.0 + 2.0 * H;
-      const double ur = ur1[j];
-      const double A = gtt, Bq = gtr * ur, C = grr * ur * ur + 1.0;
-      const double ut = C / (-Bq + sqrt(Bq * Bq - A * C));
-      const double W = alpha[e] * ut;
-      vr[e] = ur / W + betar[e] / alpha[e];
-      double gtm[9];
-      for (int s = 0; s < 6; ++s) gtm[SI[s] * 3 + SJ[s]] = gtm[SJ[s] * 3 + SI[s]] = gt[s][e];
-      sqrtg[e] = exp(6.0 * phi[e]) * sqrt(det3(gtm));
-      // b^2 for B^r = sin(theta)/sqrt(gamma) (B0 = 1), v = (v^r, 0, 0)
-      const double e4 = exp(4.0 * phi[e]);
-      const double g_rr = e4 * gt[0][e];
-      Br1[e] = sin(th) / sqrtg[e];
-      const double vv = g_rr * vr[e] * vr[e];
-      const double Wv = 1.0 / sqrt(1.0 - vv);
-      const double B2 = g_rr * Br1[e] * Br1[e], Bv = g_rr * Br1[e] * vr[e];
-      const double b2 = B2 / (Wv * Wv) + Bv * Bv;
-      min_pb = std::min(min_pb, p1[j] / b2);
+      const double s2 = sin(th) * sin(th);
+      const double gtt = -(1.0 - 2.0 * H), gtp = -2.0 * a * H * s2;
+      const double gpp = s2 * (S + a * a * s2 * (1.0 + 2.0 * H));
+      const double omega = -gtp / gpp;
+      const double alz = sqrt(omega * omega * gpp - gtt);          // ZAMO lapse
+      const double c = ell * alz / sqrt(gpp);
+      const double V = (sqrt(1.0 + 4.0 * c * c) - 1.0) / (2.0 * c);  // ZAMO azimuthal speed
+      const double ut = 1.0 / (alz * sqrt(1.0 - V * V));
+      const double Om = omega + alz * V / sqrt(gpp);
+      const double u_t = ut * (gtt + gtp * Om);
+      // integral of the circular-flow Euler equation at constant ell
+      return Flow{ut, ut * Om, log(1.0 + ell * Om) - log(-u_t) - ell * Om};
+    };
+    const double lnh_in = flow(ph.tor_r_in, 0.5 * M_PI).lnh_raw;
+    const double h_max = exp(flow(ph.tor_r_max, 0.5 * M_PI).lnh_raw - lnh_in);
+    const double Kp = (h_max - 1.0) * (G - 1.0) / (G * pow(ph.tor_rho_max, G - 1.0));
+    std::vector<double> rho_t(PL, 0.0), Aph(PL, 0.0);
+    for (int k = 0; k < nth; ++k)
+      for (int j = 0; j < nr; ++j) {
+        const size_t e = (size_t)k * nr + j;
+        const double r = ops.r[j], th = ops.th[k];
+        double ut = 0.0, uph = 0.0;
+        if (r >= ph.tor_r_in) {
+          const Flow f = flow(r, th);
+          const double lnh = f.lnh_raw - lnh_in;
+          if (lnh > 0.0) {
+            rho_t[e] = pow(expm1(lnh) * (G - 1.0) / (Kp * G), 1.0 / (G - 1.0));
+            ut = f.ut;
+            uph = f.uph;
+          }
+        }
+        const double rho_a = ph.tor_atm * ph.tor_rho_max * pow(r / ph.tor_r_max, -1.5);
+        rho_pl[e] = std::max(rho_t[e], rho_a);
+        p_pl[e] = Kp * pow(rho_pl[e], G);
+        if (rho_t[e] > 0.0) {
+          v_pl[0][e] = betar[e] / alpha[e];
+          v_pl[2][e] = uph / (alpha[e] * ut);
+        }
+        Aph[e] = std::max(rho_t[e] / ph.tor_rho_max - ph.tor_loop_cut, 0.0);
+      }
+    // one poloidal loop: sqrt(gamma) B^r = d_theta A_phi, sqrt(gamma) B^theta = -d_r A_phi
+    std::vector<double> dA;
+    dth(Aph, dA);
+    sB_pl[0] = dA;
+    dr(Aph, dA);
+    for (size_t e = 0; e < PL; ++e) sB_pl[1][e] = -dA[e];
+    double min_pb = INFINITY;
+    for (size_t e = 0; e < PL; ++e) {
+      if (!(Aph[e] > 0.0)) continue;
+      const double sBe[3] = {sB_pl[0][e], sB_pl[1][e], 0.0};
+      const double ve[3] = {v_pl[0][e], v_pl[1][e], v_pl[2][e]};
+      min_pb = std::min(min_pb, p_pl[e] / bsq(e, sBe, ve));
     }
-  const double B0 = sqrt(2.0 * min_pb / ph.beta_min);
+    B0 = sqrt(2.0 * min_pb / ph.beta_min);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (size_t e = 0; e < PL; ++e) sB_pl[i][e] *= B0;
+  if (!(B0 > 0.0) || !std::isfinite(B0)) {
+    if (err) *err = "initial data: field normalisation failed";
+    return GRMHD_E_ARG;
+  }
 
   // ---- assemble the 3D state ----
   Uout->assign((size_t)NF * P, 0.0);
@@ -301,18 +403,18 @@ int host_initial_data(const grmhd_grid& gr, const grmhd_phys& ph, const Operator
         U[17 * P + n] = alpha[e];
         U[18 * P + n] = betar[e];
         (*K0out)[n] = K0[e];
-        // matter
-        double rho = rho1[j];
-        const double p = p1[j];
+        // matter; seeded perturbation of rho (Michel) or p (torus)
+        double rho = rho_pl[e], p = p_pl[e];
         if (ph.pert_amp != 0.0) {
           const double u = (double)(splitmix64(ph.seed ^ (uint64_t)n) >> 11) * 0x1.0p-53;
-          rho = rho * (1.0 + ph.pert_amp * (2.0 * u - 1.0));
+          if (torus) p = p * (1.0 + ph.pert_amp * (2.0 * u - 1.0));
+          else rho = rho * (1.0 + ph.pert_amp * (2.0 * u - 1.0));
         }
-        const double e4 = exp(4.0 * phi[e]);
+        const double sg = sqrtg[e];
         double gm[9];
-        for (int s = 0; s < 6; ++s) gm[SI[s] * 3 + SJ[s]] = gm[SJ[s] * 3 + SI[s]] = e4 * gt[s][e];
-        const double v[3] = {vr[e], 0.0, 0.0};
-        const double Bu[3] = {B0 * Br1[e], 0.0, 0.0};
+        for (int c = 0; c < 9; ++c) gm[c] = gm_pl[c][e];
+        const double v[3] = {v_pl[0][e], v_pl[1][e], v_pl[2][e]};
+        const double Bu[3] = {sB_pl[0][e] / sg, sB_pl[1][e] / sg, sB_pl[2][e] / sg};
         double vl[3], Bl[3];
         for (int i = 0; i < 3; ++i) {
           vl[i] = gm[i * 3 + 0] * v[0] + gm[i * 3 + 1] * v[1] + gm[i * 3 + 2] * v[2];
@@ -326,16 +428,11 @@ int host_initial_data(const grmhd_grid& gr, const grmhd_phys& ph, const Operator
         const double Z = rho * h * W * W;
         const double D = rho * W;
         const double tau = Z - p + B2 - 0.5 * (B2 / (W * W) + Bv * Bv) - D;
-        const double sg = sqrtg[e];
         U[24 * P + n] = sg * D;
         for (int i = 0; i < 3; ++i) U[(25 + i) * P + n] = sg * ((Z + B2) * vl[i] - Bv * Bl[i]);
         U[28 * P + n] = sg * tau;
-        U[29 * P + n] = B0 * sin(ops.th[k]);
+        for (int i = 0; i < 3; ++i) U[(29 + i) * P + n] = sB_pl[i][e];
       }
-  if (!(B0 > 0.0) || !std::isfinite(B0)) {
-    if (err) *err = "initial data: field normalisation failed";
-    return GRMHD_E_ARG;
-  }
   return GRMHD_OK;
 }
 

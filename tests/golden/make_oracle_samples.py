@@ -1,11 +1,12 @@
-"""Writes ks_michel_64x64x128_10steps.json: the oracle's state after 10 RK4
-steps (CFL 0.25, filter on) of the 64x64x128 Kerr-Schild a = 0.5 + magnetised
-Michel workload, at a fixed set of sampled grid points.
+"""Writes <workload>_<steps>steps.json: the oracle's state after `steps` RK4
+steps (CFL 0.25, filter on) of a workload, at a fixed set of sampled grid
+points, plus the whole-field L2 norms.
 
-Calls only the oracle and the seeded workload definition.  Run from the
-repository root (takes tens of minutes of CPU):
+Calls only the oracle and the seeded workload definitions.  Run from the
+repository root (tens of minutes of CPU at full size):
 
-    python tests/golden/make_ks_michel_64x64x128_samples.py
+    python tests/golden/make_oracle_samples.py ks_michel_64x64x128 10
+    python tests/golden/make_oracle_samples.py ks_torus_128x96x192 4
 """
 
 import json
@@ -20,10 +21,6 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 from oracle import evolve, spectral  # noqa: E402
-
-NAME = "ks_michel_64x64x128"
-STEPS = 10
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{NAME}_{STEPS}steps.json")
 
 
 def sample_points(nph, nth, nr, seed=7, n_random=256):
@@ -40,28 +37,28 @@ def sample_points(nph, nth, nr, seed=7, n_random=256):
     return sorted(pts)
 
 
-def main():
-    w = workloads.WORKLOADS[NAME]
+def main(name, steps):
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_{steps}steps.json")
+    w = workloads.WORKLOADS[name]
     ga, pk, ik = workloads.oracle_kwargs(w)
     g = spectral.Grid(*ga)
     pb = evolve.Problem(g, **pk)
-    U0, K0, _ = evolve.initial_state(g, pb, **ik)
+    U, K0, _ = evolve.initial_state(g, pb, **ik)
     dt = pb.dt()
     t0 = time.time()
-    U = U0
-    for n in range(STEPS):
+    for n in range(steps):
         U = pb.step(U, K0, dt)
-        print(f"step {n + 1}/{STEPS}  {time.time() - t0:.0f} s", flush=True)
+        print(f"step {n + 1}/{steps}  {time.time() - t0:.0f} s", flush=True)
     pts = sample_points(*U.shape[1:])
     idx = tuple(np.array(pts).T)
     vals = U[(slice(None),) + idx].T  # (npoints, 32)
-    with open(OUT, "w") as f:
-        json.dump({"workload": NAME, "steps": STEPS, "dt": dt, "shape": list(U.shape),
+    with open(out, "w") as f:
+        json.dump({"workload": name, "steps": steps, "dt": dt, "shape": list(U.shape),
                    "points": pts, "values": [[float.hex(float(v)) for v in row] for row in vals],
                    "field_norms_full": [float(np.sqrt(np.sum(U[q] ** 2))) for q in range(U.shape[0])]},
                   f, separators=(",", ":"))
-    print(f"wrote {OUT}: {len(pts)} points")
+    print(f"wrote {out}: {len(pts)} points")
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1], int(sys.argv[2]))

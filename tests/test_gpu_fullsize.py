@@ -1,9 +1,9 @@
 """Full-size parity: the 64x64x128 Kerr-Schild + Michel workload, in the
 launch configuration the benchmark times, after 10 RK4 steps against the
 oracle's state at sampled grid points (stored by
-tests/golden/make_ks_michel_64x64x128_samples.py, which calls only the
-oracle).  Per-field relative error over the samples (tensor-group scaled, as
-in the small-grid tests) within 1e-11."""
+tests/golden/make_oracle_samples.py, which calls only the oracle).
+Per-field relative error over the samples (tensor-group scaled, as in the
+small-grid tests) within 1e-11."""
 
 import json
 import os

@@ -15,6 +15,21 @@ COMMON_GRID = dict(r_in=1.8, r_out=20.0, th_min=0.05, th_max=math.pi - 0.05,
 COMMON_PHYS = dict(M=1.0, a=0.5, gamma_ad=4.0 / 3.0, cfl=0.25, eta=2.0, cowling=False, gauge_k0=True,
                    r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, rho_floor=1e-20, p_floor=1e-24)
 
+# torus workloads: spin 0.9375, inner radius scaled with the horizon
+# (r_in(a) = 1.8 r_h(a)/r_h(0.5) = 1.300), outer radius 60; Fishbone-Moncrief
+# torus with inner edge 6, pressure maximum 12, Gamma = 13/9, rho_max = 1e-8;
+# one poloidal loop at min plasma beta 100 over the loop; +-4 % pressure
+# perturbation
+def _r_h(a):
+    return 1.0 + math.sqrt(1.0 - a * a)
+
+
+TORUS_SPIN = 0.9375
+TORUS_GRID = dict(COMMON_GRID, r_in=1.8 * _r_h(TORUS_SPIN) / _r_h(0.5), r_out=60.0)
+TORUS_PHYS = dict(COMMON_PHYS, a=TORUS_SPIN, gamma_ad=13.0 / 9.0, beta_min=100.0, pert_amp=0.04,
+                  id_kind="torus", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-2,
+                  tor_loop_cut=0.2)
+
 WORKLOADS = {
     # tiny coupled evolution: 16^3, 10 RK4 steps
     "ks_michel_16x16x16": dict(grid=dict(nr=16, nth=16, nph=16, **COMMON_GRID),
@@ -22,6 +37,13 @@ WORKLOADS = {
     # plain FP64 GPU baseline: 64 x 64 x 128, 100 RK4 steps
     "ks_michel_64x64x128": dict(grid=dict(nr=64, nth=64, nph=128, **COMMON_GRID),
                                 phys=dict(seed=2, **COMMON_PHYS), steps=100),
+    # magnetised Fishbone-Moncrief torus at high resolution, a = 0.9375:
+    # 128 x 96 x 192, r in [r_in(a), 60], 200 RK4 steps
+    "ks_torus_128x96x192": dict(grid=dict(nr=128, nth=96, nph=192, **TORUS_GRID),
+                                phys=dict(seed=4, **TORUS_PHYS), steps=200),
+    # the same physics on a small grid (parity against the oracle)
+    "ks_torus_24x20x16": dict(grid=dict(nr=24, nth=20, nph=16, **TORUS_GRID),
+                              phys=dict(seed=3, **TORUS_PHYS), steps=10),
 }
 
 
@@ -36,6 +58,9 @@ def oracle_kwargs(w):
                 cfl=p["cfl"])
     init = dict(r_c=p["r_c"], rho_c=p["rho_c"], beta_min=p["beta_min"], pert_amp=p["pert_amp"],
                 seed=p["seed"])
+    for k in ("id_kind", "tor_r_in", "tor_r_max", "tor_rho_max", "tor_atm", "tor_loop_cut"):
+        if k in p:
+            init[k] = p[k]
     return grid_args, prob, init
 
 
