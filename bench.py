@@ -159,6 +159,53 @@ def mixed_forms(w, K, fp64_rate, Solver, make_grid, make_phys, torch):
     return out
 
 
+def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
+    """A second measured configuration (the magnetised torus at 128x96x192):
+    FP64 and FP32-form throughput over the workload's step count from the
+    library's initial data, the dominant launch's roofline, the stage
+    fraction, and the FP32 form's errors against the FP64 path."""
+    w = workloads.WORKLOADS[name]
+    g = w["grid"]
+    P = g["nr"] * g["nth"] * g["nph"]
+    K = w["steps"]
+    costs = launch_costs(g["nr"], g["nth"], g["nph"])
+    out = {"workload": name, "grid": [g["nr"], g["nth"], g["nph"]], "points": P, "steps": K}
+    states = {}
+    for name_p, prec in (("fp64", 0), ("fp32", 1)):
+        s = Solver(make_grid(**g), make_phys(**w["phys"]), prec=prec)
+        s.init_state()
+        s.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d = s.diagnostics()
+        rec = {"value": P * 4 * K / wall, "ms_per_step": wall * 1e3 / K, "c2p_fail": d["c2p_fail"],
+               "nonfinite": d["nonfinite"], "ham_l2": d["ham_l2"]}
+        if prec == 0:
+            prof = s.profile_step(profile_steps)
+            per_step = {k: ms * cnt / profile_steps for k, (ms, cnt) in prof.items()}
+            dom = max(per_step, key=per_step.get)
+            rec["roofline"] = roofline(dom, prof[dom][0], P, costs)
+            ideal = sum(ideal_ms(k, P, costs) * cnt / profile_steps for k, (ms, cnt) in prof.items())
+            rec["stage_roofline_fraction"] = round(ideal / sum(per_step.values()), 3)
+            rec["kernels_avg_ms"] = {k: round(ms, 5) for k, (ms, cnt) in prof.items()}
+        states[name_p] = s.get_state()
+        prim = torch.empty((5,) + s.shape, dtype=torch.float64, device="cuda")
+        s.con2prim(s.U, prim)
+        states[name_p + "_rho"] = prim[0].cpu().numpy()
+        out[name_p] = rec
+        s.close()
+    import numpy as np
+    r64, r32 = states["fp64_rho"], states["fp32_rho"]
+    out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    out["fp32"]["rho_l2_rel_vs_fp64"] = float(np.sqrt(np.sum((r32 - r64) ** 2) / np.sum(r64 ** 2)))
+    out["fp32"]["ham_ratio"] = out["fp32"]["ham_l2"] / out["fp64"]["ham_l2"]
+    out["fp32"]["field_rel_err_max"] = max(group_errors(states["fp32"], states["fp64"]))
+    return out
+
+
 def traffic_probe(w, torch, Solver, make_grid, make_phys):
     """Workload for the HBM traffic counters (run under rocprofv3 --pmc): one
     plain device copy of 512 MiB (the counters' scale reference: 512 MiB read,
@@ -202,6 +249,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-second", action="store_true", help="skip the 128x96x192 torus configuration")
     ap.add_argument("--serve-t-scale", type=float, default=1e-3)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 512 MiB copy + one RK4 step, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -288,6 +336,8 @@ def main():
     }
     if not args.no_mixed:
         out["mixed_precision"] = mixed_forms(w, K, out["value"], Solver, make_grid, make_phys, torch)
+    if not args.no_second:
+        out["second_config"] = second_config("ks_torus_128x96x192", torch, Solver, make_grid, make_phys)
     if not args.no_serving:
         from paper_2508_18221_amd.serve import run_stream
         jobs = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale)
