@@ -44,6 +44,10 @@ def launch_costs(nr, nth, nph):
     c["deriv_t1"] = (58 * d, fl(nth) * 29)              # 29 in, 29 out
     c["deriv_p2"] = (33 * d, 2 * fl(nph) * 11)
     c["deriv_p1"] = (80 * d, fl(nph) * 40)              # 40 in, 40 out
+    # one launch per axis holding both kinds of task (folded FP64 / FP32 forms)
+    for k, a, b in (("deriv_r", "deriv_r2", "deriv_r1"), ("deriv_t", "deriv_t2", "deriv_t1"),
+                    ("deriv_p", "deriv_p2", "deriv_p1")):
+        c[k] = (c[a][0] + c[b][0], c[a][1] + c[b][1])
     c["rhs_rk"] = (303 * d, 0.0)                        # mean over the 4 stage modes
     for k, n in (("filter_r", nr), ("filter_t", nth), ("filter_p", nph)):
         c[k] = (64 * d, fl(n) * 32)

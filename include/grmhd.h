@@ -281,7 +281,10 @@ enum {
   GRMHD_K_DERIV_P1 = 6,   /* phi axis, first (10 + 22 mixed + 8 fluxes)            */
   GRMHD_K_RHS_RK = 7,     /* BSSN + Valencia RHS and RK4 stage update              */
   GRMHD_K_FILTER_R = 8, GRMHD_K_FILTER_T = 9, GRMHD_K_FILTER_P = 10,
-  GRMHD_K_COUNT = 11
+  GRMHD_K_DERIV_R = 11,   /* r axis, first + second and first-only tasks in one launch */
+  GRMHD_K_DERIV_T = 12,   /* theta axis, likewise                                      */
+  GRMHD_K_DERIV_P = 13,   /* phi axis, likewise                                        */
+  GRMHD_K_COUNT = 14
 };
 
 /* Advance nsteps RK4 steps exactly as grmhd_step, recording a HIP event on

@@ -168,9 +168,44 @@ struct Recorder {
     if (rec) HIPCHK((rec)->mark((k), c->stream));                  \
   } while (0)
 
+// A task applying one operator (d1 < 0) or two (outputs d0 and d1).
+void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = -1) {
+  Task& t = tl.t[tl.n++];
+  t.src_sel = ssel;
+  t.src = src;
+  t.dst_sel = dsel;
+  t.dst0 = d0;
+  t.dst1 = d1 >= 0 ? d1 : 0;
+  t.nmat = d1 >= 0 ? 2 : 1;
+}
+
+void addm(MixedTaskList& tl, int ssel, int src, int f32, int dsel, int d0, int d1 = -1) {
+  MixedTask& t = tl.t[tl.n++];
+  t.src_sel = ssel;
+  t.src = src;
+  t.src_f32 = f32;
+  t.dst_sel = dsel;
+  t.dst0 = d0;
+  t.dst1 = d1 >= 0 ? d1 : 0;
+  t.nmat = d1 >= 0 ? 2 : 1;
+}
+
+// The tasks of a list that apply `nmat` operators.
+template <class L>
+L select_tasks(const L& tl, int nmat) {
+  L out;
+  out.n = 0;
+  for (int i = 0; i < tl.n; ++i)
+    if (tl.t[i].nmat == nmat) out.t[out.n++] = tl.t[i];
+  return out;
+}
+
 // Line contractions with operators op0 (and op1 when nmat = 2).  Even N uses
 // the folded kernel (half the MFMA work); it needs the first derivative
 // beside a radial second derivative, so a lone radial D2 takes the full form.
+// nmat = 2: the list may mix two-operator tasks (op0 and op1) and one-operator
+// tasks (op0); the folded kernel takes them in one launch, the full kernel in
+// one launch per kind.
 hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const TaskList& tl,
                     const Bases& B, const JobSet& js) {
   const bool pair_ok = nmat == 1 ? !(axis == 0 && op0 == OP_D2) : (op0 == OP_D1 && op1 == OP_D2);
@@ -179,28 +214,16 @@ hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const Ta
     return launch_contract_fold(axis, nmat, tl, B, c->fop[axis][op0], c->fop[axis][op1], g10, c->ops.n,
                                 c->ops.hpad, (long long)c->L.P, js, c->stream);
   }
-  return launch_contract(axis, nmat, tl, B, c->mats[axis][op0], c->mats[axis][op1], c->ops.n,
+  if (nmat == 1)
+    return launch_contract(axis, 1, tl, B, c->mats[axis][op0], c->mats[axis][op0], c->ops.n, c->ops.npad,
+                           (long long)c->L.P, js, c->stream);
+  hipError_t e = launch_contract(axis, 2, select_tasks(tl, 2), B, c->mats[axis][op0], c->mats[axis][op1],
+                                 c->ops.n, c->ops.npad, (long long)c->L.P, js, c->stream);
+  if (e != hipSuccess) return e;
+  return launch_contract(axis, 1, select_tasks(tl, 1), B, c->mats[axis][op0], c->mats[axis][op0], c->ops.n,
                          c->ops.npad, (long long)c->L.P, js, c->stream);
 }
 
-void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = 0) {
-  Task& t = tl.t[tl.n++];
-  t.src_sel = ssel;
-  t.src = src;
-  t.dst_sel = dsel;
-  t.dst0 = d0;
-  t.dst1 = d1;
-}
-
-void addm(MixedTaskList& tl, int ssel, int src, int f32, int dsel, int d0, int d1 = 0) {
-  MixedTask& t = tl.t[tl.n++];
-  t.src_sel = ssel;
-  t.src = src;
-  t.src_f32 = f32;
-  t.dst_sel = dsel;
-  t.dst0 = d0;
-  t.dst1 = d1;
-}
 
 // Reduced-precision derivative passes: inputs FP64 (stage state, fluxes) or
 // FP32 (first derivatives for the mixed ones), FP32 outputs in the derivative
@@ -215,32 +238,29 @@ int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* re
   B.b[3] = nullptr;
   const int o2 = SC_D2 - SC_D1, omx = SC_MX - SC_D1, odf = SC_DF - SC_D1;
   for (int a = 0; a < 3; ++a) {
-    MixedTaskList t2, t1;
-    t2.n = t1.n = 0;
-    for (int s = 0; s < ND2; ++s) addm(t2, 0, D2_FIELD[s], 0, 1, 21 * a + D2_FIELD[s], o2 + 11 * a + s);
-    for (int q = 0; q < 10; ++q) addm(t1, 0, D1_ONLY[q], 0, 1, 21 * a + D1_ONLY[q]);
+    MixedTaskList tl;
+    tl.n = 0;
+    for (int s = 0; s < ND2; ++s) addm(tl, 0, D2_FIELD[s], 0, 1, 21 * a + D2_FIELD[s], o2 + 11 * a + s);
+    for (int q = 0; q < 10; ++q) addm(tl, 0, D1_ONLY[q], 0, 1, 21 * a + D1_ONLY[q]);
     if (a == 1)
-      for (int s = 0; s < ND2; ++s) addm(t1, 1, D2_FIELD[s], 1, 1, omx + s);
+      for (int s = 0; s < ND2; ++s) addm(tl, 1, D2_FIELD[s], 1, 1, omx + s);
     if (a == 2) {
-      for (int s = 0; s < ND2; ++s) addm(t1, 1, D2_FIELD[s], 1, 1, omx + 11 + s);
-      for (int s = 0; s < ND2; ++s) addm(t1, 1, 21 + D2_FIELD[s], 1, 1, omx + 22 + s);
+      for (int s = 0; s < ND2; ++s) addm(tl, 1, D2_FIELD[s], 1, 1, omx + 11 + s);
+      for (int s = 0; s < ND2; ++s) addm(tl, 1, 21 + D2_FIELD[s], 1, 1, omx + 22 + s);
     }
-    for (int v = 0; v < 8; ++v) addm(t1, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
-    if (c->prec == GRMHD_MIX_FP32 && c->ops.fold[a]) {  // folded FP32 form
+    for (int v = 0; v < 8; ++v) addm(tl, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
+    if (c->prec == GRMHD_MIX_FP32 && c->ops.fold[a]) {  // folded FP32 form, one launch per axis
       const double* g10 = a == 0 ? c->gr + 2 * (size_t)c->grid.nr : nullptr;
-      HIPCHK(launch_contract_f32_fold(a, 2, t2, B, c->fop32[a][0], c->fop32[a][1], g10, c->ops.n, c->ops.hpad,
+      HIPCHK(launch_contract_f32_fold(a, 2, tl, B, c->fop32[a][0], c->fop32[a][1], g10, c->ops.n, c->ops.hpad,
                                       (long long)c->L.P, js, c->stream));
-      MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
-      HIPCHK(launch_contract_f32_fold(a, 1, t1, B, c->fop32[a][0], c->fop32[a][0], nullptr, c->ops.n,
-                                      c->ops.hpad, (long long)c->L.P, js, c->stream));
-      MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
+      MARK(rec, GRMHD_K_DERIV_R + a);
       continue;
     }
-    HIPCHK(launch_contract_mixed(c->prec, a, 2, t2, B, c->mops[a][0], c->mops[a][1], c->ops.n, c->ops.npad,
-                                 (long long)c->L.P, js, c->stream));
+    HIPCHK(launch_contract_mixed(c->prec, a, 2, select_tasks(tl, 2), B, c->mops[a][0], c->mops[a][1], c->ops.n,
+                                 c->ops.npad, (long long)c->L.P, js, c->stream));
     MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
-    HIPCHK(launch_contract_mixed(c->prec, a, 1, t1, B, c->mops[a][0], c->mops[a][0], c->ops.n, c->ops.npad,
-                                 (long long)c->L.P, js, c->stream));
+    HIPCHK(launch_contract_mixed(c->prec, a, 1, select_tasks(tl, 1), B, c->mops[a][0], c->mops[a][0], c->ops.n,
+                                 c->ops.npad, (long long)c->L.P, js, c->stream));
     MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
   }
   return GRMHD_OK;
@@ -254,21 +274,21 @@ int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec
   B.b[2] = (double*)c->res;
   B.b[3] = nullptr;
   for (int a = 0; a < 3; ++a) {
-    TaskList t2, t1;
-    t2.n = t1.n = 0;
-    for (int s = 0; s < ND2; ++s) add(t2, 0, D2_FIELD[s], 1, SC_D1 + 21 * a + D2_FIELD[s], SC_D2 + 11 * a + s);
-    for (int q = 0; q < 10; ++q) add(t1, 0, D1_ONLY[q], 1, SC_D1 + 21 * a + D1_ONLY[q]);
+    // first + second derivatives first (the heavier tasks start first), then
+    // first derivatives only, all in one launch
+    TaskList tl;
+    tl.n = 0;
+    for (int s = 0; s < ND2; ++s) add(tl, 0, D2_FIELD[s], 1, SC_D1 + 21 * a + D2_FIELD[s], SC_D2 + 11 * a + s);
+    for (int q = 0; q < 10; ++q) add(tl, 0, D1_ONLY[q], 1, SC_D1 + 21 * a + D1_ONLY[q]);
     if (a == 1)  // mixed r-theta: d_theta of d_r
-      for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + s);
+      for (int s = 0; s < ND2; ++s) add(tl, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + s);
     if (a == 2) {  // mixed r-phi, theta-phi
-      for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + 11 + s);
-      for (int s = 0; s < ND2; ++s) add(t1, 1, SC_D1 + 21 + D2_FIELD[s], 1, SC_MX + 22 + s);
+      for (int s = 0; s < ND2; ++s) add(tl, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + 11 + s);
+      for (int s = 0; s < ND2; ++s) add(tl, 1, SC_D1 + 21 + D2_FIELD[s], 1, SC_MX + 22 + s);
     }
-    for (int v = 0; v < 8; ++v) add(t1, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
-    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, t2, B, js));
-    MARK(rec, GRMHD_K_DERIV_R2 + 2 * a);
-    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, t1, B, js));
-    MARK(rec, GRMHD_K_DERIV_R1 + 2 * a);
+    for (int v = 0; v < 8; ++v) add(tl, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
+    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, tl, B, js));
+    MARK(rec, GRMHD_K_DERIV_R + a);
   }
   return GRMHD_OK;
 }

@@ -19,6 +19,8 @@
 // (the f64 accumulator interleaves rows by 4, unlike the f32 16x16x4 form).
 #include "grmhd_internal.h"
 
+#include <type_traits>
+
 namespace grmhd {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -280,7 +282,10 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
 // the epilogue: out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u),
 // with A_0, A_1 the unmapped operators (g = null: unit scale, no coupling).
 // F0, F1: E^T (Hpad x Hpad, AT[k][i] = E[i][k], zero padded) followed by O^T.
-template <int NMAT, bool INNER, int WI>
+// NMAXT = 1: every task applies one operator (F0); NMAXT = 2: each task
+// applies one or two operators (its nmat), so the first-and-second and the
+// first-only passes of an axis share one launch.
+template <int NMAXT, bool INNER, int WI>
 __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, const double* __restrict__ F0,
                                                        const double* __restrict__ F1,
                                                        const double* __restrict__ G0,
@@ -289,7 +294,6 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
                                                        double sig1, int N, int Hpad, int inner, int slab,
                                                        long long P, JobSet js) {
   extern __shared__ double tile[];  // [2 Hpad][LDS_STRIDE]: s rows, then d rows
-  constexpr int KCF = NMAT > 1 ? 2 : 4;  // k-steps of operator fragments per chunk
   const Task tk = tl.t[blockIdx.z % tl.n];
   const long long jd = js.d[blockIdx.z / tl.n];
   F0 = shift_ptr(F0, jd);
@@ -357,97 +361,103 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   __syncthreads();
 
   // ---- MFMA: (E s) and (O d) for the H output rows of each pair --------------
-  constexpr int FW = WI;
-  const int T = Hpad >> 4;
-  const int wi = wave % WI, wf = wave / WI;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int nks = Hpad >> 2;  // a multiple of 4, hence of KCF
-  const size_t hh = (size_t)Hpad * Hpad;
-  for (int it = wi; it < T; it += WI) {
-    d4 acc[NMAT][2][FW];
-#pragma unroll
-    for (int m = 0; m < NMAT; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int f = 0; f < FW; ++f) acc[m][h][f] = d4{0.0, 0.0, 0.0, 0.0};
-    const double* __restrict__ ap[NMAT];
-    ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
-    if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
-    const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
-    double a[NMAT][2][KCF];
-#pragma unroll
-    for (int m = 0; m < NMAT; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int q = 0; q < KCF; ++q) a[m][h][q] = ap[m][h * hh + (size_t)(4 * q) * Hpad];
-    for (int kc = 0; kc < nks; kc += KCF) {
-      const int kn = (kc + KCF < nks) ? kc + KCF : kc;  // last chunk: in-bounds dummy prefetch
-      double an[NMAT][2][KCF];
+  auto run = [&](auto nm) {
+    constexpr int NMAT = decltype(nm)::value;
+    constexpr int KCF = NMAT > 1 ? 2 : 4;  // k-steps of operator fragments per chunk
+    constexpr int FW = WI;
+    const int T = Hpad >> 4;
+    const int wi = wave % WI, wf = wave / WI;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nks = Hpad >> 2;  // a multiple of 4, hence of KCF
+    const size_t hh = (size_t)Hpad * Hpad;
+    for (int it = wi; it < T; it += WI) {
+      d4 acc[NMAT][2][FW];
 #pragma unroll
       for (int m = 0; m < NMAT; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int q = 0; q < KCF; ++q) an[m][h][q] = ap[m][h * hh + (size_t)(4 * (kn + q)) * Hpad];
-#pragma unroll
-      for (int q = 0; q < KCF; ++q) {
-        double b[2][FW];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * LDS_STRIDE + f * 16];
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int f = 0; f < FW; ++f)
-#pragma unroll
-            for (int m = 0; m < NMAT; ++m) {
-              if (INNER) acc[m][h][f] = mfma_f64(b[h][f], a[m][h][q], acc[m][h][f]);
-              else acc[m][h][f] = mfma_f64(a[m][h][q], b[h][f], acc[m][h][f]);
-            }
-      }
+          for (int f = 0; f < FW; ++f) acc[m][h][f] = d4{0.0, 0.0, 0.0, 0.0};
+      const double* __restrict__ ap[NMAT];
+      ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
+      if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
+      const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
+      double a[NMAT][2][KCF];
 #pragma unroll
       for (int m = 0; m < NMAT; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int q = 0; q < KCF; ++q) a[m][h][q] = an[m][h][q];
-    }
-    // ---- unfold, scale, store ----------------------------------------------
+          for (int q = 0; q < KCF; ++q) a[m][h][q] = ap[m][h * hh + (size_t)(4 * q) * Hpad];
+      for (int kc = 0; kc < nks; kc += KCF) {
+        const int kn = (kc + KCF < nks) ? kc + KCF : kc;  // last chunk: in-bounds dummy prefetch
+        double an[NMAT][2][KCF];
 #pragma unroll
-    for (int f = 0; f < FW; ++f) {
-      const int cf = (wf * FW + f) * 16;
+        for (int m = 0; m < NMAT; ++m)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = lk + 4 * v;  // D row within the 16x16 block
-        int i, col;
-        if (INNER) {
-          col = c0 + cf + row;
-          i = it * 16 + lr;
-        } else {
-          i = it * 16 + row;
-          col = c0 + cf + lr;
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < KCF; ++q) an[m][h][q] = ap[m][h * hh + (size_t)(4 * (kn + q)) * Hpad];
+#pragma unroll
+        for (int q = 0; q < KCF; ++q) {
+          double b[2][FW];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * LDS_STRIDE + f * 16];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int f = 0; f < FW; ++f)
+#pragma unroll
+              for (int m = 0; m < NMAT; ++m) {
+                if (INNER) acc[m][h][f] = mfma_f64(b[h][f], a[m][h][q], acc[m][h][f]);
+                else acc[m][h][f] = mfma_f64(a[m][h][q], b[h][f], acc[m][h][f]);
+              }
         }
-        if (i < H && col < inner) {
-          const int im = N - 1 - i;
-          const double e0 = acc[0][0][f][v], o0 = acc[0][1][f][v];
-          const double y0 = e0 + o0, y0m = sig0 * (e0 - o0);
-          const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
-          const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
-          dst0[p] = G0 ? G0[i] * y0 : y0;
-          dst0[pm] = G0 ? G0[im] * y0m : y0m;
-          if (NMAT > 1) {
-            const double e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
-            const double y1 = e1 + o1, y1m = sig1 * (e1 - o1);
-            dst1[p] = (G1 ? G1[i] * y1 : y1) + (G10 ? G10[i] * y0 : 0.0);
-            dst1[pm] = (G1 ? G1[im] * y1m : y1m) + (G10 ? G10[im] * y0m : 0.0);
+#pragma unroll
+        for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < KCF; ++q) a[m][h][q] = an[m][h][q];
+      }
+      // ---- unfold, scale, store ----------------------------------------------
+#pragma unroll
+      for (int f = 0; f < FW; ++f) {
+        const int cf = (wf * FW + f) * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = lk + 4 * v;  // D row within the 16x16 block
+          int i, col;
+          if (INNER) {
+            col = c0 + cf + row;
+            i = it * 16 + lr;
+          } else {
+            i = it * 16 + row;
+            col = c0 + cf + lr;
+          }
+          if (i < H && col < inner) {
+            const int im = N - 1 - i;
+            const double e0 = acc[0][0][f][v], o0 = acc[0][1][f][v];
+            const double y0 = e0 + o0, y0m = sig0 * (e0 - o0);
+            const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
+            const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
+            dst0[p] = G0 ? G0[i] * y0 : y0;
+            dst0[pm] = G0 ? G0[im] * y0m : y0m;
+            if (NMAT > 1) {
+              const double e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
+              const double y1 = e1 + o1, y1m = sig1 * (e1 - o1);
+              dst1[p] = (G1 ? G1[i] * y1 : y1) + (G10 ? G10[i] * y0 : 0.0);
+              dst1[pm] = (G1 ? G1[im] * y1m : y1m) + (G10 ? G10[im] * y0m : 0.0);
+            }
           }
         }
       }
     }
-  }
+  };
+  if (NMAXT > 1 && tk.nmat > 1) run(std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>{});
+  else run(std::integral_constant<int, 1>{});
 }
 
 template <int NMAT, bool INNER, int WI>

@@ -19,6 +19,8 @@
 //                 D as for f32.
 #include "grmhd_internal.h"
 
+#include <type_traits>
+
 namespace grmhd {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -345,7 +347,8 @@ size_t mixed_lds_bytes(int prec, int npad) {
 // FP64; s and d are rounded to FP32 once, the products run on FP32 MFMA.
 // Row scales of the radial map are applied in the epilogue in FP64:
 // out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u).
-template <int NMAT, bool INNER, int WI>
+// NMAXT = 2: each task applies one or two operators (its nmat).
+template <int NMAXT, bool INNER, int WI>
 __global__ __launch_bounds__(256) void k_contract_f32_fold(MixedTaskList tl, Bases B, const float* __restrict__ F0,
                                                            const float* __restrict__ F1,
                                                            const double* __restrict__ G0,
@@ -355,7 +358,6 @@ __global__ __launch_bounds__(256) void k_contract_f32_fold(MixedTaskList tl, Bas
                                                            JobSet js) {
   extern __shared__ float tf[];  // [2 Hpad][F32_STRIDE]: s rows, d rows; then 64 doubles of line offsets
   double* shift = (double*)(tf + (size_t)2 * Hpad * F32_STRIDE);
-  constexpr int KCF = NMAT > 1 ? 2 : 4;
   const MixedTask tk = tl.t[blockIdx.z % tl.n];
   const long long jd = js.d[blockIdx.z / tl.n];
   F0 = shift_ptr(F0, jd);
@@ -402,98 +404,104 @@ __global__ __launch_bounds__(256) void k_contract_f32_fold(MixedTaskList tl, Bas
   else fill(field_base<double>(tk, B, P, jd));
   __syncthreads();
 
-  constexpr int FW = WI;
-  const int T = Hpad >> 4;
-  const int wi = wave % WI, wf = wave / WI;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int nks = Hpad >> 2;  // a multiple of 4, hence of KCF
-  const size_t hh = (size_t)Hpad * Hpad;
-  float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
-  float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
-  for (int it = wi; it < T; it += WI) {
-    f4 acc[NMAT][2][FW];
-#pragma unroll
-    for (int m = 0; m < NMAT; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int f = 0; f < FW; ++f) acc[m][h][f] = f4{0.f, 0.f, 0.f, 0.f};
-    const float* __restrict__ ap[NMAT];
-    ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
-    if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
-    const float* tp = tf + lk * F32_STRIDE + wf * FW * 16 + lr;
-    float a[NMAT][2][KCF];
-#pragma unroll
-    for (int m = 0; m < NMAT; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int q = 0; q < KCF; ++q) a[m][h][q] = ap[m][h * hh + (size_t)(4 * q) * Hpad];
-    for (int kc = 0; kc < nks; kc += KCF) {
-      const int kn = (kc + KCF < nks) ? kc + KCF : kc;  // last chunk: in-bounds dummy prefetch
-      float an[NMAT][2][KCF];
+  auto run = [&](auto nm) {
+    constexpr int NMAT = decltype(nm)::value;
+    constexpr int KCF = NMAT > 1 ? 2 : 4;
+    constexpr int FW = WI;
+    const int T = Hpad >> 4;
+    const int wi = wave % WI, wf = wave / WI;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nks = Hpad >> 2;  // a multiple of 4, hence of KCF
+    const size_t hh = (size_t)Hpad * Hpad;
+    float* dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + soff;
+    float* dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + soff;
+    for (int it = wi; it < T; it += WI) {
+      f4 acc[NMAT][2][FW];
 #pragma unroll
       for (int m = 0; m < NMAT; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int q = 0; q < KCF; ++q) an[m][h][q] = ap[m][h * hh + (size_t)(4 * (kn + q)) * Hpad];
+          for (int f = 0; f < FW; ++f) acc[m][h][f] = f4{0.f, 0.f, 0.f, 0.f};
+      const float* __restrict__ ap[NMAT];
+      ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
+      if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
+      const float* tp = tf + lk * F32_STRIDE + wf * FW * 16 + lr;
+      float a[NMAT][2][KCF];
 #pragma unroll
-      for (int q = 0; q < KCF; ++q) {
-        float b[2][FW];
+      for (int m = 0; m < NMAT; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * F32_STRIDE + f * 16];
+          for (int q = 0; q < KCF; ++q) a[m][h][q] = ap[m][h * hh + (size_t)(4 * q) * Hpad];
+      for (int kc = 0; kc < nks; kc += KCF) {
+        const int kn = (kc + KCF < nks) ? kc + KCF : kc;  // last chunk: in-bounds dummy prefetch
+        float an[NMAT][2][KCF];
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int m = 0; m < NMAT; ++m)
 #pragma unroll
-          for (int f = 0; f < FW; ++f)
+          for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int m = 0; m < NMAT; ++m) {
-              if (INNER) acc[m][h][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[h][f], a[m][h][q], acc[m][h][f], 0, 0, 0);
-              else acc[m][h][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][h][q], b[h][f], acc[m][h][f], 0, 0, 0);
-            }
+            for (int q = 0; q < KCF; ++q) an[m][h][q] = ap[m][h * hh + (size_t)(4 * (kn + q)) * Hpad];
+#pragma unroll
+        for (int q = 0; q < KCF; ++q) {
+          float b[2][FW];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * F32_STRIDE + f * 16];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int f = 0; f < FW; ++f)
+#pragma unroll
+              for (int m = 0; m < NMAT; ++m) {
+                if (INNER) acc[m][h][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[h][f], a[m][h][q], acc[m][h][f], 0, 0, 0);
+                else acc[m][h][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][h][q], b[h][f], acc[m][h][f], 0, 0, 0);
+              }
+        }
+#pragma unroll
+        for (int m = 0; m < NMAT; ++m)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < KCF; ++q) a[m][h][q] = an[m][h][q];
       }
 #pragma unroll
-      for (int m = 0; m < NMAT; ++m)
+      for (int f = 0; f < FW; ++f) {
+        const int cf = (wf * FW + f) * 16;
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-          for (int q = 0; q < KCF; ++q) a[m][h][q] = an[m][h][q];
-    }
-#pragma unroll
-    for (int f = 0; f < FW; ++f) {
-      const int cf = (wf * FW + f) * 16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 4 * lk + v;  // f32 accumulator row within the 16x16 block
-        int i, col;
-        if (INNER) {
-          col = c0 + cf + row;
-          i = it * 16 + lr;
-        } else {
-          i = it * 16 + row;
-          col = c0 + cf + lr;
-        }
-        if (i < H && col < inner) {
-          const int im = N - 1 - i;
-          const float e0 = acc[0][0][f][v], o0 = acc[0][1][f][v];
-          const float y0 = e0 + o0, y0m = sig0 * (e0 - o0);
-          const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
-          const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
-          dst0[p] = G0 ? (float)(G0[i] * (double)y0) : y0;
-          dst0[pm] = G0 ? (float)(G0[im] * (double)y0m) : y0m;
-          if (NMAT > 1) {
-            const float e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
-            const float y1 = e1 + o1, y1m = sig1 * (e1 - o1);
-            dst1[p] = (float)((G1 ? G1[i] * (double)y1 : (double)y1) + (G10 ? G10[i] * (double)y0 : 0.0));
-            dst1[pm] = (float)((G1 ? G1[im] * (double)y1m : (double)y1m) + (G10 ? G10[im] * (double)y0m : 0.0));
+        for (int v = 0; v < 4; ++v) {
+          const int row = 4 * lk + v;  // f32 accumulator row within the 16x16 block
+          int i, col;
+          if (INNER) {
+            col = c0 + cf + row;
+            i = it * 16 + lr;
+          } else {
+            i = it * 16 + row;
+            col = c0 + cf + lr;
+          }
+          if (i < H && col < inner) {
+            const int im = N - 1 - i;
+            const float e0 = acc[0][0][f][v], o0 = acc[0][1][f][v];
+            const float y0 = e0 + o0, y0m = sig0 * (e0 - o0);
+            const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
+            const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
+            dst0[p] = G0 ? (float)(G0[i] * (double)y0) : y0;
+            dst0[pm] = G0 ? (float)(G0[im] * (double)y0m) : y0m;
+            if (NMAT > 1) {
+              const float e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
+              const float y1 = e1 + o1, y1m = sig1 * (e1 - o1);
+              dst1[p] = (float)((G1 ? G1[i] * (double)y1 : (double)y1) + (G10 ? G10[i] * (double)y0 : 0.0));
+              dst1[pm] = (float)((G1 ? G1[im] * (double)y1m : (double)y1m) + (G10 ? G10[im] * (double)y0m : 0.0));
+            }
           }
         }
       }
     }
-  }
+  };
+  if (NMAXT > 1 && tk.nmat > 1) run(std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>{});
+  else run(std::integral_constant<int, 1>{});
 }
 
 template <int NMAT, bool INNER>

@@ -53,8 +53,9 @@ struct Task {
   int src_sel, src;     // base selector, field index
   int dst_sel, dst0;    // destination of matrix 0
   int dst1;             // destination of matrix 1 (same base as dst0)
+  int nmat;             // operators this task applies (1 or 2)
 };
-constexpr int MAX_TASKS = 48;
+constexpr int MAX_TASKS = 64;
 struct TaskList {
   int n;
   Task t[MAX_TASKS];
@@ -68,6 +69,7 @@ struct Bases {
 struct MixedTask {
   int src_sel, src, src_f32;
   int dst_sel, dst0, dst1;
+  int nmat;             // operators this task applies (1 or 2)
 };
 struct MixedTaskList {
   int n;
@@ -158,7 +160,8 @@ hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskLi
                                  const MixedOps& op0, const MixedOps& op1, const int n[3],
                                  const int npad[3], long long P, const JobSet& js, hipStream_t s);
 hipError_t set_mixed_kernel_attributes();
-// Folded contraction (even N): out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u)
+// Folded contraction (even N): out_0 = g0 . (A_0 u), out_1 = g1 . (A_1 u) + g10 . (A_0 u);
+// nmat = 2 lets each task apply one or two operators (its own nmat)
 hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
                                 const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
                                 long long P, const JobSet& js, hipStream_t s);
