@@ -463,6 +463,8 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->pp.nph = grid->nph;
   c->pp.P = (long long)P;
   c->pp.gamma_ad = phys->gamma_ad;
+  c->pp.gfac = phys->gamma_ad / (phys->gamma_ad - 1.0);
+  c->pp.gm1g = (phys->gamma_ad - 1.0) / phys->gamma_ad;
   c->pp.eta = phys->eta;
   c->pp.cowling = phys->cowling;
   c->pp.gauge_k0 = phys->gauge_k0;

@@ -103,6 +103,7 @@ struct PointParams {
   int nr, nth, nph;
   long long P;
   double gamma_ad, eta;
+  double gfac, gm1g;  // Gamma/(Gamma-1), (Gamma-1)/Gamma
   int cowling, gauge_k0;
   double rho_floor, p_floor;
 };

@@ -77,14 +77,14 @@ struct C2POut {
 };
 
 __device__ C2POut con2prim(double D, const double* S, double tau, const double* B, const Sym& gam,
-                           const Sym& gamu, double G, double rho_fl, double p_fl,
+                           const Sym& gamu, double G, double gm1g, double rho_fl, double p_fl,
                            double zguess) {
   C2POut o;
   double Su[3], Bl[3];
   mv(gamu, S, Su);
   mv(gam, B, Bl);
   const double S2 = dot3(S, Su), B2 = dot3(B, Bl), BS = dot3(B, S), BS2 = BS * BS;
-  const double gf = (G - 1.0) / G;
+  const double gf = gm1g;
   bool bad = !(D > 0.0 && tau + D > 0.0);
   const double Dc = bad ? 1.0 : D, Ec = bad ? 2.0 : tau + D;
   double lo = 0.0, hi = G * Ec + B2 + 1e-300;
@@ -135,13 +135,14 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
     }
   }
   double vl[3];
+  const double iZ = 1.0 / Z, ia = 1.0 / (Z + B2);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) vl[i] = (S[i] + BS * Bl[i] / Z) / (Z + B2);
+  for (int i = 0; i < 3; ++i) vl[i] = (S[i] + BS * Bl[i] * iZ) * ia;
   mv(gamu, vl, o.v);
   const double v2 = dot3(o.v, vl);
-  const double W = 1.0 / sqrt(1.0 - v2);
-  o.rho = Dc / W;
-  o.p = gf * (Z / (W * W) - o.rho);
+  const double iw2 = 1.0 - v2;  // 1/W^2
+  o.rho = Dc * sqrt(iw2);
+  o.p = gf * (Z * iw2 - o.rho);
   o.fail = bad || !(v2 < 1.0) || !(o.rho >= rho_fl) || !(o.p >= p_fl);
   if (o.fail) {
     o.rho = rho_fl;
@@ -154,7 +155,7 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
 // Magnetic quantities for Eulerian field B^i and velocity v^i:
 // W, alpha b^0 = W (B.v), b_i = B_i/W + W (B.v) v_i, b^2 = B^2/W^2 + (B.v)^2.
 struct Mag {
-  double W, ab0, bl[3], b2, vl[3];
+  double W, iW, ab0, bl[3], b2, vl[3];
 };
 
 __device__ __forceinline__ Mag magnetic(const double* v, const double* B, const Sym& gam) {
@@ -162,12 +163,14 @@ __device__ __forceinline__ Mag magnetic(const double* v, const double* B, const 
   double Bl[3];
   mv(gam, v, m.vl);
   mv(gam, B, Bl);
-  m.W = 1.0 / sqrt(1.0 - dot3(v, m.vl));
+  const double iw2 = 1.0 - dot3(v, m.vl);  // 1/W^2
+  m.iW = sqrt(iw2);
+  m.W = 1.0 / m.iW;
   const double Bv = dot3(B, m.vl), B2 = dot3(B, Bl);
   m.ab0 = m.W * Bv;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) m.bl[i] = Bl[i] / m.W + m.W * Bv * m.vl[i];
-  m.b2 = B2 / (m.W * m.W) + Bv * Bv;
+  for (int i = 0; i < 3; ++i) m.bl[i] = Bl[i] * m.iW + m.W * Bv * m.vl[i];
+  m.b2 = B2 * iw2 + Bv * Bv;
   return m;
 }
 
@@ -317,10 +320,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     mv(gam, vg, vgl);
     const double v2 = dot3(vg, vgl);
     if (rg > 0.0 && pg > 0.0 && v2 < 1.0)
-      zg = (rg + pg * pp.gamma_ad / (pp.gamma_ad - 1.0)) / (1.0 - v2);
+      zg = (rg + pg * pp.gfac) / (1.0 - v2);
   }
   const double rho_fl = floors[j], p_fl = floors[pp.nr + j];
-  C2POut c = con2prim(D, S, tau, B, gam, gamu, pp.gamma_ad, rho_fl, p_fl, zg);
+  C2POut c = con2prim(D, S, tau, B, gam, gamu, pp.gamma_ad, pp.gm1g, rho_fl, p_fl, zg);
   prim[idx] = c.rho;
   prim[(size_t)P + idx] = c.p;
   prim[2 * (size_t)P + idx] = c.v[0];
@@ -331,10 +334,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const Mag m = magnetic(c.v, B, gam);
   const double ps = c.p + 0.5 * m.b2;
   const double asg = alpha * sqrtg;
-  const double iW = 1.0 / m.W;
+  const double iW = m.iW, ial = 1.0 / alpha;
+  const double vt[3] = {c.v[0] - beta[0] * ial, c.v[1] - beta[1] * ial, c.v[2] - beta[2] * ial};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double vta = c.v[a] - beta[a] / alpha;
+    const double vta = vt[a];
     double* F = flux + (size_t)(8 * a) * P + idx;
     F[0] = asg * D * vta;
 #pragma unroll
@@ -343,7 +347,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     F[(size_t)4 * P] = asg * (tau * vta + ps * c.v[a] - m.ab0 * B[a] * iW);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double vtk = c.v[k] - beta[k] / alpha;
+      const double vtk = vt[k];
       F[(size_t)(5 + k) * P] = asg * (vta * B[k] - vtk * B[a]);
     }
   }
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
     const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
     const Mag m = magnetic(v, B, gam);
-    const double h = 1.0 + p / rho * pp.gamma_ad / (pp.gamma_ad - 1.0);
+    const double h = 1.0 + p / rho * pp.gfac;
     const double cw = (rho * h + m.b2) * m.W * m.W;
     const double ps = p + 0.5 * m.b2;
 #pragma unroll
