@@ -284,7 +284,8 @@ enum {
   GRMHD_K_DERIV_R = 11,   /* r axis, first + second and first-only tasks in one launch */
   GRMHD_K_DERIV_T = 12,   /* theta axis, likewise                                      */
   GRMHD_K_DERIV_P = 13,   /* phi axis, likewise                                        */
-  GRMHD_K_COUNT = 14
+  GRMHD_K_RICCI = 14,     /* Ricci tensor of the stage state                           */
+  GRMHD_K_COUNT = 15
 };
 
 /* Advance nsteps RK4 steps exactly as grmhd_step, recording a HIP event on

@@ -96,7 +96,7 @@ SIGNATURES = {
 }
 
 KERNEL_KINDS = ["c2p_flux", "deriv_r2", "deriv_r1", "deriv_t2", "deriv_t1", "deriv_p2", "deriv_p1",
-                "rhs_rk", "filter_r", "filter_t", "filter_p", "deriv_r", "deriv_t", "deriv_p"]
+                "rhs_rk", "filter_r", "filter_t", "filter_p", "deriv_r", "deriv_t", "deriv_p", "ricci"]
 
 _lib = None
 

@@ -302,8 +302,10 @@ int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSe
   const bool mixed = c->prec != GRMHD_FP64;
   int rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
   if (rc) return rc;
-  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->pp,
-                       js, c->stream));
+  HIPCHK(launch_ricci(mixed, Uin, sf(c, SC_D1), sf(c, SC_RIC), c->pp, js, c->stream));
+  MARK(rec, GRMHD_K_RICCI);
+  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, sf(c, SC_RIC), c->U, sf(c, SC_ACC), out,
+                       c->pp, js, c->stream));
   MARK(rec, GRMHD_K_RHS_RK);
   return GRMHD_OK;
 }
@@ -666,7 +668,7 @@ int grmhd_profile_step(grmhd_ctx* c, int32_t nsteps, double* ms, int32_t nkinds,
   if (nsteps < 1) return fail(GRMHD_E_ARG, "nsteps < 1");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
   Recorder rec;
-  const size_t per_step = 4 * 8 + 3 + 1;  // 8 launches per stage, 3 filter passes, start
+  const size_t per_step = 4 * 9 + 3 + 1;  // at most 9 launches per stage, 3 filter passes, start
   rec.ev.resize(per_step);
   rec.kind.resize(per_step);
   for (auto& e : rec.ev) HIPCHK(hipEventCreate(&e));

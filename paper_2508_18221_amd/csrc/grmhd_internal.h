@@ -31,7 +31,8 @@ enum : int {
   SC_D2 = 151,    // 33  d_a d_a of second-derivative field s at SC_D2 + 11a + s
   SC_MX = 184,    // 33  mixed (r th, r ph, th ph) at SC_MX + 11m + s
   SC_DF = 217,    // 24  d_a (alpha sqrt(gamma) F^a_v) at SC_DF + 8a + v
-  SC_NFIELDS = 241
+  SC_RIC = 241,   // 6   Ricci tensor R_ij of the stage state
+  SC_NFIELDS = 247
 };
 
 // Resident buffer: fields of P doubles, then operators and small arrays.
@@ -176,8 +177,12 @@ hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* 
 // mode 0: out = L(U_s); 1..4: classic RK4 stage s.  der: derivative arrays
 // (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
-                         const double* K0, const double* Un, double* acc, double* out,
+                         const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s);
+// Ricci tensor R_ij (6 fields of P doubles, symmetric storage) of the stage
+// state from its derivative arrays (FP64 or FP32)
+hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double* R, const PointParams& pp,
+                        const JobSet& js, hipStream_t s);
 // Hamiltonian constraint from FP64 derivative arrays into H (P doubles)
 hipError_t launch_ham(const double* U, const double* der, const double* prim, double* H,
                       const PointParams& pp, hipStream_t s);

@@ -371,6 +371,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                 const DT* __restrict__ der,
                                                 const double* __restrict__ prim,
                                                 const double* __restrict__ K0p,
+                                                const double* __restrict__ Ric,
                                                 const double* Un, double* acc, double* out,
                                                 PointParams pp, JobSet js) {
   const long long P = pp.P;
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     der = shift_ptr(der, jd);
     prim = shift_ptr(prim, jd);
     K0p = shift_ptr(K0p, jd);
+    Ric = shift_ptr(Ric, jd);
     Un = shift_ptr(Un, jd);
     acc = shift_ptr(acc, jd);
     out = shift_ptr(out, jd);
@@ -553,14 +555,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   PHASE();
 
-  // ---- phase 4: Ricci tensor R_ij = Rt_ij + Rphi_ij ---------------------------
+  // ---- phase 4: Ricci tensor (computed by k_ricci) ------------------------------
   Sym R;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) R.m[s] = Ric[(size_t)s * P + idx];
   double dGt[3][3];  // [a][i] = d_a Gt^i
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int i = 0; i < 3; ++i) dGt[a][i] = D1(a, 14 + i);
-  ricci(gt, gtu, Gl, Gu, Gd, dGt, dphi, DD, R);
   PHASE();
 
   // ---- phase 5: D_i D_j alpha, A-tilde contractions, K and A-tilde -------------
@@ -659,6 +662,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #undef LU
 }
 #undef PHASE
+
+// ---------------------------------------------------------------------------
+// Ricci tensor R_ij = Rt_ij + Rphi_ij of the stage state (the heaviest part of
+// the BSSN right-hand side, in a kernel of its own so that the RHS kernel
+// needs fewer live registers): reads gt_ij, d_a phi, d_a gt_ij, d_a Gt^i and
+// the second derivatives of phi and gt_ij; writes 6 fields.
+template <typename DT>
+__global__ __launch_bounds__(256) void k_ricci(const double* __restrict__ Us, const DT* __restrict__ der,
+                                               double* __restrict__ Rout, PointParams pp, JobSet js) {
+  const long long P = pp.P;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P) return;
+  {
+    const long long jd = js.d[blockIdx.y];
+    Us = shift_ptr(Us, jd);
+    der = shift_ptr(der, jd);
+    Rout = shift_ptr(Rout, jd);
+  }
+#define LS(g) ((double)der[(size_t)(g) * P + idx])
+  auto DD = [&](int a, int b, int s) -> double {
+    if (a == b) return LS(O_D2 + 11 * a + s);
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    const int m = (lo == 0) ? (hi == 1 ? 0 : 1) : 2;
+    return LS(O_MX + 11 * m + s);
+  };
+  Sym gt;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) gt.m[s] = Us[(size_t)(1 + s) * P + idx];
+  const Sym gtu = inv_sym(gt, det_sym(gt));
+  double dgt[3][6], Gl[3][6], Gu[3][6], Gd[3], dGt[3][3], dphi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dphi[a] = LS(21 * a);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dgt[a][q] = LS(21 * a + 1 + q);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dGt[a][i] = LS(21 * a + 14 + i);
+  }
+  christoffel(gtu, dgt, Gl, Gu, Gd);
+  Sym R;
+  ricci(gt, gtu, Gl, Gu, Gd, dGt, dphi, DD, R);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) Rout[(size_t)s * P + idx] = R.m[s];
+#undef LS
+}
 
 // ---------------------------------------------------------------------------
 // Hamiltonian constraint H = e^{-4 phi} gt^ij R_ij + 2/3 K^2 - A_ij A^ij - 16 pi E
@@ -809,16 +857,27 @@ hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* 
   return hipGetLastError();
 }
 
+hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double* R, const PointParams& pp,
+                        const JobSet& js, hipStream_t s) {
+  if (js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
+  if (der_f32)
+    hipLaunchKernelGGL(k_ricci<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, (const float*)der, R, pp, js);
+  else
+    hipLaunchKernelGGL(k_ricci<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, (const double*)der, R, pp,
+                       js);
+  return hipGetLastError();
+}
+
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
-                         const double* K0, const double* Un, double* acc, double* out,
+                         const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s) {
   if (mode < 0 || mode > 4 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
   if (der_f32)
     hipLaunchKernelGGL(k_rhs_rk<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, (const float*)der,
-                       prim, K0, Un, acc, out, pp, js);
+                       prim, K0, Ric, Un, acc, out, pp, js);
   else
     hipLaunchKernelGGL(k_rhs_rk<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us,
-                       (const double*)der, prim, K0, Un, acc, out, pp, js);
+                       (const double*)der, prim, K0, Ric, Un, acc, out, pp, js);
   return hipGetLastError();
 }
 
