@@ -70,7 +70,8 @@ __device__ __forceinline__ double dot3(const double* a, const double* b) {
 // and tau + D = Z + B^2 - p - B^2/(2W^2) - (B.S)^2/(2 Z^2) with the ideal-gas
 // p = (Gamma-1)/Gamma (Z/W^2 - D/W).  Newton iteration on the residual with
 // analytic derivative, kept inside a bracket [lo, hi] that shrinks with the
-// sign of the residual (bisection whenever a step leaves it or v^2 >= 1).
+// sign of the residual (bisection whenever a step leaves it or v^2 >= 1);
+// converged once a Newton step is below 1e-12 relative.
 struct C2POut {
   double rho, p, v[3];
   int fail;
@@ -121,11 +122,14 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
         if (f < 0.0) lo = Z;
         else hi = Z;
         zn = Z - f / fp;
-        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
-        if (fabs(zn - Z) <= 1e-15 * zn) {
+        // a Newton step this small leaves an error of the order of its square:
+        // accept it before the bracket test (the converged step may land on a
+        // bracket end, which must not trigger a bisection)
+        if (fabs(zn - Z) <= 1e-12 * zn) {
           Z = zn;
           break;
         }
+        if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
       }
       if (!(zn > lo && zn < hi)) {  // bracket collapsed onto adjacent doubles
         Z = hi;
