@@ -285,7 +285,10 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
 // NMAXT = 1: every task applies one operator (F0); NMAXT = 2: each task
 // applies one or two operators (its nmat), so the first-and-second and the
 // first-only passes of an axis share one launch.
-template <int NMAXT, bool INNER, int WI>
+//
+// TC: columns per tile (64, or 32 for the strided axes at N = 128, where a
+// 64-column tile's LDS would hold two workgroups per CU).
+template <int NMAXT, bool INNER, int WI, int TC = TILE_COLS>
 __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, const double* __restrict__ F0,
                                                        const double* __restrict__ F1,
                                                        const double* __restrict__ G0,
@@ -293,7 +296,9 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
                                                        const double* __restrict__ G10, double sig0,
                                                        double sig1, int N, int Hpad, int inner, int slab,
                                                        long long P, JobSet js) {
-  extern __shared__ double tile[];  // [2 Hpad][LDS_STRIDE]: s rows, then d rows
+  extern __shared__ double tile[];  // [2 Hpad][LS]: s rows, then d rows
+  static_assert(TC == TILE_COLS || (!INNER && TC == 32 && WI >= 2), "32-column tiles: strided axes, WI >= 2");
+  constexpr int LS = TC + 8;  // row stride in doubles: rows 16 banks apart
   const Task tk = tl.t[blockIdx.z % tl.n];
   const long long jd = js.d[blockIdx.z / tl.n];
   F0 = shift_ptr(F0, jd);
@@ -304,7 +309,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int H = N >> 1;
-  const int c0 = blockIdx.x * TILE_COLS;
+  const int c0 = blockIdx.x * TC;
   const size_t off = (size_t)blockIdx.y * (size_t)slab;
   const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
   double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
@@ -312,10 +317,10 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 
   // ---- stage and fold the input tile ----------------------------------------
   constexpr int LOADS = 8;  // pairs per thread in flight
-  const int total = Hpad * TILE_COLS;
+  const int total = Hpad * TC;
   if (INNER) {
     // 64 consecutive lines of N doubles; pair (k, N-1-k) of line `line`
-    const int ncols = min(TILE_COLS, inner - c0);
+    const int ncols = min(TC, inner - c0);
     const double* __restrict__ s = src + (size_t)c0 * N;
     for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
       double lo[LOADS], hi[LOADS];
@@ -332,8 +337,8 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
         const int e = e0 + q * 256;
         if (e < total) {
           const int line = e / Hpad, k = e - line * Hpad;
-          tile[k * LDS_STRIDE + line] = lo[q] + hi[q];
-          tile[(Hpad + k) * LDS_STRIDE + line] = lo[q] - hi[q];
+          tile[k * LS + line] = lo[q] + hi[q];
+          tile[(Hpad + k) * LS + line] = lo[q] - hi[q];
         }
       }
     }
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 #pragma unroll
       for (int q = 0; q < LOADS; ++q) {
         const int e = e0 + q * 256;
-        const int k = e >> 6, c = e & 63;
+        const int k = e / TC, c = e % TC;
         const bool ok = e < total && k < H && c0 + c < inner;
         lo[q] = ok ? src[(size_t)k * inner + c0 + c] : 0.0;
         hi[q] = ok ? src[(size_t)(N - 1 - k) * inner + c0 + c] : 0.0;
@@ -352,8 +357,8 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
       for (int q = 0; q < LOADS; ++q) {
         const int e = e0 + q * 256;
         if (e < total) {
-          tile[(e >> 6) * LDS_STRIDE + (e & 63)] = lo[q] + hi[q];
-          tile[(Hpad + (e >> 6)) * LDS_STRIDE + (e & 63)] = lo[q] - hi[q];
+          tile[(e / TC) * LS + (e % TC)] = lo[q] + hi[q];
+          tile[(Hpad + e / TC) * LS + (e % TC)] = lo[q] - hi[q];
         }
       }
     }
@@ -364,7 +369,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   auto run = [&](auto nm) {
     constexpr int NMAT = decltype(nm)::value;
     constexpr int KCF = NMAT > 1 ? 2 : 4;  // k-steps of operator fragments per chunk
-    constexpr int FW = WI;
+    constexpr int FW = TC * WI / 64;  // 16-column blocks per wave
     const int T = Hpad >> 4;
     const int wi = wave % WI, wf = wave / WI;
     const int lr = lane & 15, lk = lane >> 4;
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
       const double* __restrict__ ap[NMAT];
       ap[0] = F0 + (size_t)lk * Hpad + it * 16 + lr;
       if (NMAT > 1) ap[NMAT - 1] = F1 + (size_t)lk * Hpad + it * 16 + lr;
-      const double* tp = tile + lk * LDS_STRIDE + wf * FW * 16 + lr;
+      const double* tp = tile + lk * LS + wf * FW * 16 + lr;
       double a[NMAT][2][KCF];
 #pragma unroll
       for (int m = 0; m < NMAT; ++m)
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * LDS_STRIDE + f * 16];
+            for (int f = 0; f < FW; ++f) b[h][f] = tp[(h * Hpad + 4 * (kc + q)) * LS + f * 16];
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -460,10 +465,10 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   else run(std::integral_constant<int, 1>{});
 }
 
-template <int NMAT, bool INNER, int WI>
+template <int NMAT, bool INNER, int WI, int TC = TILE_COLS>
 static hipError_t set_fold_attr() {
-  const int max_lds = 256 * LDS_STRIDE * (int)sizeof(double);  // 2 Hpad <= 256
-  return hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI>,
+  const int max_lds = 256 * (TC + 8) * (int)sizeof(double);  // 2 Hpad <= 256
+  return hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI, TC>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
 }
 
@@ -478,6 +483,8 @@ hipError_t set_fold_kernel_attributes() {
   FA(1, false)
   FA(2, false)
 #undef FA
+  if (e == hipSuccess) e = set_fold_attr<1, false, 4, 32>();
+  if (e == hipSuccess) e = set_fold_attr<2, false, 4, 32>();
   return e;
 }
 
@@ -503,9 +510,11 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     outer = 1;
     slab = 0;
   }
-  dim3 grid((inner + TILE_COLS - 1) / TILE_COLS, outer, tl.n * js.n);
-  const size_t lds = (size_t)2 * Hpad * LDS_STRIDE * sizeof(double);
   const int T = Hpad >> 4;
+  const bool narrow = axis != 0 && T == 4;  // N = 128 on a strided axis: 32-column tiles
+  const int tc = narrow ? 32 : TILE_COLS;
+  dim3 grid((inner + tc - 1) / tc, outer, tl.n * js.n);
+  const size_t lds = (size_t)2 * Hpad * (tc + 8) * sizeof(double);
 #define LF(NM, IN, W)                                                                                     \
   hipLaunchKernelGGL((k_contract_fold<NM, IN, W>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, op0.g, \
                      op1.g, g10, op0.sigma, op1.sigma, N, Hpad, inner, slab, P, js)
@@ -515,11 +524,17 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     else if (T >= 2) LF(NM, IN, 2); \
     else LF(NM, IN, 1);             \
   } while (0)
+#define LN(NM)                                                                                           \
+  hipLaunchKernelGGL((k_contract_fold<NM, false, 4, 32>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, \
+                     op0.g, op1.g, g10, op0.sigma, op1.sigma, N, Hpad, inner, slab, P, js)
   if (axis == 0) {
     if (nmat == 1) LFW(1, true); else LFW(2, true);
+  } else if (narrow) {
+    if (nmat == 1) LN(1); else LN(2);
   } else {
     if (nmat == 1) LFW(1, false); else LFW(2, false);
   }
+#undef LN
 #undef LFW
 #undef LF
   return hipGetLastError();
