@@ -28,6 +28,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int TILE_COLS = 64;
 constexpr int LDS_STRIDE = 72;  // doubles: rows 16 banks apart, so the 4 rows a
                                 // fragment read touches hit each bank twice
+constexpr int NARROW = 32;     // tile columns on the strided axes at N = 128
 constexpr int KC = 4;           // k-steps (of 4) of operator fragments held in registers
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
                                                        double sig1, int N, int Hpad, int inner, int slab,
                                                        long long P, JobSet js) {
   extern __shared__ double tile[];  // [2 Hpad][LS]: s rows, then d rows
-  static_assert(TC == TILE_COLS || (!INNER && TC == 32 && WI >= 2), "32-column tiles: strided axes, WI >= 2");
+  static_assert(TC == TILE_COLS || (!INNER && TC * WI >= 64), "narrow tiles: strided axes, TC * WI >= 64");
   constexpr int LS = TC + 8;  // row stride in doubles: rows 16 banks apart
   const Task tk = tl.t[blockIdx.z % tl.n];
   const long long jd = js.d[blockIdx.z / tl.n];
@@ -483,8 +484,8 @@ hipError_t set_fold_kernel_attributes() {
   FA(1, false)
   FA(2, false)
 #undef FA
-  if (e == hipSuccess) e = set_fold_attr<1, false, 4, 32>();
-  if (e == hipSuccess) e = set_fold_attr<2, false, 4, 32>();
+  if (e == hipSuccess) e = set_fold_attr<1, false, 4, NARROW>();
+  if (e == hipSuccess) e = set_fold_attr<2, false, 4, NARROW>();
   return e;
 }
 
@@ -512,7 +513,7 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
   }
   const int T = Hpad >> 4;
   const bool narrow = axis != 0 && T == 4;  // N = 128 on a strided axis: 32-column tiles
-  const int tc = narrow ? 32 : TILE_COLS;
+  const int tc = narrow ? NARROW : TILE_COLS;
   dim3 grid((inner + tc - 1) / tc, outer, tl.n * js.n);
   const size_t lds = (size_t)2 * Hpad * (tc + 8) * sizeof(double);
 #define LF(NM, IN, W)                                                                                     \
@@ -525,7 +526,7 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     else LF(NM, IN, 1);             \
   } while (0)
 #define LN(NM)                                                                                           \
-  hipLaunchKernelGGL((k_contract_fold<NM, false, 4, 32>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, \
+  hipLaunchKernelGGL((k_contract_fold<NM, false, 4, NARROW>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, \
                      op0.g, op1.g, g10, op0.sigma, op1.sigma, N, Hpad, inner, slab, P, js)
   if (axis == 0) {
     if (nmat == 1) LFW(1, true); else LFW(2, true);
