@@ -36,8 +36,12 @@
  * operators; "scratch": stage temporaries) that grmhd_create() borrows for
  * the context's lifetime.  The library never allocates or frees device
  * memory.  Every call that takes a device pointer expects memory on the
- * context's device.  All work is enqueued on the caller's HIP stream; calls
- * marked "syncs" wait for that stream.
+ * context's device.  All work is enqueued on the caller's HIP stream; a
+ * right-hand side evaluation also forks part of its work (primitive recovery,
+ * flux derivatives) to a stream the context owns (default priority) and
+ * joins it back into the caller's stream before its last launch, so the
+ * caller's stream alone orders every result.  Calls marked "syncs" wait for
+ * that stream.
  *
  * Errors: functions return GRMHD_OK (0) or a negative code; the thread-local
  * message of the last failure is grmhd_last_error().  Device-side faults
@@ -140,7 +144,8 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
                  void* dev_resident, void* dev_scratch, void* hip_stream,
                  grmhd_ctx** out);
 
-/* Waits for the stream and releases host metadata (never device memory). */
+/* Waits for the streams, releases the context's own stream and events and
+ * the host metadata (never device memory). */
 int grmhd_destroy(grmhd_ctx* ctx);
 
 /* Kerr-Schild background in BSSN variables + magnetised Michel flow + seeded
@@ -270,26 +275,32 @@ const char* grmhd_server_last_error(void);
 
 /* ---- timing ---------------------------------------------------------------- */
 
-/* Launch kinds of one RK4 step (4 stages x 8 launches + 3 filter launches). */
+/* Launch kinds of one RK4 step (per stage: con2prim, 3 flux-derivative and
+ * 3 (folded forms) or 6 state-derivative launches, Ricci, RHS; then 3 filter
+ * launches). */
 enum {
   GRMHD_K_C2P_FLUX = 0,   /* con2prim + densitised fluxes                        */
   GRMHD_K_DERIV_R2 = 1,   /* r axis, first + second derivative (11 fields)        */
-  GRMHD_K_DERIV_R1 = 2,   /* r axis, first derivative (10 fields + 8 fluxes)      */
+  GRMHD_K_DERIV_R1 = 2,   /* r axis, first derivative (10 fields)                 */
   GRMHD_K_DERIV_T2 = 3,   /* theta axis, first + second                            */
-  GRMHD_K_DERIV_T1 = 4,   /* theta axis, first (10 + 11 mixed + 8 fluxes)          */
+  GRMHD_K_DERIV_T1 = 4,   /* theta axis, first (10 + 11 mixed)                     */
   GRMHD_K_DERIV_P2 = 5,   /* phi axis, first + second                              */
-  GRMHD_K_DERIV_P1 = 6,   /* phi axis, first (10 + 22 mixed + 8 fluxes)            */
+  GRMHD_K_DERIV_P1 = 6,   /* phi axis, first (10 + 22 mixed)                       */
   GRMHD_K_RHS_RK = 7,     /* BSSN + Valencia RHS and RK4 stage update              */
   GRMHD_K_FILTER_R = 8, GRMHD_K_FILTER_T = 9, GRMHD_K_FILTER_P = 10,
   GRMHD_K_DERIV_R = 11,   /* r axis, first + second and first-only tasks in one launch */
   GRMHD_K_DERIV_T = 12,   /* theta axis, likewise                                      */
   GRMHD_K_DERIV_P = 13,   /* phi axis, likewise                                        */
   GRMHD_K_RICCI = 14,     /* Ricci tensor of the stage state                           */
-  GRMHD_K_COUNT = 15
+  GRMHD_K_DFLUX_R = 15,   /* r derivatives of the 8 densitised fluxes                  */
+  GRMHD_K_DFLUX_T = 16,   /* theta derivatives of the fluxes                           */
+  GRMHD_K_DFLUX_P = 17,   /* phi derivatives of the fluxes                             */
+  GRMHD_K_COUNT = 18
 };
 
-/* Advance nsteps RK4 steps exactly as grmhd_step, recording a HIP event on
- * the context stream after every launch; ms[k] (nkinds >= GRMHD_K_COUNT)
+/* Advance nsteps RK4 steps as grmhd_step does, but with every launch in
+ * order on the context stream (no fork to the context's own stream), and
+ * record a HIP event after every launch; ms[k] (nkinds >= GRMHD_K_COUNT)
  * receives the average duration in milliseconds of launch kind k (time
  * between the event before and after it) and counts[k] (optional) the
  * number of launches of that kind.  Syncs. */

@@ -96,7 +96,8 @@ SIGNATURES = {
 }
 
 KERNEL_KINDS = ["c2p_flux", "deriv_r2", "deriv_r1", "deriv_t2", "deriv_t1", "deriv_p2", "deriv_p1",
-                "rhs_rk", "filter_r", "filter_t", "filter_p", "deriv_r", "deriv_t", "deriv_p", "ricci"]
+                "rhs_rk", "filter_r", "filter_t", "filter_p", "deriv_r", "deriv_t", "deriv_p", "ricci",
+                "dflux_r", "dflux_t", "dflux_p"]
 
 _lib = None
 

@@ -2,14 +2,17 @@
 // state transfer, the RHS pipeline, RK4 stepping with the post-step filter,
 // diagnostics.  Declarations and contracts: include/grmhd.h.
 //
-// One RHS evaluation (per RK stage) on the caller's stream:
-//   1. k_c2p_flux           con2prim + 24 densitised flux arrays
-//   2. r pass   (2 launches) d_r, d_rr of 11 fields; d_r of 10 fields, 8 r-fluxes
-//   3. th pass  (2 launches) d_th, d_thth; d_th of 10 fields, of the 11 d_r
-//                            arrays (mixed r-th) and of 8 th-fluxes
-//   4. ph pass  (2 launches) d_ph, d_phph; d_ph of 10 fields, of the 11 d_r and
-//                            11 d_th arrays (mixed) and of 8 ph-fluxes
-//   5. k_rhs_rk             BSSN + Valencia RHS, boundary freeze, RK4 update
+// One RHS evaluation (per RK stage), forked from the caller's stream:
+//   side stream:    k_c2p_flux (con2prim + 24 densitised flux arrays), then
+//                   d_r, d_th, d_ph of the 8 fluxes of each direction
+//   caller's stream: r pass   d_r, d_rr of 11 fields; d_r of 10 fields
+//                    th pass  d_th, d_thth; d_th of 10 fields and of the 11
+//                             d_r arrays (mixed r-th)
+//                    ph pass  d_ph, d_phph; d_ph of 10 fields and of the 11
+//                             d_r and 11 d_th arrays (mixed)
+//                    k_ricci  Ricci tensor
+//                    (join)   k_rhs_rk: BSSN + Valencia RHS, boundary freeze,
+//                             RK4 update
 // After the fourth stage the filter runs as three contraction passes.
 #include <math.h>
 #include <stdio.h>
@@ -124,6 +127,11 @@ struct grmhd_ctx {
   char* res;
   double* scr;
   hipStream_t stream;
+  // second stream of a stage: primitive recovery and the flux derivatives run
+  // there beside the state derivatives and the Ricci tensor (fork and join
+  // events on the context stream)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device;
   double *U, *K0, *prim, *fail;
   const double* mats[3][3];
@@ -207,21 +215,21 @@ L select_tasks(const L& tl, int nmat) {
 // tasks (op0); the folded kernel takes them in one launch, the full kernel in
 // one launch per kind.
 hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const TaskList& tl,
-                    const Bases& B, const JobSet& js) {
+                    const Bases& B, const JobSet& js, hipStream_t st) {
   const bool pair_ok = nmat == 1 ? !(axis == 0 && op0 == OP_D2) : (op0 == OP_D1 && op1 == OP_D2);
   if (c->ops.fold[axis] && pair_ok) {
     const double* g10 = (axis == 0 && nmat == 2) ? c->gr + 2 * (size_t)c->grid.nr : nullptr;
     return launch_contract_fold(axis, nmat, tl, B, c->fop[axis][op0], c->fop[axis][op1], g10, c->ops.n,
-                                c->ops.hpad, (long long)c->L.P, js, c->stream);
+                                c->ops.hpad, (long long)c->L.P, js, st);
   }
   if (nmat == 1)
     return launch_contract(axis, 1, tl, B, c->mats[axis][op0], c->mats[axis][op0], c->ops.n, c->ops.npad,
-                           (long long)c->L.P, js, c->stream);
+                           (long long)c->L.P, js, st);
   hipError_t e = launch_contract(axis, 2, select_tasks(tl, 2), B, c->mats[axis][op0], c->mats[axis][op1],
-                                 c->ops.n, c->ops.npad, (long long)c->L.P, js, c->stream);
+                                 c->ops.n, c->ops.npad, (long long)c->L.P, js, st);
   if (e != hipSuccess) return e;
   return launch_contract(axis, 1, select_tasks(tl, 1), B, c->mats[axis][op0], c->mats[axis][op0], c->ops.n,
-                         c->ops.npad, (long long)c->L.P, js, c->stream);
+                         c->ops.npad, (long long)c->L.P, js, st);
 }
 
 
@@ -230,13 +238,14 @@ hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const Ta
 // block of the scratch buffer (field g of the block at float offset g P).
 // Selectors: 0 = stage input state (FP64), 1 = FP32 derivative block,
 // 2 = scratch (FP64 fluxes).  Derivative indices are relative to SC_D1.
+// State derivatives (first, second and mixed) of the stage input:
 int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
   Bases B;
   B.b[0] = const_cast<double*>(Uin);
   B.b[1] = sf(c, SC_D1);
   B.b[2] = c->scr;
   B.b[3] = nullptr;
-  const int o2 = SC_D2 - SC_D1, omx = SC_MX - SC_D1, odf = SC_DF - SC_D1;
+  const int o2 = SC_D2 - SC_D1, omx = SC_MX - SC_D1;
   for (int a = 0; a < 3; ++a) {
     MixedTaskList tl;
     tl.n = 0;
@@ -248,7 +257,6 @@ int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* re
       for (int s = 0; s < ND2; ++s) addm(tl, 1, D2_FIELD[s], 1, 1, omx + 11 + s);
       for (int s = 0; s < ND2; ++s) addm(tl, 1, 21 + D2_FIELD[s], 1, 1, omx + 22 + s);
     }
-    for (int v = 0; v < 8; ++v) addm(tl, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
     if (c->prec == GRMHD_MIX_FP32 && c->ops.fold[a]) {  // folded FP32 form, one launch per axis
       const double* g10 = a == 0 ? c->gr + 2 * (size_t)c->grid.nr : nullptr;
       HIPCHK(launch_contract_f32_fold(a, 2, tl, B, c->fop32[a][0], c->fop32[a][1], g10, c->ops.n, c->ops.hpad,
@@ -266,7 +274,30 @@ int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* re
   return GRMHD_OK;
 }
 
-// FP64 derivative passes (selectors: 0 = stage input state, 1 = scratch).
+// Reduced-precision derivatives of the densitised fluxes, on stream st.
+int mixed_flux_derivs(grmhd_ctx* c, const JobSet& js, Recorder* rec, hipStream_t st) {
+  Bases B;
+  B.b[0] = nullptr;
+  B.b[1] = sf(c, SC_D1);
+  B.b[2] = c->scr;
+  B.b[3] = nullptr;
+  const int odf = SC_DF - SC_D1;
+  for (int a = 0; a < 3; ++a) {
+    MixedTaskList tl;
+    tl.n = 0;
+    for (int v = 0; v < 8; ++v) addm(tl, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
+    if (c->prec == GRMHD_MIX_FP32 && c->ops.fold[a])
+      HIPCHK(launch_contract_f32_fold(a, 1, tl, B, c->fop32[a][0], c->fop32[a][0], nullptr, c->ops.n,
+                                      c->ops.hpad, (long long)c->L.P, js, st));
+    else
+      HIPCHK(launch_contract_mixed(c->prec, a, 1, tl, B, c->mops[a][0], c->mops[a][0], c->ops.n, c->ops.npad,
+                                   (long long)c->L.P, js, st));
+    if (rec) HIPCHK(rec->mark(GRMHD_K_DFLUX_R + a, st));
+  }
+  return GRMHD_OK;
+}
+
+// FP64 state derivatives (selectors: 0 = stage input state, 1 = scratch).
 int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
   Bases B;
   B.b[0] = const_cast<double*>(Uin);
@@ -286,24 +317,54 @@ int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec
       for (int s = 0; s < ND2; ++s) add(tl, 1, SC_D1 + D2_FIELD[s], 1, SC_MX + 11 + s);
       for (int s = 0; s < ND2; ++s) add(tl, 1, SC_D1 + 21 + D2_FIELD[s], 1, SC_MX + 22 + s);
     }
-    for (int v = 0; v < 8; ++v) add(tl, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
-    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, tl, B, js));
+    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, tl, B, js, c->stream));
     MARK(rec, GRMHD_K_DERIV_R + a);
   }
   return GRMHD_OK;
 }
 
+// FP64 derivatives of the densitised fluxes, on stream st.
+int fp64_flux_derivs(grmhd_ctx* c, const JobSet& js, Recorder* rec, hipStream_t st) {
+  Bases B;
+  B.b[0] = nullptr;
+  B.b[1] = c->scr;
+  B.b[2] = (double*)c->res;
+  B.b[3] = nullptr;
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    for (int v = 0; v < 8; ++v) add(tl, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, js, st));
+    if (rec) HIPCHK(rec->mark(GRMHD_K_DFLUX_R + a, st));
+  }
+  return GRMHD_OK;
+}
+
 // One RHS evaluation (+ RK stage update for mode >= 1) of the jobs in js,
-// addressed through context c (the first job).
+// addressed through context c (the first job).  Primitive recovery and the
+// flux derivatives run on the side stream while the state derivatives and the
+// Ricci tensor run on the context stream; the RHS kernel waits for both.  A
+// profiled evaluation (rec set) runs every launch in order on the context
+// stream so that each launch is timed alone.
 int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSet& js,
              Recorder* rec = nullptr) {
-  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, c->stream));
-  MARK(rec, GRMHD_K_C2P_FLUX);
+  const bool split = rec == nullptr;
+  hipStream_t fs = split ? c->side : c->stream;
+  if (split) {
+    HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  }
   const bool mixed = c->prec != GRMHD_FP64;
-  int rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
+  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, fs));
+  if (rec) HIPCHK(rec->mark(GRMHD_K_C2P_FLUX, fs));
+  int rc = mixed ? mixed_flux_derivs(c, js, rec, fs) : fp64_flux_derivs(c, js, rec, fs);
+  if (rc) return rc;
+  if (split) HIPCHK(hipEventRecord(c->ev_join, c->side));
+  rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
   if (rc) return rc;
   HIPCHK(launch_ricci(mixed, Uin, sf(c, SC_D1), sf(c, SC_RIC), c->pp, js, c->stream));
   MARK(rec, GRMHD_K_RICCI);
+  if (split) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
   HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, sf(c, SC_RIC), c->U, sf(c, SC_ACC), out,
                        c->pp, js, c->stream));
   MARK(rec, GRMHD_K_RHS_RK);
@@ -323,7 +384,7 @@ int filter_state(grmhd_ctx* c, const JobSet& js, Recorder* rec = nullptr) {
     TaskList tl;
     tl.n = 0;
     for (int f = 0; f < NF; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
-    HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B, js));
+    HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B, js, c->stream));
     MARK(rec, GRMHD_K_FILTER_R + a);
   }
   return GRMHD_OK;
@@ -349,6 +410,17 @@ int one_step(grmhd_ctx* c, Recorder* rec) {
   return GRMHD_OK;
 }
 
+void release_streams(grmhd_ctx* c) {
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  c->ev_fork = c->ev_join = nullptr;
+  c->side = nullptr;
+}
+
 int prime_guesses(grmhd_ctx* c) {
   HIPCHK(hipMemsetAsync(c->prim, 0, 5 * c->L.P * sizeof(double), c->stream));
   HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->floors, c->pp, single(c), c->stream));
@@ -365,7 +437,7 @@ int compute_k0(grmhd_ctx* c) {
     TaskList tl;
     tl.n = 0;
     add(tl, 0, 17, 1, SC_D1 + 21 * a + 17);
-    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, single(c)));
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, single(c), c->stream));
   }
   HIPCHK(launch_k0(c->U, c->scr, c->K0, c->pp, c->stream));
   return GRMHD_OK;
@@ -418,6 +490,16 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   if (ge != hipSuccess) {
     delete c;
     return fail(GRMHD_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(ge));
+  }
+  {
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      release_streams(c);
+      delete c;
+      return fail(GRMHD_E_DEVICE, std::string("stream/event create: ") + hipGetErrorString(e));
+    }
   }
   build_operators(*grid, phys->cfl, &c->ops);
   // atmosphere floors rho_floor r^-3/2 and p_floor r^-5/2 at the radial nodes
@@ -516,6 +598,7 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
     e = hipMemcpyAsync(c->wth, c->ops.wth.data(), grid->nth * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
+    release_streams(c);
     delete c;
     return fail(GRMHD_E_DEVICE, std::string("create: ") + hipGetErrorString(e));
   }
@@ -526,6 +609,7 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
 int grmhd_destroy(grmhd_ctx* c) {
   if (!c) return GRMHD_OK;
   hipError_t e = hipStreamSynchronize(c->stream);
+  release_streams(c);
   delete c;
   if (e != hipSuccess) return fail(GRMHD_E_DEVICE, std::string("destroy: ") + hipGetErrorString(e));
   return GRMHD_OK;
@@ -668,7 +752,7 @@ int grmhd_profile_step(grmhd_ctx* c, int32_t nsteps, double* ms, int32_t nkinds,
   if (nsteps < 1) return fail(GRMHD_E_ARG, "nsteps < 1");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
   Recorder rec;
-  const size_t per_step = 4 * 9 + 3 + 1;  // at most 9 launches per stage, 3 filter passes, start
+  const size_t per_step = 4 * 14 + 3 + 1;  // at most 14 launches per stage, 3 filter passes, start
   rec.ev.resize(per_step);
   rec.kind.resize(per_step);
   for (auto& e : rec.ev) HIPCHK(hipEventCreate(&e));
@@ -721,7 +805,7 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     TaskList tl;
     tl.n = 0;
     add(tl, 0, 29 + a, 1, SC_D1 + 21 * a + a);
-    hipError_t e = contract(c, a, 1, OP_D1, OP_D1, tl, B, single(c));
+    hipError_t e = contract(c, a, 1, OP_D1, OP_D1, tl, B, single(c), c->stream);
     if (e != hipSuccess) return fail(GRMHD_E_DEVICE, hipGetErrorString(e));
   }
   int nb = 0;
@@ -776,7 +860,7 @@ int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* d
     TaskList tl;
     tl.n = 0;
     for (int f = f0; f < nfields && f < f0 + MAX_TASKS; ++f) add(tl, 0, f, 1, f);
-    HIPCHK(contract(c, axis, 1, o, o, tl, B, single(c)));
+    HIPCHK(contract(c, axis, 1, o, o, tl, B, single(c), c->stream));
   }
   return GRMHD_OK;
 }
