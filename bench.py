@@ -217,7 +217,8 @@ def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
 def traffic_probe(w, torch, Solver, make_grid, make_phys):
     """Workload for the HBM traffic counters (run under rocprofv3 --pmc): one
     plain device copy of 512 MiB (the counters' scale reference: 512 MiB read,
-    512 MiB written) followed by one FP64 RK4 step of the workload."""
+    512 MiB written) followed by one FP64 RK4 step of the workload, its
+    launches in order on one stream (the profiled form of the step)."""
     n = 64 * 1024 * 1024
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -226,7 +227,7 @@ def traffic_probe(w, torch, Solver, make_grid, make_phys):
     torch.cuda.synchronize()
     s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]))
     s.init_state()
-    s.step(1)
+    s.profile_step(1)  # every launch in order on one stream
     torch.cuda.synchronize()
     s.close()
     print(json.dumps({"traffic_probe": True, "copy_bytes_each_way": n * 8, "steps": 1}), flush=True)

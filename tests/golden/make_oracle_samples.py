@@ -6,7 +6,7 @@ Calls only the oracle and the seeded workload definitions.  Run from the
 repository root (tens of minutes of CPU at full size):
 
     python tests/golden/make_oracle_samples.py ks_michel_64x64x128 10
-    python tests/golden/make_oracle_samples.py ks_torus_128x96x192 4
+    python tests/golden/make_oracle_samples.py ks_torus_128x96x192 10
 """
 
 import json
