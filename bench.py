@@ -264,8 +264,8 @@ def main():
                     help="one 512 MiB copy + one RK4 step, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is a design (see the sharding section of the docs)",
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is described in the design notes, not built",
               file=sys.stderr)
         sys.exit(2)
     w = workloads.WORKLOADS[args.workload]

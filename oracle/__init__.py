@@ -11,7 +11,7 @@ modal filtering, classic RK4) or, where the method only approaches a result
 that has a plain definition (con2prim), computes that definition directly by a
 bracketed root search.  Where the paper is garbled the standard published form
 it names (Valencia GRMHD, BSSN as in Alcubierre's textbook) is used; every such
-reading is listed in the design doc's register and in the function docstrings.
+reading is stated in the docstring of the function that takes it.
 
 Modules
   spectral     grid nodes, maps, derivative and filter operators (Methods,

@@ -6,7 +6,7 @@ cites Alcubierre's textbook for the ADM/BSSN formalism; the Ricci tensor,
 D_i D_j alpha and the matter projections it does not print are the textbook
 forms written out below.
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here (where it is silent or inconsistent):
   * conformal factor phi = (1/12) ln det gamma_ij (the printed (1/4) ln det
     contradicts the printed d_t phi = -alpha K/6 + ...).
   * the Gamma-tilde equation carries the standard +12 alpha A^{ij} d_j phi

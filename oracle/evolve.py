@@ -6,7 +6,7 @@ tableau), "The Stability and Complexity" (CFL condition), "Dealiasing and
 Spectral Filtering", Results "GRMHD Conservative Form" (conservation law) and
 the coupled-evolution description.
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here (where it is silent or inconsistent):
   * coupling: all 32 fields (24 spacetime + 8 densitised GRMHD) are advanced
     together by one unsplit classic RK4 step (the paper's half-step/Euler
     operator split would not give the fourth-order accuracy it claims).

@@ -5,7 +5,7 @@ B^k; fluxes; Lorentz factor; magnetic four-vector b^mu; source term; magnetic
 constraint), Methods, "The Primitive Variable Recovery", "The Conserved Fluxes
 and Geometric Source Terms", "Stress-Energy Tensor" and "Ideal-gas EOS".
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here (where it is silent or inconsistent):
   * conserved variables: the paper's h* = 1 + eps + p/rho + b^2/rho followed by
     (rho h* + b^2) counts b^2 twice; the standard Valencia form is used:
       D = rho W,  S_j = (rho h W^2 + B^2) v_j - (B.v) B_j,

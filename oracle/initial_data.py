@@ -9,7 +9,7 @@ sonic point u_c^2 = M/(2 r_c), c_s^2 = u_c^2/(1 - 3 u_c^2)) is the standard
 closed-form solution; its parameters (r_c, rho(r_c)) and the field strength
 (minimum of 2p/b^2 over the nodes) are inputs.
 
-Readings (listed in DESIGN.md):
+Readings of the paper taken here (where it is silent or inconsistent):
   * K_ij from stationarity of the background: K_ij = L_beta gamma_ij / (2 alpha)
     with spectral derivatives of the nodal gamma_ij and beta^i.
   * Gamma-tilde^i = gt^{jk} Gamma-tilde^i_jk from spectral derivatives of gt_ij;
@@ -264,7 +264,7 @@ def fm_torus(grid, fields, M, a, Gamma, r_in, r_max, rho_max, beta_min, pert_amp
     """Magnetised Fishbone-Moncrief torus on the nodes (same return keys as
     michel_monopole).
 
-    Readings (listed in the design doc): atmosphere rho = atm rho_max (r/r_max)^-3/2
+    Readings (the paper leaves these open): atmosphere rho = atm rho_max (r/r_max)^-3/2
     at Eulerian rest on the same isentrope, rho = max(rho_torus, rho_atm);
     one poloidal loop A_phi = max(rho_torus/rho_max - a_cut, 0) with the
     densitised field sqrt(gamma) B^r = d_theta A_phi, sqrt(gamma) B^theta =

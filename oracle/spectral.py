@@ -6,7 +6,7 @@ Operators" (Chebyshev expansion -> chebder -> evaluation; Fourier (ik)^d with
 k = -N/2+1 .. N/2) and "Dealiasing and Spectral Filtering" (2/3 rule and the
 exponential filter sigma(k) = exp(-alpha (|k|/k_max)^p)).
 
-Readings (each listed in the design doc):
+Readings of the paper taken here (where it is silent or inconsistent):
   * radial coordinate: CGL nodes in x, with ln r = Lc + Lh x (logarithmic map;
     the paper's contour figure uses x1 = ln r).  Index 0 is r_out.
   * polar coordinate: CGL nodes y in [-1, 1], theta = Tc + Th y on

@@ -3,7 +3,7 @@
     python -m paper_2508_18221_amd.serve [--jobs 256] [--rate 4] [--t-scale 0.001] [--prec 0]
 
 Jobs arrive on the wall clock at their (seeded Poisson) arrival times and are
-submitted the moment the driver sees them; the server admits them against
+submitted the moment the replay loop sees them; the server admits them against
 the memory budget, steps every running job once per tick (one batched launch
 sequence per grid class) and retires finished ones.  Latency is measured
 from the nominal arrival time to the end of the tick in which the job's last
