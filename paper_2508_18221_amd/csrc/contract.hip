@@ -19,6 +19,7 @@
 // (the f64 accumulator interleaves rows by 4, unlike the f32 16x16x4 form).
 #include "grmhd_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace grmhd {
@@ -466,6 +467,142 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   else run(std::integral_constant<int, 1>{});
 }
 
+// ---------------------------------------------------------------------------
+// Folded contraction on a strided axis (theta, phi), software-pipelined.  A
+// workgroup walks PIPE_TPB consecutive column tiles of one task (tiles run
+// over slab x column block).  The next tile's raw rows are copied from HBM
+// straight into LDS (global_load_lds: 16 bytes per lane, no registers) while
+// the MFMAs run on the current tile from the other LDS buffer, and each
+// wave's operator fragments (its 16 output rows, all k) stay in registers
+// for every tile of the workgroup.
+//
+// Tile: the N input rows of TC = 1024 / HP contiguous inner points (16 KB).
+// One copy instruction moves 1 KB = R = 1024 / (8 TC) rows of TC doubles.
+// Copy chunk q (0 <= q < Q = N / R) holds rows q, q + Q, ..., q + (R-1) Q at
+// a pitch of 8 TC bytes; chunks sit PIPE_CH bytes apart, so the 4
+// consecutive rows one fragment read touches alternate between the two
+// halves of the 64 LDS banks.  The fold s_k = u_k + u_{N-1-k},
+// d_k = u_k - u_{N-1-k} is formed at the fragment read.  Each wave computes
+// one 16 x 16 output block per operator and tile (HP / 16 row tiles times
+// 64 / HP column groups), so every lane stores 8 values per operator and
+// tile; before a tile is read each wave waits only until its copy has
+// landed (vector-memory operations complete in issue order, and exactly the
+// previous tile's stores were issued after it), not for those stores.
+// Requirements (checked by the launcher): N = 2 HP with HP in {16, 32, 64},
+// inner a multiple of TC, no row scales (the angular operators carry none).
+constexpr int PIPE_CH = 1152;  // bytes between copy chunks (1 KB + 128 B)
+
+// s_waitcnt immediate: vector-memory count n (0..63), no wait on the others
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int HP, int NMAXT>
+__global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, const double* __restrict__ F0,
+                                                       const double* __restrict__ F1, double sig0, double sig1,
+                                                       int N, int inner, int slab, int ncb, int ntiles, int tpb,
+                                                       long long P, JobSet js) {
+  constexpr int TC = 1024 / HP;  // columns per tile
+  constexpr int T = HP / 16;     // 16-row output tiles
+  constexpr int NKS = HP / 4;    // k-steps of 4
+  constexpr int LPR = TC / 2;    // lanes per row in a copy
+  constexpr int R = 64 / LPR;    // rows per copy chunk
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const Task tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  F0 = shift_ptr(F0, jd);
+  F1 = shift_ptr(F1, jd);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int Q = N / R;
+  const int bufbytes = Q * PIPE_CH;
+  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P;
+  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
+  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
+  const int t0 = blockIdx.x * tpb;
+  const int nt = min(tpb, ntiles - t0);
+  // element offset of tile t's first column: slab x column block
+  auto tile_off = [&](int t) -> size_t {
+    const int g = t0 + t, sl = g / ncb, cb = g - sl * ncb;
+    return (size_t)sl * (size_t)slab + (size_t)cb * TC;
+  };
+  // copy of tile t into buffer b: wave w issues chunks w, w + 4, ...
+  const int cm = lane / LPR, cp = lane - cm * LPR;
+  auto copy_tile = [&](int t, int b) {
+    const double* g = src + tile_off(t) + 2 * cp;
+    char* base = lds + b * bufbytes;
+    for (int q = wave; q < Q; q += 4)
+      __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + cm * Q) * inner),
+                                       (lds_void_t*)(base + q * PIPE_CH), 16, 0, 0);
+  };
+
+  auto run = [&](auto nm) {
+    constexpr int NMAT = decltype(nm)::value;
+    const int wi = wave % T, wf = wave / T;
+    const int lr = lane & 15, lk = lane >> 4;
+    const size_t hh = (size_t)HP * HP;
+    // operator fragments: lane (lr, lk) holds E^T / O^T [4 ks + lk][16 wi + lr]
+    double a[NMAT][2][NKS];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m) {
+      const double* __restrict__ F = m == 0 ? F0 : F1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) a[m][h][ks] = F[h * hh + (size_t)(4 * ks + lk) * HP + 16 * wi + lr];
+    }
+    copy_tile(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int t = 0; t < nt; ++t) {
+      if (t > 0) {
+        // tile t's copy was issued before the 8 NMAT stores of tile t - 1;
+        // after the barrier every wave's copy has landed and every wave is
+        // done reading the buffer the next copy overwrites
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(8 * NMAT));
+        __syncthreads();
+      }
+      if (t + 1 < nt) copy_tile(t + 1, (t + 1) & 1);
+      const char* buf = lds + (t & 1) * bufbytes;
+      const char* lp = buf + lk * PIPE_CH + (16 * wf + lr) * 8;  // row 4 ks + lk
+      const char* lm = buf - lk * PIPE_CH + (16 * wf + lr) * 8;  // row N - 1 - (4 ks + lk)
+      d4 acc[NMAT][2];
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m) acc[m][0] = acc[m][1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int qa = (4 * ks) % Q, ma = (4 * ks) / Q;  // uniform
+        const double u = *(const double*)(lp + qa * PIPE_CH + ma * (8 * TC));
+        const double w = *(const double*)(lm + (Q - 1 - qa) * PIPE_CH + (R - 1 - ma) * (8 * TC));
+        const double sk = u + w, dk = u - w;
+#pragma unroll
+        for (int m = 0; m < NMAT; ++m) {
+          acc[m][0] = mfma_f64(a[m][0][ks], sk, acc[m][0]);
+          acc[m][1] = mfma_f64(a[m][1][ks], dk, acc[m][1]);
+        }
+      }
+      // unfold, scale, store: D row lk + 4 v of the block, column lr
+      const size_t toff = tile_off(t);
+      const int col = 16 * wf + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {  // every row i < H = HP: stores unconditional
+        const int i = 16 * wi + lk + 4 * v;
+        const int im = N - 1 - i;
+        const size_t p = toff + (size_t)i * inner + col, pm = toff + (size_t)im * inner + col;
+        const double e0 = acc[0][0][v], o0 = acc[0][1][v];
+        dst0[p] = e0 + o0;
+        dst0[pm] = sig0 * (e0 - o0);
+        if (NMAT > 1) {
+          const double e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
+          dst1[p] = e1 + o1;
+          dst1[pm] = sig1 * (e1 - o1);
+        }
+      }
+    }
+  };
+  if (NMAXT > 1 && tk.nmat > 1) run(std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>{});
+  else run(std::integral_constant<int, 1>{});
+}
+
 template <int NMAT, bool INNER, int WI, int TC = TILE_COLS>
 static hipError_t set_fold_attr() {
   const int max_lds = 256 * (TC + 8) * (int)sizeof(double);  // 2 Hpad <= 256
@@ -512,6 +649,28 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     slab = 0;
   }
   const int T = Hpad >> 4;
+  if (axis != 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad && op0.g == nullptr &&
+      op1.g == nullptr && g10 == nullptr) {
+    // pipelined form: inner a multiple of the tile width
+    const int tc = 1024 / Hpad, rows = 1024 / (8 * tc);
+    const long long all = (long long)(inner / tc) * outer * tl.n * js.n;  // tiles of the launch
+    // small launches (a few tiles per workgroup) keep the one-tile kernel
+    if (inner % tc == 0 && all >= 4096) {
+      const int ncb = inner / tc, ntiles = ncb * outer;
+      const int bufbytes = (N / rows) * PIPE_CH;
+      // tiles per workgroup: up to 8, keeping at least 1024 workgroups
+      const int tpb = (int)std::min(8LL, all / 1024);
+      dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
+#define LP(HPV, NM)                                                                                          \
+  hipLaunchKernelGGL((k_contract_pipe<HPV, NM>), pg, dim3(256), 2 * bufbytes, s, tl, B, op0.et, op1.et,    \
+                     op0.sigma, op1.sigma, N, inner, slab, ncb, ntiles, tpb, P, js)
+      if (Hpad == 16) { if (nmat == 1) LP(16, 1); else LP(16, 2); }
+      else if (Hpad == 32) { if (nmat == 1) LP(32, 1); else LP(32, 2); }
+      else { if (nmat == 1) LP(64, 1); else LP(64, 2); }
+#undef LP
+      return hipGetLastError();
+    }
+  }
   const bool narrow = axis != 0 && T == 4;  // N = 128 on a strided axis: 32-column tiles
   const int tc = narrow ? NARROW : TILE_COLS;
   dim3 grid((inner + tc - 1) / tc, outer, tl.n * js.n);
