@@ -497,6 +497,11 @@ constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// Workgroup barrier for the copy pipelines: LDS reads done, then s_barrier.
+// The copies a barrier needs are waited for explicitly before it (the
+// compiler may otherwise wait for every outstanding copy and store there).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int HP, int NMAXT>
 __global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, const double* __restrict__ F0,
                                                        const double* __restrict__ F1, double sig0, double sig1,
@@ -559,7 +564,7 @@ __global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, con
         // after the barrier every wave's copy has landed and every wave is
         // done reading the buffer the next copy overwrites
         __builtin_amdgcn_s_waitcnt(waitcnt_vm(8 * NMAT));
-        __syncthreads();
+        lds_barrier();
       }
       if (t + 1 < nt) copy_tile(t + 1, (t + 1) & 1);
       const char* buf = lds + (t & 1) * bufbytes;
@@ -595,6 +600,131 @@ __global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, con
           const double e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
           dst1[p] = e1 + o1;
           dst1[pm] = sig1 * (e1 - o1);
+        }
+      }
+    }
+  };
+  if (NMAXT > 1 && tk.nmat > 1) run(std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>{});
+  else run(std::integral_constant<int, 1>{});
+}
+
+// ---------------------------------------------------------------------------
+// The same pipeline on the r axis, whose lines are contiguous.  A tile is
+// TL = 2048 / N whole lines (16 KB); copy chunk q (0 <= q < 16) holds lines
+// q, q + 16, ... (N / 2 lanes per line, 128 / N lines per chunk), chunks
+// PIPE_CH_R bytes apart so that the 16 lines one fragment read touches start
+// 4 banks apart (conflict-free 8-byte reads).  The data are the MFMA's A
+// operand (16 lines x 4 k), the operator the B operand (4 k x 16 rows), so a
+// wave's output block is 16 lines x 16 rows; 4 waves cover the tile's
+// TL / 16 line blocks times HP / 16 row blocks.  The radial row scales of a
+// lane's rows are read once, before the copies start.  Requirements (checked
+// by the launcher): N = 2 HP with HP in {16, 32, 64}, the line count a
+// multiple of TL.
+constexpr int PIPE_CH_R = 1040;  // bytes between copy chunks (1 KB + 16 B)
+
+template <int HP, int NMAXT>
+__global__ __launch_bounds__(256) void k_contract_pipe_r(TaskList tl, Bases B, const double* __restrict__ F0,
+                                                         const double* __restrict__ F1,
+                                                         const double* __restrict__ G0,
+                                                         const double* __restrict__ G1,
+                                                         const double* __restrict__ G10, double sig0,
+                                                         double sig1, int ntiles, int tpb, long long P,
+                                                         JobSet js) {
+  constexpr int N2 = 2 * HP;        // line length
+  constexpr int TL = 2048 / N2;     // lines per tile
+  constexpr int NKS = HP / 4;       // k-steps of 4
+  constexpr int LPL = N2 / 2;       // lanes per line in a copy
+  constexpr int Q = 16;             // copy chunks per tile
+  constexpr int BUF = Q * PIPE_CH_R;
+  static_assert(TL * N2 * 8 == Q * 1024, "16 one-KB chunks per tile");
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const Task tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  F0 = shift_ptr(F0, jd);
+  F1 = shift_ptr(F1, jd);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P;
+  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
+  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
+  const int t0 = blockIdx.x * tpb;
+  const int nt = min(tpb, ntiles - t0);
+  const int cm = lane / LPL, cp = lane - cm * LPL;
+  auto copy_tile = [&](int t, int b) {
+    const double* g = src + (size_t)(t0 + t) * TL * N2 + 2 * cp;
+    char* base = lds + b * BUF;
+#pragma unroll
+    for (int q = wave; q < Q; q += 4)
+      __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + 16 * cm) * N2),
+                                       (lds_void_t*)(base + q * PIPE_CH_R), 16, 0, 0);
+  };
+
+  auto run = [&](auto nm) {
+    constexpr int NMAT = decltype(nm)::value;
+    constexpr int RT = HP / 16;      // row blocks
+    const int wr = wave % RT, wl = wave / RT;  // this wave's row block and line block
+    const int lr = lane & 15, lk = lane >> 4;
+    const size_t hh = (size_t)HP * HP;
+    // operator fragments (B operand): lane (lr, lk) holds E^T / O^T [4 ks + lk][16 wr + lr]
+    double a[NMAT][2][NKS];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m) {
+      const double* __restrict__ F = m == 0 ? F0 : F1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) a[m][h][ks] = F[h * hh + (size_t)(4 * ks + lk) * HP + 16 * wr + lr];
+    }
+    // radial row scales of this lane's output rows i = 16 wr + lr and N - 1 - i
+    const int i = 16 * wr + lr, im = N2 - 1 - i;
+    const double* g0 = G0 ? shift_ptr(G0, jd) : nullptr;
+    const double* g1 = G1 ? shift_ptr(G1, jd) : nullptr;
+    const double* g10 = G10 ? shift_ptr(G10, jd) : nullptr;
+    const double s0 = g0 ? g0[i] : 1.0, s0m = g0 ? g0[im] : 1.0;
+    const double s1 = g1 ? g1[i] : 1.0, s1m = g1 ? g1[im] : 1.0;
+    const double s10 = g10 ? g10[i] : 0.0, s10m = g10 ? g10[im] : 0.0;
+    __builtin_amdgcn_s_waitcnt(0);  // fragments and scales in registers before the copies start
+    copy_tile(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // data fragment (A operand): lane (lr, lk) reads line 16 wl + lr, k = 4 ks + lk
+    const int line = 16 * wl + lr;
+    const int lq = line & 15, lm = line >> 4;  // its copy chunk and slot
+    for (int t = 0; t < nt; ++t) {
+      if (t > 0) {
+        // tile t's copy was issued before the 8 NMAT stores of tile t - 1
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(8 * NMAT));
+        lds_barrier();
+      }
+      if (t + 1 < nt) copy_tile(t + 1, (t + 1) & 1);
+      const char* lp = lds + (t & 1) * BUF + lq * PIPE_CH_R + lm * (8 * N2);
+      d4 acc[NMAT][2];
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m) acc[m][0] = acc[m][1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int k = 4 * ks + lk;
+        const double u = *(const double*)(lp + 8 * k);
+        const double w = *(const double*)(lp + 8 * (N2 - 1 - k));
+        const double sk = u + w, dk = u - w;
+#pragma unroll
+        for (int m = 0; m < NMAT; ++m) {
+          acc[m][0] = mfma_f64(sk, a[m][0][ks], acc[m][0]);
+          acc[m][1] = mfma_f64(dk, a[m][1][ks], acc[m][1]);
+        }
+      }
+      // unfold, scale, store: D line lk + 4 v of the block, row i
+      const size_t l0 = (size_t)(t0 + t) * TL + 16 * wl;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t p = (l0 + lk + 4 * v) * N2;
+        const double e0 = acc[0][0][v], o0 = acc[0][1][v];
+        const double y0 = e0 + o0, y0m = sig0 * (e0 - o0);
+        dst0[p + i] = s0 * y0;
+        dst0[p + im] = s0m * y0m;
+        if (NMAT > 1) {
+          const double e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
+          dst1[p + i] = s1 * (e1 + o1) + s10 * y0;
+          dst1[p + im] = s1m * (sig1 * (e1 - o1)) + s10m * y0m;
         }
       }
     }
@@ -649,6 +779,24 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     slab = 0;
   }
   const int T = Hpad >> 4;
+  if (axis == 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad) {
+    // pipelined form of the r axis: the line count a multiple of the tile's
+    const int tlines = 2048 / N;
+    const long long all = (long long)(inner / tlines) * tl.n * js.n;
+    if (inner % tlines == 0 && all >= 4096) {
+      const int ntiles = inner / tlines;
+      const int tpb = (int)std::min(8LL, all / 1024);
+      dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
+#define LR(HPV, NM)                                                                                         \
+  hipLaunchKernelGGL((k_contract_pipe_r<HPV, NM>), pg, dim3(256), 2 * 16 * PIPE_CH_R, s, tl, B, op0.et,     \
+                     op1.et, op0.g, op1.g, g10, op0.sigma, op1.sigma, ntiles, tpb, P, js)
+      if (Hpad == 16) { if (nmat == 1) LR(16, 1); else LR(16, 2); }
+      else if (Hpad == 32) { if (nmat == 1) LR(32, 1); else LR(32, 2); }
+      else { if (nmat == 1) LR(64, 1); else LR(64, 2); }
+#undef LR
+      return hipGetLastError();
+    }
+  }
   if (axis != 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad && op0.g == nullptr &&
       op1.g == nullptr && g10 == nullptr) {
     // pipelined form: inner a multiple of the tile width
