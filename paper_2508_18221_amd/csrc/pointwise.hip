@@ -405,25 +405,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int m = (lo == 0) ? (hi == 1 ? 0 : 1) : 2;
     return LS(O_MX + 11 * m + s);
   };
-  // classic RK4 stage update of field f with right-hand side kf
-  // mode 0: out = k; 1: acc = k/6, out = Un + dt/2 k; 2: acc += k/3, out = Un + dt/2 k;
-  // 3: acc += k/3, out = Un + dt k; 4: out = Un + dt (acc + k/6)
+  // classic RK4 stage update of field f with right-hand side kf; the
+  // accumulator holds Un + dt sum_s b_s k_s, so the last stage does not read Un
+  // mode 0: out = k; 1: acc = Un + dt/6 k, out = Un + dt/2 k;
+  // 2: acc += dt/3 k, out = Un + dt/2 k; 3: acc += dt/3 k, out = Un + dt k;
+  // 4: out = acc + dt/6 k
   auto emit = [&](int f, double kf) {
     if (frozen) kf = 0.0;
     const size_t e = (size_t)f * P + idx;
     if (mode == 0) {
       out[e] = kf;
     } else if (mode == 1) {
-      acc[e] = kf / 6.0;
-      out[e] = Un[e] + 0.5 * dt * kf;
+      const double un = Un[e];
+      acc[e] = un + (dt / 6.0) * kf;
+      out[e] = un + 0.5 * dt * kf;
     } else if (mode == 2) {
-      acc[e] += kf / 3.0;
+      acc[e] += (dt / 3.0) * kf;
       out[e] = Un[e] + 0.5 * dt * kf;
     } else if (mode == 3) {
-      acc[e] += kf / 3.0;
+      acc[e] += (dt / 3.0) * kf;
       out[e] = Un[e] + dt * kf;
     } else {
-      out[e] = Un[e] + dt * (acc[e] + kf / 6.0);
+      out[e] = acc[e] + (dt / 6.0) * kf;
     }
   };
 

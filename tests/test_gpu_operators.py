@@ -77,3 +77,38 @@ def test_operators_exact_on_polynomials():
     assert np.abs(o[1] - 4 * (g.TH - 1.0) ** 3).max() < 1e-12
     assert np.abs(o[2] + 3 * np.sin(3 * g.PH)).max() < 1e-12
     s.close()
+
+
+# Grids and field counts large enough that every launch takes the pipelined
+# folded kernels (tiles copied into LDS ahead of the MFMAs): half sizes 32
+# (r, theta) and 16 (phi) on 64 x 64 x 32; 64 (r) and 16 (theta, phi) on
+# 128 x 32 x 32; 64 (theta) on 64 x 128 x 16.
+PIPE_SIZES = [(64, 64, 32), (128, 32, 32), (64, 128, 16)]
+
+
+@pytest.mark.parametrize("size", PIPE_SIZES)
+def test_pipelined_operators_match_oracle(size):
+    nr, nth, nph = size
+    log(f"[operators, pipelined] grid {size}, 64 fields")
+    w = workload("ks_michel_16x16x16", nr=nr, nth=nth, nph=nph)
+    s = solver(w)
+    g = spectral.Grid(nr, nth, nph, 1.8, 20.0, 0.05, np.pi - 0.05)
+    nf = 64
+    data = workloads.random_fields(g.shape, nf, seed=11)
+    dev_in = torch.tensor(data, device="cuda")
+    for axis in range(3):
+        for op in (1, 2, 3):
+            dev_out = torch.full_like(dev_in, np.nan)
+            s.apply_operator(axis, op, dev_in, dev_out)
+            torch.cuda.synchronize()
+            got = dev_out.cpu().numpy()
+            n = size[axis]
+            tol = {1: 1e-15 * n * n, 2: 4e-16 * n ** 4, 3: 1e-13}[op]
+            worst = 0.0
+            for i in range(0, nf, 9):  # every ninth field (all tasks share the kernel)
+                ref = oracle_op(g, data[i], axis, op)
+                worst = max(worst, np.abs(got[i] - ref).max() / np.abs(ref).max())
+            log(f"  axis {axis} op {op}: rel err {worst:.2e} (tol {tol:.1e})")
+            assert np.isfinite(got).all()
+            assert worst < max(tol, 1e-14), (axis, op, worst)
+    s.close()
