@@ -492,15 +492,6 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 // inner a multiple of TC, no row scales (the angular operators carry none).
 constexpr int PIPE_CH = 1152;  // bytes between copy chunks (1 KB + 128 B)
 
-// s_waitcnt immediate: vector-memory count n (0..63), no wait on the others
-constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Workgroup barrier for the copy pipelines: LDS reads done, then s_barrier.
-// The copies a barrier needs are waited for explicitly before it (the
-// compiler may otherwise wait for every outstanding copy and store there).
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int HP, int NMAXT>
 __global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, const double* __restrict__ F0,

@@ -19,6 +19,7 @@
 //                 D as for f32.
 #include "grmhd_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace grmhd {
@@ -504,6 +505,185 @@ __global__ __launch_bounds__(256) void k_contract_f32_fold(MixedTaskList tl, Bas
   else run(std::integral_constant<int, 1>{});
 }
 
+// ---------------------------------------------------------------------------
+// FP32 form of the copy-ahead pipelines of the folded contraction (the FP64
+// ones are in contract.hip): a workgroup walks tpb tiles of one task; the
+// next tile's raw input rows are copied into LDS (global_load_lds) while FP32
+// MFMAs run on the current one; operator fragments stay in registers.  Each
+// line is shifted by its middle-node value and folded in FP64, then cast.
+// Strided axes (theta, phi): tiles of TC = 1024 / HP columns of N rows,
+// inputs FP64 or FP32 per task; r axis: tiles of TL = 2048 / N whole lines,
+// FP64 inputs.  Copy chunk q holds rows (lines) q, q + Q, ...; chunk pitches
+// keep the fragment reads conflict-free (FP64 rows: 1152 bytes, FP32 rows:
+// 1088, r lines: 1040).  Requirements (checked by the launcher): N = 2 HP,
+// HP in {16, 32, 64}, whole tiles, row scales only on the r axis.
+constexpr int P32_BUF = 16 * 1152;  // bytes per tile buffer (largest layout)
+
+template <int HP, int NMAXT, bool INNER>
+__global__ __launch_bounds__(256) void k_contract_f32_pipe(MixedTaskList tl, Bases B, const float* __restrict__ F0,
+                                                           const float* __restrict__ F1,
+                                                           const double* __restrict__ G0,
+                                                           const double* __restrict__ G1,
+                                                           const double* __restrict__ G10, float sig0, float sig1,
+                                                           int inner, int slab, int ncb, int ntiles, int tpb,
+                                                           long long P, JobSet js) {
+  constexpr int N2 = 2 * HP;     // line length
+  constexpr int NKS = HP / 4;    // k-steps of 4
+  constexpr int TC = 1024 / HP;  // strided axes: columns per tile
+  constexpr int TL = 2048 / N2;  // r axis: lines per tile
+  constexpr int RT = HP / 16;    // 16-row output blocks
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const MixedTask tk = tl.t[blockIdx.z % tl.n];
+  const long long jd = js.d[blockIdx.z / tl.n];
+  F0 = shift_ptr(F0, jd);
+  F1 = shift_ptr(F1, jd);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int wa = wave % RT, wb = wave / RT;  // row block; column (strided) or line (r) block
+  float* __restrict__ dst0 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
+  float* __restrict__ dst1 = (float*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
+  const int t0 = blockIdx.x * tpb;
+  const int nt = min(tpb, ntiles - t0);
+  auto tile_off = [&](int t) -> size_t {
+    const int g = t0 + t;
+    if (INNER) return (size_t)g * TL * N2;
+    const int sl = g / ncb, cb = g - sl * ncb;
+    return (size_t)sl * (size_t)slab + (size_t)cb * TC;
+  };
+
+  auto body = [&](auto nm, auto es) {
+    constexpr int NMAT = decltype(nm)::value;
+    constexpr int ES = decltype(es)::value;  // input element bytes
+    using T = typename std::conditional<ES == 8, double, float>::type;
+    constexpr int CH = INNER ? 1040 : (ES == 8 ? 1152 : 1088);
+    constexpr int RB = INNER ? ES * N2 : ES * TC;  // bytes per line (r) or row (strided)
+    constexpr int LPR = RB / 16;                  // lanes per row in a copy
+    constexpr int RPC = 64 / LPR;                 // rows per chunk
+    constexpr int Q = (INNER ? TL : N2) / RPC;    // chunks per tile
+    static_assert(Q % 4 == 0 && Q * CH <= P32_BUF, "chunk layout");
+    const T* __restrict__ src = field_base<T>(tk, B, P, jd);
+    const int cm = lane / LPR, cp = lane - cm * LPR;
+    auto copy_tile = [&](int t, int b) {
+      const T* g = src + tile_off(t) + (16 / ES) * cp;
+      char* base = lds + b * P32_BUF;
+#pragma unroll
+      for (int q = wave; q < Q; q += 4)
+        __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + Q * cm) * (INNER ? N2 : inner)),
+                                         (lds_void_t*)(base + q * CH), 16, 0, 0);
+    };
+    // operator fragments: lane (lr, lk) holds E^T / O^T [4 ks + lk][16 wa + lr]
+    const size_t hh = (size_t)HP * HP;
+    float a[NMAT][2][NKS];
+#pragma unroll
+    for (int m = 0; m < NMAT; ++m) {
+      const float* __restrict__ F = m == 0 ? F0 : F1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) a[m][h][ks] = F[h * hh + (size_t)(4 * ks + lk) * HP + 16 * wa + lr];
+    }
+    // r axis: row scales of this lane's output rows i = 16 wa + lr and N - 1 - i
+    const int ir = 16 * wa + lr, irm = N2 - 1 - ir;
+    double s0 = 1.0, s0m = 1.0, s1 = 1.0, s1m = 1.0, s10 = 0.0, s10m = 0.0;
+    if (INNER) {
+      if (G0) { s0 = shift_ptr(G0, jd)[ir]; s0m = shift_ptr(G0, jd)[irm]; }
+      if (G1) { s1 = shift_ptr(G1, jd)[ir]; s1m = shift_ptr(G1, jd)[irm]; }
+      if (G10) { s10 = shift_ptr(G10, jd)[ir]; s10m = shift_ptr(G10, jd)[irm]; }
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // fragments and scales in registers before the copies start
+    copy_tile(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int own = 16 * wb + lr;  // strided: this lane's column; r: the line its fragment reads
+    for (int t = 0; t < nt; ++t) {
+      if (t > 0) {
+        // tile t's copy was issued before the 8 NMAT stores of tile t - 1
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(8 * NMAT));
+        lds_barrier();
+      }
+      if (t + 1 < nt) copy_tile(t + 1, (t + 1) & 1);
+      const char* buf = lds + (t & 1) * P32_BUF;
+      // the middle-node value of the line this lane's fragment reads
+      const char* lp;
+      const char* lm;
+      double c;
+      if (INNER) {
+        lp = buf + (own % Q) * CH + (own / Q) * RB;
+        lm = lp;
+        c = (double)*(const T*)(lp + HP * ES);
+      } else {
+        lp = buf + lk * CH + own * ES;
+        lm = buf - lk * CH + own * ES;
+        c = (double)*(const T*)(buf + (HP % Q) * CH + (HP / Q) * RB + own * ES);
+      }
+      f4 acc[NMAT][2];
+#pragma unroll
+      for (int m = 0; m < NMAT; ++m) acc[m][0] = acc[m][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        double u, w;
+        if (INNER) {
+          const int k = 4 * ks + lk;
+          u = (double)*(const T*)(lp + k * ES);
+          w = (double)*(const T*)(lm + (N2 - 1 - k) * ES);
+        } else {
+          const int qa = (4 * ks) % Q, ma = (4 * ks) / Q;
+          u = (double)*(const T*)(lp + qa * CH + ma * RB);
+          w = (double)*(const T*)(lm + (Q - 1 - qa) * CH + (RPC - 1 - ma) * RB);
+        }
+        const double lo = u - c, hi = w - c;
+        const float sk = (float)(lo + hi), dk = (float)(lo - hi);
+#pragma unroll
+        for (int m = 0; m < NMAT; ++m) {
+          if (INNER) {
+            acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(sk, a[m][0][ks], acc[m][0], 0, 0, 0);
+            acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(dk, a[m][1][ks], acc[m][1], 0, 0, 0);
+          } else {
+            acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][0][ks], sk, acc[m][0], 0, 0, 0);
+            acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][1][ks], dk, acc[m][1], 0, 0, 0);
+          }
+        }
+      }
+      // unfold, scale in FP64, store FP32: accumulator row 4 lk + v, column lr
+      const size_t toff = tile_off(t);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        size_t p, pm;
+        if (INNER) {  // rows: lines; columns: output rows ir
+          const size_t l = toff + (size_t)(16 * wb + 4 * lk + v) * N2;
+          p = l + ir;
+          pm = l + irm;
+        } else {  // rows: output rows i; columns: this lane's column
+          const int i = 16 * wa + 4 * lk + v;
+          p = toff + (size_t)i * inner + own;
+          pm = toff + (size_t)(N2 - 1 - i) * inner + own;
+        }
+        const float e0 = acc[0][0][v], o0 = acc[0][1][v];
+        const float y0 = e0 + o0, y0m = sig0 * (e0 - o0);
+        dst0[p] = INNER ? (float)(s0 * (double)y0) : y0;
+        dst0[pm] = INNER ? (float)(s0m * (double)y0m) : y0m;
+        if (NMAT > 1) {
+          const float e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
+          const float y1 = e1 + o1, y1m = sig1 * (e1 - o1);
+          dst1[p] = INNER ? (float)(s1 * (double)y1 + s10 * (double)y0) : y1;
+          dst1[pm] = INNER ? (float)(s1m * (double)y1m + s10m * (double)y0m) : y1m;
+        }
+      }
+    }
+  };
+  using I8 = std::integral_constant<int, 8>;
+  using I4 = std::integral_constant<int, 4>;
+  if (NMAXT > 1 && tk.nmat > 1) {
+    using M = std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>;
+    if (!INNER && tk.src_f32) body(M{}, I4{});
+    else body(M{}, I8{});
+  } else {
+    using M = std::integral_constant<int, 1>;
+    if (!INNER && tk.src_f32) body(M{}, I4{});
+    else body(M{}, I8{});
+  }
+}
+
 template <int NMAT, bool INNER>
 static hipError_t set_f32_fold_attr() {
   const int max_lds = 160 * 1024;
@@ -526,6 +706,48 @@ hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl,
   if ((N & 1) || Hpad < N / 2 || (Hpad & 15) || 2 * Hpad > 256) return hipErrorInvalidValue;
   int inner, outer, slab;
   geometry(axis, n, &inner, &outer, &slab);
+  if ((Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad) {
+    // copy-ahead pipeline: whole tiles, enough of them, FP64 inputs on the r
+    // axis, row scales only there
+    bool ok;
+    int ntiles, ncb = 1;
+    if (axis == 0) {
+      const int tlines = 2048 / N;
+      ok = inner % tlines == 0;
+      for (int i = 0; i < tl.n && ok; ++i) ok = tl.t[i].src_f32 == 0;
+      ntiles = inner / tlines;
+    } else {
+      const int tc = 1024 / Hpad;
+      ok = inner % tc == 0 && op0.g == nullptr && op1.g == nullptr && g10 == nullptr;
+      ncb = inner / tc;
+      ntiles = ncb * outer;
+    }
+    const long long all = (long long)ntiles * tl.n * js.n;
+    if (ok && all >= 4096) {
+      const int tpb = (int)std::min(8LL, all / 1024);
+      dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
+#define LP(HPV, NM, IN)                                                                                          \
+  hipLaunchKernelGGL((k_contract_f32_pipe<HPV, NM, IN>), pg, dim3(256), 2 * P32_BUF, s, tl, B, op0.et, op1.et, \
+                     op0.g, op1.g, g10, (float)op0.sigma, (float)op1.sigma, inner, slab, ncb, ntiles, tpb, P, js)
+#define LPA(HPV, IN)                     \
+  do {                                   \
+    if (nmat == 1) LP(HPV, 1, IN);       \
+    else LP(HPV, 2, IN);                 \
+  } while (0)
+#define LPH(IN)                          \
+  do {                                   \
+    if (Hpad == 16) LPA(16, IN);         \
+    else if (Hpad == 32) LPA(32, IN);    \
+    else LPA(64, IN);                    \
+  } while (0)
+      if (axis == 0) LPH(true);
+      else LPH(false);
+#undef LPH
+#undef LPA
+#undef LP
+      return hipGetLastError();
+    }
+  }
   dim3 grid((inner + MT_COLS - 1) / MT_COLS, outer, tl.n * js.n);
   const size_t lds = (size_t)2 * Hpad * F32_STRIDE * sizeof(float) + MT_COLS * sizeof(double);
   const int T = Hpad >> 4;

@@ -199,4 +199,15 @@ hipError_t launch_diag_partials(const double* U, const double* prim, const doubl
 int diag_partials_blocks(long long P);
 hipError_t set_kernel_attributes();
 
+// ---- helpers of the copy-ahead contraction pipelines ---------------------------
+// s_waitcnt immediate: vector-memory count n (0..63), no wait on the others
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Workgroup barrier for the copy pipelines: LDS reads done, then s_barrier.
+// The copies a barrier needs are waited for explicitly before it (the
+// compiler may otherwise wait for every outstanding copy and store there).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 }  // namespace grmhd

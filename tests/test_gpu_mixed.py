@@ -93,3 +93,38 @@ def test_hamiltonian_diagnostic_matches_oracle():
     log(f"[ham] GPU L2 {d['ham_l2']:.6e} oracle {l2:.6e}; Linf {d['ham_linf']:.6e} vs {np.abs(H).max():.6e}")
     assert abs(d["ham_l2"] / l2 - 1) < 1e-9
     assert abs(d["ham_linf"] / np.abs(H).max() - 1) < 1e-9
+
+
+def test_fp32_form_full_size_within_bounds():
+    """The FP32 form at 64 x 64 x 128, where its contractions take the
+    copy-ahead pipelined kernels (FP64 and FP32 input rows, all three axes):
+    after 10 RK4 steps from the same state the density stays within 1e-6
+    (relative L2) of the FP64 path and the Hamiltonian-constraint norm within
+    a factor 2 of the FP64 run's."""
+    log("[mixed evolve] fp32 64x64x128, 10 RK4 steps vs the FP64 path")
+    w = workload("ks_michel_64x64x128")
+    s64 = solver_prec(w, 0)
+    s64.init_state()
+    U0, K0 = s64.get_state(with_k0=True)
+    s64.step(10)
+    ref = s64.get_state()
+    d64 = s64.diagnostics()
+    s64.close()
+    s = solver_prec(w, PRECS["fp32"])
+    s.set_state(U0, K0)
+    s.step(10)
+    got = s.get_state()
+    d = s.diagnostics()
+    s.close()
+    # rest-mass density through the oracle's recovery on both states
+    from oracle import spectral, evolve
+    import workloads
+    ga, pk, _ = workloads.oracle_kwargs(w)
+    pb = evolve.Problem(spectral.Grid(*ga), **pk)
+    r_ref, r_got = rho_of(pb, ref), rho_of(pb, got)
+    l2 = np.sqrt(np.sum((r_got - r_ref) ** 2) / np.sum(r_ref ** 2))
+    log(f"  rho L2 rel {l2:.2e}; H L2 {d['ham_l2']:.4e} vs FP64 {d64['ham_l2']:.4e}")
+    assert np.isfinite(got).all()
+    assert l2 < 1e-6
+    assert d["ham_l2"] < 2.0 * d64["ham_l2"]
+    assert d["nonfinite"] == 0 and d["c2p_fail"] == 0
