@@ -476,33 +476,44 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 // wave's operator fragments (its 16 output rows, all k) stay in registers
 // for every tile of the workgroup.
 //
-// Tile: the N input rows of TC = 1024 / HP contiguous inner points (16 KB).
-// One copy instruction moves 1 KB = R = 1024 / (8 TC) rows of TC doubles.
+// Tile: the N input rows of TC = 16 NW / (HP / 16) contiguous inner points
+// (NW waves: 16 KB for 4, 24 KB for 6).  One copy instruction moves 1 KB =
+// R = 1024 / (8 TC) rows of TC doubles.
 // Copy chunk q (0 <= q < Q = N / R) holds rows q, q + Q, ..., q + (R-1) Q at
 // a pitch of 8 TC bytes; chunks sit PIPE_CH bytes apart, so the 4
 // consecutive rows one fragment read touches alternate between the two
 // halves of the 64 LDS banks.  The fold s_k = u_k + u_{N-1-k},
 // d_k = u_k - u_{N-1-k} is formed at the fragment read.  Each wave computes
 // one 16 x 16 output block per operator and tile (HP / 16 row tiles times
-// 64 / HP column groups), so every lane stores 8 values per operator and
+// TC / 16 column groups), so every lane stores 8 values per operator and
 // tile; before a tile is read each wave waits only until its copy has
 // landed (vector-memory operations complete in issue order, and exactly the
 // previous tile's stores were issued after it), not for those stores.
-// Requirements (checked by the launcher): N = 2 HP with HP in {16, 32, 64},
+// Requirements (checked by the launcher): N = 2 HP with HP in {16, 32, 48,
+// 64, 96} (one operator only at 96: two would not fit in registers),
 // inner a multiple of TC, no row scales (the angular operators carry none).
 constexpr int PIPE_CH = 1152;  // bytes between copy chunks (1 KB + 128 B)
 
 
+// Waves per workgroup: 4, or 6 for the half sizes 48 and 96 (3 or 6 row
+// blocks), so that every wave owns one 16 x 16 output block per tile.
+template <int HP>
+constexpr int pipe_waves() { return (HP == 48 || HP == 96) ? 6 : 4; }
+
 template <int HP, int NMAXT>
-__global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, const double* __restrict__ F0,
-                                                       const double* __restrict__ F1, double sig0, double sig1,
-                                                       int N, int inner, int slab, int ncb, int ntiles, int tpb,
-                                                       long long P, JobSet js) {
-  constexpr int TC = 1024 / HP;  // columns per tile
-  constexpr int T = HP / 16;     // 16-row output tiles
-  constexpr int NKS = HP / 4;    // k-steps of 4
-  constexpr int LPR = TC / 2;    // lanes per row in a copy
-  constexpr int R = 64 / LPR;    // rows per copy chunk
+__global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskList tl, Bases B,
+                                                                         const double* __restrict__ F0,
+                                                                         const double* __restrict__ F1,
+                                                                         double sig0, double sig1, int N, int inner,
+                                                                         int slab, int ncb, int ntiles, int tpb,
+                                                                         long long P, JobSet js) {
+  constexpr int NW = pipe_waves<HP>();
+  constexpr int T = HP / 16;       // 16-row output tiles
+  constexpr int TC = 16 * NW / T;  // columns per tile (T x TC/16 = NW output blocks)
+  constexpr int NKS = HP / 4;      // k-steps of 4
+  constexpr int LPR = TC / 2;      // lanes per row in a copy
+  constexpr int R = 64 / LPR;      // rows per copy chunk
+  static_assert(T * (TC / 16) == NW && (2 * HP / R) % NW == 0, "one output block per wave");
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const Task tk = tl.t[blockIdx.z % tl.n];
   const long long jd = js.d[blockIdx.z / tl.n];
@@ -521,12 +532,12 @@ __global__ __launch_bounds__(256) void k_contract_pipe(TaskList tl, Bases B, con
     const int g = t0 + t, sl = g / ncb, cb = g - sl * ncb;
     return (size_t)sl * (size_t)slab + (size_t)cb * TC;
   };
-  // copy of tile t into buffer b: wave w issues chunks w, w + 4, ...
+  // copy of tile t into buffer b: wave w issues chunks w, w + NW, ...
   const int cm = lane / LPR, cp = lane - cm * LPR;
   auto copy_tile = [&](int t, int b) {
     const double* g = src + tile_off(t) + 2 * cp;
     char* base = lds + b * bufbytes;
-    for (int q = wave; q < Q; q += 4)
+    for (int q = wave; q < Q; q += NW)
       __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + cm * Q) * inner),
                                        (lds_void_t*)(base + q * PIPE_CH), 16, 0, 0);
   };
@@ -788,10 +799,11 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
       return hipGetLastError();
     }
   }
-  if (axis != 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad && op0.g == nullptr &&
-      op1.g == nullptr && g10 == nullptr) {
-    // pipelined form: inner a multiple of the tile width
-    const int tc = 1024 / Hpad, rows = 1024 / (8 * tc);
+  if (axis != 0 && (Hpad == 16 || Hpad == 32 || Hpad == 48 || Hpad == 64 || Hpad == 96) && N == 2 * Hpad &&
+      op0.g == nullptr && op1.g == nullptr && g10 == nullptr) {
+    // copy-ahead form: inner a multiple of the tile width
+    const int nw = (Hpad == 48 || Hpad == 96) ? 6 : 4;
+    const int tc = 16 * nw / (Hpad / 16), rows = 1024 / (8 * tc);
     const long long all = (long long)(inner / tc) * outer * tl.n * js.n;  // tiles of the launch
     // small launches (a few tiles per workgroup) keep the one-tile kernel
     if (inner % tc == 0 && all >= 4096) {
@@ -799,15 +811,38 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
       const int bufbytes = (N / rows) * PIPE_CH;
       // tiles per workgroup: up to 8, keeping at least 1024 workgroups
       const int tpb = (int)std::min(8LL, all / 1024);
-      dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
-#define LP(HPV, NM)                                                                                          \
-  hipLaunchKernelGGL((k_contract_pipe<HPV, NM>), pg, dim3(256), 2 * bufbytes, s, tl, B, op0.et, op1.et,    \
-                     op0.sigma, op1.sigma, N, inner, slab, ncb, ntiles, tpb, P, js)
-      if (Hpad == 16) { if (nmat == 1) LP(16, 1); else LP(16, 2); }
-      else if (Hpad == 32) { if (nmat == 1) LP(32, 1); else LP(32, 2); }
-      else { if (nmat == 1) LP(64, 1); else LP(64, 2); }
+      auto launch = [&](const TaskList& L, int nm, const FoldOp& o0, const FoldOp& o1) {
+        dim3 pg((ntiles + tpb - 1) / tpb, 1, L.n * js.n);
+#define LP(HPV, NM)                                                                                               \
+  hipLaunchKernelGGL((k_contract_pipe<HPV, NM>), pg, dim3(64 * pipe_waves<HPV>()), 2 * bufbytes, s, L, B, o0.et, \
+                     o1.et, o0.sigma, o1.sigma, N, inner, slab, ncb, ntiles, tpb, P, js)
+        if (Hpad == 16) { if (nm == 1) LP(16, 1); else LP(16, 2); }
+        else if (Hpad == 32) { if (nm == 1) LP(32, 1); else LP(32, 2); }
+        else if (Hpad == 48) { if (nm == 1) LP(48, 1); else LP(48, 2); }
+        else if (Hpad == 64) { if (nm == 1) LP(64, 1); else LP(64, 2); }
+        else LP(96, 1);
 #undef LP
-      return hipGetLastError();
+        return hipGetLastError();
+      };
+      if (Hpad == 96 && nmat == 2) {
+        // one pass per operator: every task's first operator, then the
+        // second operator of the two-operator tasks
+        TaskList la = tl, lb;
+        lb.n = 0;
+        for (int i = 0; i < tl.n; ++i) {
+          la.t[i].nmat = 1;
+          if (tl.t[i].nmat == 2) {
+            lb.t[lb.n] = tl.t[i];
+            lb.t[lb.n].dst0 = tl.t[i].dst1;
+            lb.t[lb.n].nmat = 1;
+            ++lb.n;
+          }
+        }
+        hipError_t e = launch(la, 1, op0, op0);
+        if (e == hipSuccess && lb.n > 0) e = launch(lb, 1, op1, op1);
+        return e;
+      }
+      return launch(tl, nmat, op0, op1);
     }
   }
   const bool narrow = axis != 0 && T == 4;  // N = 128 on a strided axis: 32-column tiles

@@ -82,8 +82,9 @@ def test_operators_exact_on_polynomials():
 # Grids and field counts large enough that every launch takes the pipelined
 # folded kernels (tiles copied into LDS ahead of the MFMAs): half sizes 32
 # (r, theta) and 16 (phi) on 64 x 64 x 32; 64 (r) and 16 (theta, phi) on
-# 128 x 32 x 32; 64 (theta) on 64 x 128 x 16.
-PIPE_SIZES = [(64, 64, 32), (128, 32, 32), (64, 128, 16)]
+# 128 x 32 x 32; 64 (theta) on 64 x 128 x 16; the six-wave forms, 48
+# (theta) on 64 x 96 x 32 and 96 (phi) on 32 x 32 x 192.
+PIPE_SIZES = [(64, 64, 32), (128, 32, 32), (64, 128, 16), (64, 96, 32), (32, 32, 192)]
 
 
 @pytest.mark.parametrize("size", PIPE_SIZES)
