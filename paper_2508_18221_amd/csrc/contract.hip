@@ -785,7 +785,7 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     // pipelined form of the r axis: the line count a multiple of the tile's
     const int tlines = 2048 / N;
     const long long all = (long long)(inner / tlines) * tl.n * js.n;
-    if (inner % tlines == 0 && all >= 4096) {
+    if (inner % tlines == 0 && all >= 2048) {
       const int ntiles = inner / tlines;
       const int tpb = (int)std::min(8LL, all / 1024);
       dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
@@ -806,7 +806,7 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     const int tc = 16 * nw / (Hpad / 16), rows = 1024 / (8 * tc);
     const long long all = (long long)(inner / tc) * outer * tl.n * js.n;  // tiles of the launch
     // small launches (a few tiles per workgroup) keep the one-tile kernel
-    if (inner % tc == 0 && all >= 4096) {
+    if (inner % tc == 0 && all >= 2048) {
       const int ncb = inner / tc, ntiles = ncb * outer;
       const int bufbytes = (N / rows) * PIPE_CH;
       // tiles per workgroup: up to 8, keeping at least 1024 workgroups

@@ -723,7 +723,7 @@ hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl,
       ntiles = ncb * outer;
     }
     const long long all = (long long)ntiles * tl.n * js.n;
-    if (ok && all >= 4096) {
+    if (ok && all >= 2048) {
       const int tpb = (int)std::min(8LL, all / 1024);
       dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
 #define LP(HPV, NM, IN)                                                                                          \
