@@ -22,6 +22,15 @@ Readings of the paper taken here (where it is silent or inconsistent):
   * time step: dt = cfl * min over nodes of min(dr, r dtheta, r sin(theta)
     dphi) with neighbour spacings and characteristic speed bound 1 (light
     speed), fixed for the run.
+  * GLM constraint damping (optional, Methods "GLM Constraint Damping
+    Source"): a 33rd evolved field psi (undensitised) with
+    d_t psi = -c_h^2 D_i B^i - psi / tau, D_i B^i = d_i(sqrt(gamma) B^i) /
+    sqrt(gamma), and the induction source sqrt(gamma) S^i with
+    S^i = -gamma^{ij} d_j psi.  The paper prints S_{B^i} = d_i psi: the index
+    is raised with the spatial metric, and the sign is Dedner's (with the
+    printed sign the pair d_t psi, d_t B would give d_tt psi = -c_h^2
+    Laplacian psi, which is ill-posed); no lapse factors, as printed.
+    Frozen at the same boundary nodes and filtered like the other fields.
 """
 
 import numpy as np
@@ -82,8 +91,10 @@ class Problem:
 
     def __init__(self, grid, M=1.0, a=0.5, Gamma=4.0 / 3.0, eta=2.0, cowling=False,
                  gauge_k0=True, rho_floor=1e-20, p_floor=1e-24, filt_alpha=36.0,
-                 filt_order=16, filter_on=True, dealias=False, cfl=0.25):
+                 filt_order=16, filter_on=True, dealias=False, cfl=0.25, glm=False, glm_ch=1.0,
+                 glm_tau=2.0):
         self.g = grid
+        self.glm, self.glm_ch, self.glm_tau = glm, glm_ch, glm_tau
         self.M, self.a, self.Gamma, self.eta = M, a, Gamma, eta
         self.cowling, self.gauge_k0 = cowling, gauge_k0
         self.rho_fl = rho_floor * grid.R ** -1.5
@@ -156,7 +167,14 @@ class Problem:
         rm = dict(sD=-div[0], sS=-div[1:4] + sqrtg * srcS, stau=-div[4] + sqrtg * srcT, sB=-div[5:8])
         if self.cowling:
             rb = {k: np.zeros_like(v) for k, v in rb.items()}
-        R = pack(rb, rm)
+        if self.glm:
+            psi = U[NF]
+            dpsi = np.array([g.d1(psi, k) for k in range(3)])
+            divB = sum(g.d1(U[29 + i], i) for i in range(3)) / sqrtg
+            rm['sB'] = rm['sB'] - sqrtg * np.einsum('ij...,j...->i...', P['gamu'], dpsi)
+            R = np.concatenate([pack(rb, rm), (-self.glm_ch ** 2 * divB - psi / self.glm_tau)[None]])
+        else:
+            R = pack(rb, rm)
         # freeze: r_out nodes and theta end nodes
         R[:, :, :, 0] = 0.0
         R[:, :, 0, :] = 0.0
@@ -200,6 +218,8 @@ def initial_state(grid, problem, r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1
         mat = michel_monopole(grid, f, problem.M, problem.a, problem.Gamma, r_c, rho_c, beta_min, pert_amp,
                               seed)
     U = pack(f, dict(sD=mat['sD'], sS=mat['sS'], stau=mat['stau'], sB=mat['sB']))
+    if problem.glm:
+        U = np.concatenate([U, np.zeros((1,) + U.shape[1:])])  # psi = 0
     return U, gauge_source_k0(grid, f), mat
 
 
