@@ -69,6 +69,7 @@ enum {
 };
 
 #define GRMHD_NFIELDS 32
+#define GRMHD_NFIELDS_GLM 33   /* with GLM constraint damping: psi is field 32 */
 
 /* Precision of the derivative contractions (the only part that changes):
  * FP64; FP32 MFMA with FP32 accumulation; split-BF16 x3 MFMA with FP32
@@ -113,6 +114,12 @@ typedef struct {
   double tor_atm;           /* atmosphere rho = tor_atm rho_max (r/r_max)^-1.5,
                                at Eulerian rest on the torus isentrope       */
   double tor_loop_cut;      /* A_phi = max(rho/rho_max - tor_loop_cut, 0)    */
+  /* GLM constraint damping (Methods, "GLM Constraint Damping Source"; reading:
+   * index raised with the spatial metric, Dedner's sign): a 33rd field psi
+   * with d_t psi = -c_h^2 d_i(sqrt(gamma) B^i)/sqrt(gamma) - psi/tau and the
+   * induction source -sqrt(gamma) gamma^{ij} d_j psi.  0: off (32 fields). */
+  int32_t glm;
+  double glm_ch, glm_tau;   /* c_h (<= 1 for the CFL bound) and tau > 0      */
 } grmhd_phys;
 
 /* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"). */
@@ -153,22 +160,26 @@ int grmhd_destroy(grmhd_ctx* ctx);
  * primes the con2prim guesses.  t = 0.  Syncs. */
 int grmhd_init_state(grmhd_ctx* ctx);
 
-/* Copy a state in (host, n = 32 P doubles, layout above), set the static
+/* Copy a state in (host, n = 32 P doubles, layout above; a GLM context also
+ * takes n = 33 P with psi last, and sets psi = 0 for n = 32 P), set the static
  * 1+log source K0 (host, P doubles; NULL: K0 = K - beta^k d_k alpha/(2 alpha)
  * computed on the device from the state) and the time t; primes the
  * con2prim guesses by a cold-start recovery.  Syncs. */
 int grmhd_set_state(grmhd_ctx* ctx, const double* host_U, size_t n,
                     const double* host_K0, double t);
 
-/* Copy the state (and optionally K0, P doubles) out.  Syncs. */
+/* Copy the state (n = 32 P, or 33 P with psi last in a GLM context; and
+ * optionally K0, P doubles) out.  Syncs. */
 int grmhd_get_state(grmhd_ctx* ctx, double* host_U, size_t n, double* host_K0);
 
-/* Device pointers of the resident state (32 P doubles) and K0 (P doubles);
+/* Device pointers of the resident state (32 P doubles, then psi in a GLM
+ * context) and K0 (P doubles);
  * valid for the context's lifetime.  No copy, no sync. */
 int grmhd_state_ptr(grmhd_ctx* ctx, double** dev_U, double** dev_K0);
 
-/* One RHS evaluation dU/dt = L(U) of a device state (32 P doubles) into
- * dev_dUdt (32 P doubles); uses the context's K0 and con2prim guesses.
+/* One RHS evaluation dU/dt = L(U) of a device state (32 P doubles, 33 P in
+ * a GLM context) into dev_dUdt (as many); uses the context's K0 and con2prim
+ * guesses.
  * dev_U may be the resident state.  Async. */
 int grmhd_rhs(grmhd_ctx* ctx, const double* dev_U, double* dev_dUdt);
 
@@ -179,7 +190,7 @@ int grmhd_step(grmhd_ctx* ctx, int32_t nsteps);
 /* nsteps RK4 steps (+ filter) of n contexts of one grid class, each kernel
  * launched once for all of them (continuous batching; up to 32 jobs per
  * launch, larger n is split).  The contexts must share grid sizes, precision,
- * the kernel parameters (Gamma, eta, cowling, gauge_k0, floors), the stream
+ * the kernel parameters (Gamma, eta, cowling, gauge_k0, floors, GLM), the stream
  * and the offset between their scratch and resident buffers; r_in, the spin,
  * the initial data and dt may differ.  Each job's arithmetic is the same
  * as when stepped alone (bitwise).  Async. */

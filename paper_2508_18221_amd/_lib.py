@@ -30,7 +30,8 @@ class Phys(ctypes.Structure):
                 ("pert_amp", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
                 ("id_kind", ctypes.c_int32), ("tor_r_in", ctypes.c_double), ("tor_r_max", ctypes.c_double),
-                ("tor_rho_max", ctypes.c_double), ("tor_atm", ctypes.c_double), ("tor_loop_cut", ctypes.c_double)]
+                ("tor_rho_max", ctypes.c_double), ("tor_atm", ctypes.c_double), ("tor_loop_cut", ctypes.c_double),
+                ("glm", ctypes.c_int32), ("glm_ch", ctypes.c_double), ("glm_tau", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):

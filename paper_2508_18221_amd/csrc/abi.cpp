@@ -275,9 +275,9 @@ int mixed_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* re
 }
 
 // Reduced-precision derivatives of the densitised fluxes, on stream st.
-int mixed_flux_derivs(grmhd_ctx* c, const JobSet& js, Recorder* rec, hipStream_t st) {
+int mixed_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec, hipStream_t st) {
   Bases B;
-  B.b[0] = nullptr;
+  B.b[0] = const_cast<double*>(Uin);
   B.b[1] = sf(c, SC_D1);
   B.b[2] = c->scr;
   B.b[3] = nullptr;
@@ -286,6 +286,10 @@ int mixed_flux_derivs(grmhd_ctx* c, const JobSet& js, Recorder* rec, hipStream_t
     MixedTaskList tl;
     tl.n = 0;
     for (int v = 0; v < 8; ++v) addm(tl, 2, SC_FLUX + 8 * a + v, 0, 1, odf + 8 * a + v);
+    if (c->pp.glm) {  // d_a (sqrt(gamma) B^a) and d_a psi of the stage input
+      addm(tl, 0, 29 + a, 0, 1, SC_GLM - SC_D1 + a);
+      addm(tl, 0, NF, 0, 1, SC_GLM - SC_D1 + 3 + a);
+    }
     if (c->prec == GRMHD_MIX_FP32 && c->ops.fold[a])
       HIPCHK(launch_contract_f32_fold(a, 1, tl, B, c->fop32[a][0], c->fop32[a][0], nullptr, c->ops.n,
                                       c->ops.hpad, (long long)c->L.P, js, st));
@@ -324,9 +328,9 @@ int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec
 }
 
 // FP64 derivatives of the densitised fluxes, on stream st.
-int fp64_flux_derivs(grmhd_ctx* c, const JobSet& js, Recorder* rec, hipStream_t st) {
+int fp64_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec, hipStream_t st) {
   Bases B;
-  B.b[0] = nullptr;
+  B.b[0] = const_cast<double*>(Uin);
   B.b[1] = c->scr;
   B.b[2] = (double*)c->res;
   B.b[3] = nullptr;
@@ -334,6 +338,10 @@ int fp64_flux_derivs(grmhd_ctx* c, const JobSet& js, Recorder* rec, hipStream_t 
     TaskList tl;
     tl.n = 0;
     for (int v = 0; v < 8; ++v) add(tl, 1, SC_FLUX + 8 * a + v, 1, SC_DF + 8 * a + v);
+    if (c->pp.glm) {  // d_a (sqrt(gamma) B^a) and d_a psi of the stage input
+      add(tl, 0, 29 + a, 1, SC_GLM + a);
+      add(tl, 0, NF, 1, SC_GLM + 3 + a);
+    }
     HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, js, st));
     if (rec) HIPCHK(rec->mark(GRMHD_K_DFLUX_R + a, st));
   }
@@ -357,7 +365,7 @@ int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSe
   const bool mixed = c->prec != GRMHD_FP64;
   HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, fs));
   if (rec) HIPCHK(rec->mark(GRMHD_K_C2P_FLUX, fs));
-  int rc = mixed ? mixed_flux_derivs(c, js, rec, fs) : fp64_flux_derivs(c, js, rec, fs);
+  int rc = mixed ? mixed_flux_derivs(c, Uin, js, rec, fs) : fp64_flux_derivs(c, Uin, js, rec, fs);
   if (rc) return rc;
   if (split) HIPCHK(hipEventRecord(c->ev_join, c->side));
   rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
@@ -383,7 +391,8 @@ int filter_state(grmhd_ctx* c, const JobSet& js, Recorder* rec = nullptr) {
   for (int a = 0; a < 3; ++a) {
     TaskList tl;
     tl.n = 0;
-    for (int f = 0; f < NF; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
+    const int nf = c->pp.glm ? NFA : NF;  // psi is filtered like the other fields
+    for (int f = 0; f < nf; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
     HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B, js, c->stream));
     MARK(rec, GRMHD_K_FILTER_R + a);
   }
@@ -474,6 +483,9 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
     return fail(GRMHD_E_ARG, "need Gamma > 1, cfl > 0, M >= 0, |a| <= M");
   if (phys->id_kind != GRMHD_ID_MICHEL && phys->id_kind != GRMHD_ID_TORUS)
     return fail(GRMHD_E_ARG, "unknown initial-data kind");
+  if (phys->glm != 0 && phys->glm != 1) return fail(GRMHD_E_ARG, "glm must be 0 or 1");
+  if (phys->glm && !(phys->glm_ch > 0.0 && phys->glm_tau > 0.0))
+    return fail(GRMHD_E_ARG, "GLM needs c_h > 0 and tau > 0");
   if (phys->id_kind == GRMHD_ID_TORUS &&
       !(phys->tor_r_in > 0.0 && phys->tor_r_max > phys->tor_r_in && phys->tor_rho_max > 0.0 &&
         phys->tor_atm > 0.0 && phys->tor_loop_cut >= 0.0 && phys->tor_loop_cut < 1.0))
@@ -554,6 +566,9 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->pp.gauge_k0 = phys->gauge_k0;
   c->pp.rho_floor = phys->rho_floor;
   c->pp.p_floor = phys->p_floor;
+  c->pp.glm = phys->glm;
+  c->pp.ch2 = phys->glm ? phys->glm_ch * phys->glm_ch : 0.0;
+  c->pp.itau = phys->glm ? 1.0 / phys->glm_tau : 0.0;
   c->dt = c->ops.dt;
   c->t = 0.0;
   c->step = 0;
@@ -622,6 +637,7 @@ int grmhd_init_state(grmhd_ctx* c) {
   int rc = host_initial_data(c->grid, c->phys, c->ops, &U, &K0, &err);
   if (rc) return fail(rc, err);
   HIPCHK(hipMemcpyAsync(c->U, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->U + (size_t)NF * c->L.P, 0, c->L.P * sizeof(double), c->stream));  // psi = 0
   HIPCHK(hipMemcpyAsync(c->K0, K0.data(), K0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   if ((rc = prime_guesses(c))) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -633,8 +649,11 @@ int grmhd_init_state(grmhd_ctx* c) {
 
 int grmhd_set_state(grmhd_ctx* c, const double* host_U, size_t n, const double* host_K0, double t) {
   if (!c || !host_U) return fail(GRMHD_E_ARG, "null argument");
-  if (n != (size_t)NF * c->L.P) return fail(GRMHD_E_SIZE, "state size must be 32 * P");
+  if (n != (size_t)NF * c->L.P && !(c->pp.glm && n == (size_t)NFA * c->L.P))
+    return fail(GRMHD_E_SIZE, "state size must be 32 * P (or 33 * P with GLM)");
   HIPCHK(hipMemcpyAsync(c->U, host_U, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (n == (size_t)NF * c->L.P)  // psi = 0
+    HIPCHK(hipMemsetAsync(c->U + (size_t)NF * c->L.P, 0, c->L.P * sizeof(double), c->stream));
   int rc;
   if (host_K0) {
     HIPCHK(hipMemcpyAsync(c->K0, host_K0, c->L.P * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -651,7 +670,8 @@ int grmhd_set_state(grmhd_ctx* c, const double* host_U, size_t n, const double* 
 
 int grmhd_get_state(grmhd_ctx* c, double* host_U, size_t n, double* host_K0) {
   if (!c || !host_U) return fail(GRMHD_E_ARG, "null argument");
-  if (n != (size_t)NF * c->L.P) return fail(GRMHD_E_SIZE, "state size must be 32 * P");
+  if (n != (size_t)NF * c->L.P && !(c->pp.glm && n == (size_t)NFA * c->L.P))
+    return fail(GRMHD_E_SIZE, "state size must be 32 * P (or 33 * P with GLM)");
   HIPCHK(hipMemcpyAsync(host_U, c->U, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (host_K0)
     HIPCHK(hipMemcpyAsync(host_K0, c->K0, c->L.P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -695,6 +715,7 @@ int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {
                       c->pp.gamma_ad == c0->pp.gamma_ad && c->pp.eta == c0->pp.eta &&
                       c->pp.cowling == c0->pp.cowling && c->pp.gauge_k0 == c0->pp.gauge_k0 &&
                       c->pp.rho_floor == c0->pp.rho_floor && c->pp.p_floor == c0->pp.p_floor &&
+                      c->pp.glm == c0->pp.glm && c->pp.ch2 == c0->pp.ch2 && c->pp.itau == c0->pp.itau &&
                       c->stream == c0->stream &&
                       ((const char*)c->scr - c->res) == ((const char*)c0->scr - c0->res);
     if (!same)

@@ -15,6 +15,7 @@
 namespace grmhd {
 
 constexpr int NF = 32;    // evolved fields
+constexpr int NFA = 33;   // fields per stored state: the 32, then psi (GLM contexts)
 constexpr int ND1 = 21;   // fields with first derivatives (0..20)
 constexpr int ND2 = 11;   // fields with second derivatives
 // fields with second derivatives: phi, gt_ij, alpha, beta^i
@@ -24,24 +25,25 @@ constexpr int D1_ONLY[10] = {7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
 
 // Scratch buffer: fields of P doubles.
 enum : int {
-  SC_US = 0,      // 32  stage state U^(s)
-  SC_ACC = 32,    // 32  RK accumulator
-  SC_FLUX = 64,   // 24  alpha sqrt(gamma) F^a of var v at SC_FLUX + 8a + v
-  SC_D1 = 88,     // 63  d_a f at SC_D1 + 21a + f (f = 0..20)
-  SC_D2 = 151,    // 33  d_a d_a of second-derivative field s at SC_D2 + 11a + s
-  SC_MX = 184,    // 33  mixed (r th, r ph, th ph) at SC_MX + 11m + s
-  SC_DF = 217,    // 24  d_a (alpha sqrt(gamma) F^a_v) at SC_DF + 8a + v
-  SC_RIC = 241,   // 6   Ricci tensor R_ij of the stage state
-  SC_NFIELDS = 247
+  SC_US = 0,      // 33  stage state U^(s) (+ psi)
+  SC_ACC = 33,    // 33  RK accumulator (+ psi)
+  SC_FLUX = 66,   // 24  alpha sqrt(gamma) F^a of var v at SC_FLUX + 8a + v
+  SC_D1 = 90,     // 63  d_a f at SC_D1 + 21a + f (f = 0..20)
+  SC_D2 = 153,    // 33  d_a d_a of second-derivative field s at SC_D2 + 11a + s
+  SC_MX = 186,    // 33  mixed (r th, r ph, th ph) at SC_MX + 11m + s
+  SC_DF = 219,    // 24  d_a (alpha sqrt(gamma) F^a_v) at SC_DF + 8a + v
+  SC_GLM = 243,   // 6   GLM: d_a (sqrt(gamma) B^a) at SC_GLM + a, d_a psi at SC_GLM + 3 + a
+  SC_RIC = 249,   // 6   Ricci tensor R_ij of the stage state
+  SC_NFIELDS = 255
 };
 
 // Resident buffer: fields of P doubles, then operators and small arrays.
 enum : int {
-  RS_U = 0,       // 32  state U^n
-  RS_K0 = 32,     // 1   static 1+log source
-  RS_PRIM = 33,   // 5   rho, p, v^r, v^th, v^ph (last recovery; warm start)
-  RS_FAIL = 38,   // 1   1.0 where the atmosphere policy was taken
-  RS_NFIELDS = 39
+  RS_U = 0,       // 33  state U^n (+ psi)
+  RS_K0 = 33,     // 1   static 1+log source
+  RS_PRIM = 34,   // 5   rho, p, v^r, v^th, v^ph (last recovery; warm start)
+  RS_FAIL = 39,   // 1   1.0 where the atmosphere policy was taken
+  RS_NFIELDS = 40
 };
 
 // Operators per axis: first derivative, second derivative, filter.
@@ -107,6 +109,8 @@ struct PointParams {
   double gfac, gm1g;  // Gamma/(Gamma-1), (Gamma-1)/Gamma
   int cowling, gauge_k0;
   double rho_floor, p_floor;
+  int glm;            // GLM constraint damping on (psi is field 32)
+  double ch2, itau;   // c_h^2, 1/tau of the GLM terms
 };
 
 // A folded operator on the device (even N): E^T then O^T, each Hpad x Hpad,

@@ -273,7 +273,7 @@ __device__ __forceinline__ void ricci(const Sym& gt, const Sym& gtu, const doubl
 }
 
 // derivative array offsets relative to the first-derivative block
-constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1;
+constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1, O_GLM = SC_GLM - SC_D1;
 
 }  // namespace
 
@@ -552,12 +552,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     mv(gamu, Sl, Su);
     srcT -= dot3(Su, dal);
     PHASE();
+    // GLM: induction source -sqrt(gamma) gamma^{ij} d_j psi
+    double sb[3] = {0.0, 0.0, 0.0};
+    if (pp.glm) {
+      const double dpsi[3] = {LS(O_GLM + 3), LS(O_GLM + 4), LS(O_GLM + 5)};
+      mv(gamu, dpsi, sb);
+    }
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       double r = -(LS(O_DF + v) + LS(O_DF + 8 + v) + LS(O_DF + 16 + v));
       if (v >= 1 && v <= 3) r += sqrtg * src[v - 1];
       if (v == 4) r += sqrtg * srcT;
+      if (v >= 5) r -= sqrtg * sb[v - 5];
       emit(24 + v, r);
+    }
+    if (pp.glm) {  // d_t psi = -c_h^2 d_i(sqrt(gamma) B^i) / sqrt(gamma) - psi / tau
+      const double divB = (LS(O_GLM) + LS(O_GLM + 1) + LS(O_GLM + 2)) * isg;
+      emit(32, -pp.ch2 * divB - LU(32) * pp.itau);
     }
   }
   PHASE();

@@ -18,11 +18,11 @@ def make_grid(nr, nth, nph, r_in=1.8, r_out=20.0, th_min=0.05, th_max=np.pi - 0.
 def make_phys(M=1.0, a=0.5, gamma_ad=4.0 / 3.0, cfl=0.25, eta=2.0, cowling=False, gauge_k0=True,
               r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, seed=1, rho_floor=1e-20, p_floor=1e-24,
               id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-6,
-              tor_loop_cut=0.2):
+              tor_loop_cut=0.2, glm=False, glm_ch=1.0, glm_tau=2.0):
     kind = {"michel": 0, "torus": 1}[id_kind]
     return Phys(M, a, gamma_ad, cfl, eta, int(cowling), int(gauge_k0), r_c, rho_c, beta_min,
                 pert_amp, seed, rho_floor, p_floor, kind, tor_r_in, tor_r_max, tor_rho_max, tor_atm,
-                tor_loop_cut)
+                tor_loop_cut, int(glm), glm_ch, glm_tau)
 
 
 def _ptr(t):
@@ -40,6 +40,8 @@ class Solver:
         self.grid, self.phys = grid, phys
         self.shape = (grid.nph, grid.nth, grid.nr)
         self.P = grid.nr * grid.nth * grid.nph
+        # fields of the state: 32, and psi with GLM constraint damping
+        self.nfields = NFIELDS + 1 if phys.glm else NFIELDS
         res, scr = ctypes.c_size_t(), ctypes.c_size_t()
         check(lib.grmhd_query_bytes(ctypes.byref(grid), prec, ctypes.byref(res), ctypes.byref(scr)))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -57,8 +59,8 @@ class Solver:
         dU, dK = ctypes.c_void_p(), ctypes.c_void_p()
         check(lib.grmhd_state_ptr(ctx, ctypes.byref(dU), ctypes.byref(dK)))
         off = dU.value - self.resident.data_ptr()
-        n = NFIELDS * self.P
-        self.U = self.resident[off:off + 8 * n].view(torch.float64).view((NFIELDS,) + self.shape)
+        n = self.nfields * self.P
+        self.U = self.resident[off:off + 8 * n].view(torch.float64).view((self.nfields,) + self.shape)
         offk = dK.value - self.resident.data_ptr()
         self.K0 = self.resident[offk:offk + 8 * self.P].view(torch.float64).view(self.shape)
 
@@ -79,8 +81,8 @@ class Solver:
 
     def set_state(self, U, K0=None, t=0.0):
         U = np.ascontiguousarray(U, dtype=np.float64)
-        if U.size != NFIELDS * self.P:
-            raise ValueError("state must have 32 * P entries")
+        if U.size not in (NFIELDS * self.P, self.nfields * self.P):
+            raise ValueError("state must have 32 * P entries (33 * P with GLM)")
         k = None
         if K0 is not None:
             K0 = np.ascontiguousarray(K0, dtype=np.float64)
@@ -89,7 +91,7 @@ class Solver:
                                        U.size, k, float(t)))
 
     def get_state(self, with_k0=False):
-        U = np.empty((NFIELDS,) + self.shape)
+        U = np.empty((self.nfields,) + self.shape)
         K0 = np.empty(self.shape) if with_k0 else None
         check(self.lib.grmhd_get_state(self.ctx, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), U.size,
                                        K0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if with_k0 else None))

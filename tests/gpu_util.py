@@ -21,10 +21,15 @@ GROUPS = [[0], list(range(1, 7)), list(range(7, 13)), [13], [14, 15, 16, 21, 22,
           [18, 19, 20], [24], [25, 26, 27], [28], [29, 30, 31]]
 
 
+def groups_for(n):
+    """Tensor groups of an n-field state (psi, field 32, alone)."""
+    return GROUPS + [[32]] if n > 32 else GROUPS
+
+
 def field_errors(gpu, ref):
-    """e_f for each of the 32 fields (arrays shaped (32, ...))."""
-    e = np.zeros(32)
-    for grp in GROUPS:
+    """e_f for each field (arrays shaped (32 or 33, ...))."""
+    e = np.zeros(ref.shape[0])
+    for grp in groups_for(ref.shape[0]):
         sg = max(np.abs(ref[f]).max() for f in grp)
         for f in grp:
             den = max(np.abs(ref[f]).max(), sg)
@@ -40,8 +45,8 @@ def rhs_errors(gpu, ref, U):
     pure truncation error (~0), so its own magnitude is no scale for
     round-off; the state magnitude is the rate that changes it by O(1) per
     unit time."""
-    e = np.zeros(32)
-    for grp in GROUPS:
+    e = np.zeros(ref.shape[0])
+    for grp in groups_for(ref.shape[0]):
         sg = max(max(np.abs(ref[f]).max(), np.abs(U[f]).max()) for f in grp)
         for f in grp:
             d = np.abs(gpu[f] - ref[f]).max()
