@@ -166,6 +166,49 @@ def mixed_forms(w, K, fp64_rate, Solver, make_grid, make_phys, torch):
     return out
 
 
+def glm_study(w_main, K_main, value_fp64, torch, Solver, make_grid, make_phys):
+    """GLM constraint damping (psi field; c_h = 1, tau = 0.5): the main
+    workload's throughput with it on, and its cleaning effect on 16^3 on the
+    fixed Kerr-Schild background (only the GRMHD fields evolve) from the
+    library's initial data with a divergence-carrying field perturbation:
+    max |d_i(sqrt(gamma) B^i)| (library diagnostics) every 25 RK4 steps up to
+    200 (t = 1.77 M), with and without it."""
+    glm = dict(glm=True, glm_ch=1.0, glm_tau=0.5)
+    g = w_main["grid"]
+    P = g["nr"] * g["nth"] * g["nph"]
+    s = Solver(make_grid(**g), make_phys(**dict(w_main["phys"], **glm)))
+    s.init_state()
+    s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(K_main)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = s.diagnostics()
+    s.close()
+    out = {"c_h": 1.0, "tau": 0.5, "value": P * 4 * K_main / wall, "ms_per_step": wall * 1e3 / K_main,
+           "cost_vs_plain": value_fp64 / (P * 4 * K_main / wall), "nonfinite": d["nonfinite"]}
+    w16 = workloads.WORKLOADS["ks_michel_16x16x16"]
+    study = {"grid": [16, 16, 16], "background": "fixed (Cowling)", "steps_between": 25, "max_abs_divB": {},
+             "nonfinite_end": {}}
+    for name, on in (("with_glm", True), ("without_glm", False)):
+        phys = dict(w16["phys"], cowling=True, **(glm if on else {}))
+        s = Solver(make_grid(**w16["grid"]), make_phys(**phys))
+        s.init_state()
+        U = workloads.divergence_seed(w16["grid"], s.get_state())
+        s.set_state(U, s.get_state(with_k0=True)[1])
+        series = [s.diagnostics()["max_abs_divB"]]
+        for _ in range(8):
+            s.step(25)
+            series.append(s.diagnostics()["max_abs_divB"])
+        study["t_end"] = s.time
+        study["max_abs_divB"][name] = series
+        study["nonfinite_end"][name] = s.diagnostics()["nonfinite"]
+        s.close()
+    out["divergence_study"] = study
+    return out
+
+
 def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
     """A second measured configuration (the magnetised torus at 128x96x192):
     FP64 and FP32-form throughput over the workload's step count from the
@@ -259,6 +302,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-second", action="store_true", help="skip the 128x96x192 torus configuration")
+    ap.add_argument("--no-glm", action="store_true", help="skip the GLM constraint-damping measurements")
     ap.add_argument("--serve-t-scale", type=float, default=1e-3)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 512 MiB copy + one RK4 step, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -348,6 +392,8 @@ def main():
         out["mixed_precision"] = mixed_forms(w, K, out["value"], Solver, make_grid, make_phys, torch)
     if not args.no_second:
         out["second_config"] = second_config("ks_torus_128x96x192", torch, Solver, make_grid, make_phys)
+    if not args.no_glm:
+        out["glm"] = glm_study(w, K, out["value"], torch, Solver, make_grid, make_phys)
     if not args.no_serving:
         from paper_2508_18221_amd.serve import run_stream
         jobs = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale)

@@ -16,6 +16,10 @@ Readings of the paper taken here (where it is silent or inconsistent):
     boundary lies inside the horizon and is left free; phi is periodic.
   * filter: once per step, on the new state, all 32 fields, along r, theta,
     phi; optional 2/3 dealiasing before it.
+  * fixed background (cowling = True, the solver's fixed-background version
+    in "Numerical Implementation of Coupled GRMHD-Einstein Evolution"): the
+    24 spacetime fields keep their initial values exactly; their right-hand
+    sides are zero and neither the filter nor the dealiasing touches them.
   * 1+log source: K0 = K - beta^k d_k alpha/(2 alpha) at t = 0 (stored,
     static), so that the Kerr-Schild slice is stationary with the advection
     term of the printed 1+log equation kept.
@@ -183,12 +187,15 @@ class Problem:
 
     # ---- RK4 + filter -----------------------------------------------------------
     def apply_filter(self, U):
-        out = U
+        # with a fixed background (Cowling) only the GRMHD fields (and psi)
+        # are evolved, so only they are dealiased and filtered
+        lo = 24 if self.cowling else 0
+        out = U[lo:]
         if self.dealias:
             out = self.g.dealias(out)
         if self.filter_on:
             out = self.g.filter(out, self.filt_alpha, self.filt_order)
-        return out
+        return np.concatenate([U[:lo], out]) if lo else out
 
     def step(self, U, K0, dt):
         k1 = self.rhs(U, K0)

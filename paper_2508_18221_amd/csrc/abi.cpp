@@ -34,6 +34,11 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// Max / min keeping a NaN operand (a non-finite state must not report a
+// finite extremum).
+inline double host_nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
+inline double host_nan_min(double a, double b) { return (a != a || a < b) ? a : b; }
+
 #define HIPCHK(expr)                                                                      \
   do {                                                                                    \
     hipError_t e_ = (expr);                                                               \
@@ -392,7 +397,8 @@ int filter_state(grmhd_ctx* c, const JobSet& js, Recorder* rec = nullptr) {
     TaskList tl;
     tl.n = 0;
     const int nf = c->pp.glm ? NFA : NF;  // psi is filtered like the other fields
-    for (int f = 0; f < nf; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
+    const int f0 = c->pp.cowling ? 24 : 0;  // a fixed background is not filtered
+    for (int f = f0; f < nf; ++f) add(tl, src_sel[a], src_base[a] + f, dst_sel[a], dst_base[a] + f);
     HIPCHK(contract(c, a, 1, OP_FILT, OP_FILT, tl, B, js, c->stream));
     MARK(rec, GRMHD_K_FILTER_R + a);
   }
@@ -842,11 +848,11 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     s1 += q[1];
     s2 += q[2];
     s3 += q[3];
-    mx4 = fmax(mx4, q[4]);
-    mn5 = fmin(mn5, q[5]);
-    mx6 = fmax(mx6, q[6]);
+    mx4 = host_nan_max(mx4, q[4]);
+    mn5 = host_nan_min(mn5, q[5]);
+    mx6 = host_nan_max(mx6, q[6]);
     s7 += q[7];
-    mx8 = fmax(mx8, q[8]);
+    mx8 = host_nan_max(mx8, q[8]);
     s9 += q[9];
   }
   out->ham_l2 = s9 > 0 ? sqrt(s7 / s9) : 0.0;

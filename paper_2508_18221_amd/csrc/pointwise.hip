@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // 2: acc += dt/3 k, out = Un + dt/2 k; 3: acc += dt/3 k, out = Un + dt k;
   // 4: out = acc + dt/6 k
   auto emit = [&](int f, double kf) {
-    if (frozen) kf = 0.0;
+    if (frozen || (pp.cowling && f < 24)) kf = 0.0;  // Cowling: fixed spacetime
     const size_t e = (size_t)f * P + idx;
     if (mode == 0) {
       out[e] = kf;
@@ -806,6 +806,11 @@ __global__ __launch_bounds__(256) void k_k0(const double* __restrict__ U, const 
 // [9] sum w.
 constexpr int DIAG_THREADS = 256;
 
+// Max / min that keep a NaN operand (fmax/fmin drop it), so that a state gone
+// non-finite never reports a finite extremum.
+__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
+__device__ __forceinline__ double nan_min(double a, double b) { return (a != a || a < b) ? a : b; }
+
 __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict__ U,
                                                        const double* __restrict__ prim,
                                                        const double* __restrict__ fail,
@@ -830,21 +835,21 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
     v[1] += rho * log(p / pow(rho, G)) / (G - 1.0) * sqrtg * w;
     v[2] += fail[idx];
     int nf = 0;
-    for (int f = 0; f < 32; ++f) nf += !isfinite(U[(size_t)f * P + idx]);
+    for (int f = 0; f < (pp.glm ? NFA : 32); ++f) nf += !isfinite(U[(size_t)f * P + idx]);
     v[3] += nf;
     const double dB = scr[(size_t)(SC_D1 + 0) * P + idx] + scr[(size_t)(SC_D1 + 21 + 1) * P + idx] +
                       scr[(size_t)(SC_D1 + 42 + 2) * P + idx];
-    v[4] = fmax(v[4], fabs(dB));
-    v[5] = fmin(v[5], U[(size_t)17 * P + idx]);
+    v[4] = nan_max(v[4], fabs(dB));
+    v[5] = nan_min(v[5], U[(size_t)17 * P + idx]);
     const double e4 = exp(4.0 * phi);
     Sym gam;
     for (int s = 0; s < 6; ++s) gam.m[s] = e4 * gt.m[s];
     double vv[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]}, vl[3];
     mv(gam, vv, vl);
-    v[6] = fmax(v[6], 1.0 / sqrt(1.0 - dot3(vv, vl)));
+    v[6] = nan_max(v[6], 1.0 / sqrt(1.0 - dot3(vv, vl)));
     const double h = H[idx];
     v[7] += h * h * w;
-    v[8] = fmax(v[8], fabs(h));
+    v[8] = nan_max(v[8], fabs(h));
     v[9] += w;
   }
   for (int q = 0; q < DIAG_Q; ++q) sh[q][threadIdx.x] = v[q];
@@ -852,11 +857,11 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
   for (int half = DIAG_THREADS / 2; half > 0; half >>= 1) {
     if ((int)threadIdx.x < half) {
       for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + half];
-      sh[4][threadIdx.x] = fmax(sh[4][threadIdx.x], sh[4][threadIdx.x + half]);
-      sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + half]);
-      sh[6][threadIdx.x] = fmax(sh[6][threadIdx.x], sh[6][threadIdx.x + half]);
+      sh[4][threadIdx.x] = nan_max(sh[4][threadIdx.x], sh[4][threadIdx.x + half]);
+      sh[5][threadIdx.x] = nan_min(sh[5][threadIdx.x], sh[5][threadIdx.x + half]);
+      sh[6][threadIdx.x] = nan_max(sh[6][threadIdx.x], sh[6][threadIdx.x + half]);
       sh[7][threadIdx.x] += sh[7][threadIdx.x + half];
-      sh[8][threadIdx.x] = fmax(sh[8][threadIdx.x], sh[8][threadIdx.x + half]);
+      sh[8][threadIdx.x] = nan_max(sh[8][threadIdx.x], sh[8][threadIdx.x + half]);
       sh[9][threadIdx.x] += sh[9][threadIdx.x + half];
     }
     __syncthreads();

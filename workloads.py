@@ -67,6 +67,31 @@ def oracle_kwargs(w):
     return grid_args, prob, init
 
 
+def grid_nodes(g):
+    """(r, theta, phi) node coordinates of a workload grid, each shaped
+    (n_phi, n_theta, n_r) for broadcasting: Chebyshev-Gauss-Lobatto in
+    ln r and theta (index 0 at the outer / upper end), uniform in phi."""
+    nr, nth, nph = g["nr"], g["nth"], g["nph"]
+    x = np.cos(np.pi * np.arange(nr) / (nr - 1))
+    y = np.cos(np.pi * np.arange(nth) / (nth - 1))
+    lc, lh = 0.5 * math.log(g["r_in"] * g["r_out"]), 0.5 * math.log(g["r_out"] / g["r_in"])
+    tc, th = 0.5 * (g["th_min"] + g["th_max"]), 0.5 * (g["th_max"] - g["th_min"])
+    r = np.exp(lc + lh * x)[None, None, :]
+    t = (tc + th * y)[None, :, None]
+    p = (2.0 * np.pi * np.arange(nph) / nph)[:, None, None]
+    return r, t, p
+
+
+def divergence_seed(g, U):
+    """The divergence-carrying field perturbation of the GLM studies: the
+    densitised radial field scaled by 1 + 0.05 exp(-ln(r/5)^2) sin(theta)
+    sin(phi) (a monopole's is independent of r, so its divergence vanishes)."""
+    r, t, p = grid_nodes(g)
+    U = U.copy()
+    U[29] = U[29] * (1.0 + 0.05 * np.exp(-np.log(r / 5.0) ** 2) * np.sin(t) * np.sin(p))
+    return U
+
+
 def random_fields(shape, nfields, seed):
     """Seeded standard-normal test fields (float64), for operator tests."""
     return np.random.default_rng(seed).standard_normal((nfields,) + tuple(shape))
