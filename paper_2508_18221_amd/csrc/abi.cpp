@@ -150,6 +150,10 @@ struct grmhd_ctx {
   double dt, t;
   int64_t step;
   bool have_state;
+  // fixed-background form: the SC_BG block holds the first derivatives of the
+  // current state's background (stale after init_state, set_state, state_ptr
+  // and rhs, which may change or replace it)
+  bool bg_ready = false;
 };
 
 namespace {
@@ -353,6 +357,41 @@ int fp64_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder
   return GRMHD_OK;
 }
 
+// Fixed-background form: FP64 first derivatives of the background fields
+// (phi, gt_ij, alpha, beta^i) of Ug along r, theta, phi into the SC_BG block,
+// once per background.
+int background_derivs(grmhd_ctx* c, const double* Ug, const JobSet& js) {
+  Bases B;
+  B.b[0] = const_cast<double*>(Ug);
+  B.b[1] = c->scr;
+  B.b[2] = (double*)c->res;
+  B.b[3] = nullptr;
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    for (int s = 0; s < ND2; ++s) add(tl, 0, D2_FIELD[s], 1, SC_BG + 11 * a + s);
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, js, c->stream));
+  }
+  return GRMHD_OK;
+}
+
+// Fixed-background form of one RHS evaluation (+ RK stage): primitive
+// recovery and fluxes from the stage fluid Uin on the background Ug, the flux
+// derivatives, then the GRMHD right-hand sides and stage update; all on the
+// context stream (nothing else runs beside them).
+int rhs_eval_fixed(grmhd_ctx* c, const double* Uin, const double* Ug, int mode, double* out, const JobSet& js,
+                   Recorder* rec) {
+  const bool mixed = c->prec != GRMHD_FP64;
+  HIPCHK(launch_c2p_flux(Uin, Ug, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, c->stream));
+  MARK(rec, GRMHD_K_C2P_FLUX);
+  int rc = mixed ? mixed_flux_derivs(c, Uin, js, rec, c->stream) : fp64_flux_derivs(c, Uin, js, rec, c->stream);
+  if (rc) return rc;
+  HIPCHK(launch_rhs_fixed(mode, mixed, Uin, Ug, sf(c, SC_BG), sf(c, SC_D1), c->prim, c->U, sf(c, SC_ACC), out,
+                          c->pp, js, c->stream));
+  MARK(rec, GRMHD_K_RHS_RK);
+  return GRMHD_OK;
+}
+
 // One RHS evaluation (+ RK stage update for mode >= 1) of the jobs in js,
 // addressed through context c (the first job).  Primitive recovery and the
 // flux derivatives run on the side stream while the state derivatives and the
@@ -361,6 +400,7 @@ int fp64_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder
 // stream so that each launch is timed alone.
 int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSet& js,
              Recorder* rec = nullptr) {
+  if (c->pp.cowling) return rhs_eval_fixed(c, Uin, c->U, mode, out, js, rec);
   const bool split = rec == nullptr;
   hipStream_t fs = split ? c->side : c->stream;
   if (split) {
@@ -368,7 +408,7 @@ int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSe
     HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
   }
   const bool mixed = c->prec != GRMHD_FP64;
-  HIPCHK(launch_c2p_flux(Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, fs));
+  HIPCHK(launch_c2p_flux(Uin, Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, fs));
   if (rec) HIPCHK(rec->mark(GRMHD_K_C2P_FLUX, fs));
   int rc = mixed ? mixed_flux_derivs(c, Uin, js, rec, fs) : fp64_flux_derivs(c, Uin, js, rec, fs);
   if (rc) return rc;
@@ -417,8 +457,20 @@ int rk4_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   return GRMHD_OK;
 }
 
+// Fixed-background form: make the SC_BG block current for the state's
+// background.
+int ensure_background(grmhd_ctx* c) {
+  if (!c->pp.cowling || c->bg_ready) return GRMHD_OK;
+  int rc = background_derivs(c, c->U, single(c));
+  if (rc) return rc;
+  c->bg_ready = true;
+  return GRMHD_OK;
+}
+
 int one_step(grmhd_ctx* c, Recorder* rec) {
-  int rc = rk4_step(c, single(c), rec);
+  int rc = ensure_background(c);
+  if (rc) return rc;
+  rc = rk4_step(c, single(c), rec);
   if (rc) return rc;
   c->t += c->dt;
   c->step += 1;
@@ -438,7 +490,7 @@ void release_streams(grmhd_ctx* c) {
 
 int prime_guesses(grmhd_ctx* c) {
   HIPCHK(hipMemsetAsync(c->prim, 0, 5 * c->L.P * sizeof(double), c->stream));
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, nullptr, c->floors, c->pp, single(c), c->stream));
+  HIPCHK(launch_c2p_flux(c->U, c->U, c->prim, c->fail, nullptr, c->floors, c->pp, single(c), c->stream));
   return GRMHD_OK;
 }
 
@@ -650,6 +702,7 @@ int grmhd_init_state(grmhd_ctx* c) {
   c->t = 0.0;
   c->step = 0;
   c->have_state = true;
+  c->bg_ready = false;
   return GRMHD_OK;
 }
 
@@ -671,6 +724,7 @@ int grmhd_set_state(grmhd_ctx* c, const double* host_U, size_t n, const double* 
   c->t = t;
   c->step = 0;
   c->have_state = true;
+  c->bg_ready = false;
   return GRMHD_OK;
 }
 
@@ -689,12 +743,19 @@ int grmhd_state_ptr(grmhd_ctx* c, double** dev_U, double** dev_K0) {
   if (!c) return fail(GRMHD_E_ARG, "null context");
   if (dev_U) *dev_U = c->U;
   if (dev_K0) *dev_K0 = c->K0;
+  c->bg_ready = false;  // the caller may write the background through the pointer
   return GRMHD_OK;
 }
 
 int grmhd_rhs(grmhd_ctx* c, const double* dev_U, double* dev_dUdt) {
   if (!c || !dev_U || !dev_dUdt) return fail(GRMHD_E_ARG, "null argument");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
+  if (c->pp.cowling) {  // the background of this evaluation is dev_U's spacetime
+    c->bg_ready = false;
+    int rc = background_derivs(c, dev_U, single(c));
+    if (rc) return rc;
+    return rhs_eval_fixed(c, dev_U, dev_U, 0, dev_dUdt, single(c), nullptr);
+  }
   return rhs_eval(c, dev_U, 0, dev_dUdt, single(c));
 }
 
@@ -738,6 +799,13 @@ int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {
       js.d[j] = (long long)(ctxs[j0 + j]->res - c->res);
       js.dt[j] = ctxs[j0 + j]->dt;
     }
+    bool need_bg = false;
+    for (int j = 0; j < m; ++j) need_bg = need_bg || (ctxs[j0 + j]->pp.cowling && !ctxs[j0 + j]->bg_ready);
+    if (need_bg && nsteps > 0) {
+      int rc = background_derivs(c, c->U, js);
+      if (rc) return rc;
+      for (int j = 0; j < m; ++j) ctxs[j0 + j]->bg_ready = true;
+    }
     for (int s = 0; s < nsteps; ++s) {
       int rc = rk4_step(c, js, nullptr);
       if (rc) return rc;
@@ -778,6 +846,8 @@ int grmhd_profile_step(grmhd_ctx* c, int32_t nsteps, double* ms, int32_t nkinds,
   if (!c || !ms || nkinds < GRMHD_K_COUNT) return fail(GRMHD_E_ARG, "need ms[GRMHD_K_COUNT]");
   if (nsteps < 1) return fail(GRMHD_E_ARG, "nsteps < 1");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
+  int rc0 = ensure_background(c);  // outside the timed launches
+  if (rc0) return rc0;
   Recorder rec;
   const size_t per_step = 4 * 14 + 3 + 1;  // at most 14 launches per stage, 3 filter passes, start
   rec.ev.resize(per_step);
@@ -819,7 +889,7 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
   // (into the accumulator slot, free between steps); then d_i (sqrt(gamma) B^i)
   // into free first-derivative slots
   int rc = GRMHD_OK;
-  HIPCHK(launch_c2p_flux(c->U, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, single(c), c->stream));
+  HIPCHK(launch_c2p_flux(c->U, c->U, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, single(c), c->stream));
   if ((rc = fp64_derivs(c, c->U, single(c), nullptr))) return rc;
   double* H = sf(c, SC_ACC);
   HIPCHK(launch_ham(c->U, sf(c, SC_D1), c->prim, H, c->pp, c->stream));
@@ -895,7 +965,7 @@ int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* d
 int grmhd_con2prim(grmhd_ctx* c, const double* dev_U, double* dev_prim, double* dev_flux) {
   if (!c || !dev_U || !dev_prim) return fail(GRMHD_E_ARG, "null argument");
   // guesses come from the context's last recovery; results also stored there
-  HIPCHK(launch_c2p_flux(dev_U, c->prim, c->fail, dev_flux, c->floors, c->pp, single(c), c->stream));
+  HIPCHK(launch_c2p_flux(dev_U, dev_U, c->prim, c->fail, dev_flux, c->floors, c->pp, single(c), c->stream));
   HIPCHK(hipMemcpyAsync(dev_prim, c->prim, 5 * c->L.P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return GRMHD_OK;
 }

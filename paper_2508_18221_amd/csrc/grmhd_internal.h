@@ -34,7 +34,9 @@ enum : int {
   SC_DF = 219,    // 24  d_a (alpha sqrt(gamma) F^a_v) at SC_DF + 8a + v
   SC_GLM = 243,   // 6   GLM: d_a (sqrt(gamma) B^a) at SC_GLM + a, d_a psi at SC_GLM + 3 + a
   SC_RIC = 249,   // 6   Ricci tensor R_ij of the stage state
-  SC_NFIELDS = 255
+  SC_BG = 255,    // 33  fixed-background form: d_a of background field s at SC_BG + 11a + s
+                  //     (s: phi, gt_ij, alpha, beta^i, the D2_FIELD order)
+  SC_NFIELDS = 288
 };
 
 // Resident buffer: fields of P doubles, then operators and small arrays.
@@ -175,14 +177,21 @@ hipError_t set_fold_kernel_attributes();
 hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl, const Bases& B,
                                     const FoldOp32& op0, const FoldOp32& op1, const double* g10, const int n[3],
                                     const int hpad[3], long long P, const JobSet& js, hipStream_t s);
-// floors: rho floor at the nr radial nodes, then the p floor
-hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
+// floors: rho floor at the nr radial nodes, then the p floor; the metric
+// (phi, gt_ij, alpha, beta^i) is read from Ug, the GRMHD fields from U
+hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, double* fail, double* flux,
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s);
 // mode 0: out = L(U_s); 1..4: classic RK4 stage s.  der: derivative arrays
 // (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s);
+// Fixed-background form: GRMHD (and psi) right-hand sides / RK4 stage from the
+// stage fluid Us, background state Ug, background first derivatives bg
+// (SC_BG block) and the flux derivative arrays (der as in launch_rhs_rk).
+hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const double* Ug, const double* bg,
+                            const void* der, const double* prim, const double* Un, double* acc, double* out,
+                            const PointParams& pp, const JobSet& js, hipStream_t s);
 // Ricci tensor R_ij (6 fields of P doubles, symmetric storage) of the stage
 // state from its derivative arrays (FP64 or FP32)
 hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double* R, const PointParams& pp,

@@ -279,6 +279,7 @@ constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1, 
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_c2p_flux(const double* __restrict__ U,
+                                                  const double* __restrict__ Ug,
                                                   double* __restrict__ prim,
                                                   double* __restrict__ fail,
                                                   double* __restrict__ flux,
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   {  // this job's buffers
     const long long jd = js.d[blockIdx.y];
     U = shift_ptr(U, jd);
+    Ug = shift_ptr(Ug, jd);
     prim = shift_ptr(prim, jd);
     fail = shift_ptr(fail, jd);
     floors = shift_ptr(floors, jd);
@@ -297,12 +299,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
   const int j = (int)(idx % pp.nr);
 #define LD(f) U[(size_t)(f) * P + idx]
-  const double phi = LD(0);
+#define LG(f) Ug[(size_t)(f) * P + idx]
+  const double phi = LG(0);
   Sym gt;
 #pragma unroll
-  for (int s = 0; s < 6; ++s) gt.m[s] = LD(1 + s);
-  const double alpha = LD(17);
-  double beta[3] = {LD(18), LD(19), LD(20)};
+  for (int s = 0; s < 6; ++s) gt.m[s] = LG(1 + s);
+  const double alpha = LG(17);
+  double beta[3] = {LG(18), LG(19), LG(20)};
   const double e2 = exp(2.0 * phi), e4 = e2 * e2;
   const double detgt = det_sym(gt);
   const double sqrtg = e4 * e2 * sqrt(detgt);
@@ -314,6 +317,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const double D = LD(24) * isg, tau = LD(28) * isg;
   double S[3] = {LD(25) * isg, LD(26) * isg, LD(27) * isg};
   double B[3] = {LD(29) * isg, LD(30) * isg, LD(31) * isg};
+#undef LG
 #undef LD
   // warm start Z = rho h W^2 from the last recovered primitives
   double zg = -1.0;
@@ -369,6 +373,124 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // Us, Un, acc and out may alias (in-place stages): no restrict on them; every
 // element is read and written by the same thread.
 #define PHASE() __asm__ __volatile__("" ::: "memory")
+
+// Matter terms of one point that the BSSN right-hand sides use: E, S_i,
+// S_ij and the trace of S^i_j.
+struct Matter {
+  double Em, Sl[3], Str;
+  Sym Sij;
+};
+
+// Valencia right-hand sides of one point: minus the divergence of the
+// densitised fluxes (their derivative arrays at O_DF) plus sqrt(gamma) times the
+// geometric sources of S_j and tau; with GLM the induction source
+// -sqrt(gamma) gamma^{ij} d_j psi and the psi equation.  Geometry: sqrt(gamma),
+// e^{+-4 phi}, gt_ij and its inverse, A-tilde_ij, K, alpha and the first
+// derivatives of alpha, beta^i, gt_ij and phi ([a][..] = d_a).  Each result goes
+// to emit(f, value) (f = 24..31, and 32 with GLM).
+template <typename DT, typename Emit>
+__device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __restrict__ der,
+                                               const double* __restrict__ prim, long long idx, long long P,
+                                               const PointParams& pp, double sqrtg, double e4, double em4,
+                                               const Sym& gt, const Sym& gtu, const Sym& At, double K,
+                                               double alpha, const double* dal, const double (*dbeta)[3],
+                                               const double (*dgt)[6], const double* dphi, Emit& emit) {
+#define LU(f) Us[(size_t)(f) * P + idx]
+#define LS(g) ((double)der[(size_t)(g) * P + idx])
+  Matter mt;
+  const double isg = 1.0 / sqrtg;
+  mt.Em = (LU(28) + LU(24)) * isg;
+  const double Em = mt.Em;
+  double* Sl = mt.Sl;
+  Sl[0] = LU(25) * isg;
+  Sl[1] = LU(26) * isg;
+  Sl[2] = LU(27) * isg;
+  Sym gam, gamu;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    gam.m[s] = e4 * gt.m[s];
+    gamu.m[s] = em4 * gtu.m[s];
+  }
+  Sym& Sij = mt.Sij;
+  {
+    const double rho = prim[idx], p = prim[(size_t)P + idx];
+    const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
+    const Mag m = magnetic(v, B, gam);
+    const double h = 1.0 + p / rho * pp.gfac;
+    const double cw = (rho * h + m.b2) * m.W * m.W;
+    const double ps = p + 0.5 * m.b2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int jj = i; jj < 3; ++jj)
+        Sij.m[S6(i, jj)] = cw * m.vl[i] * m.vl[jj] + ps * gam.m[S6(i, jj)] - m.bl[i] * m.bl[jj];
+  }
+  double Str = 0.0;
+  {
+    double Sup[3][3];  // S^{kl} = gamma^{ki} gamma^{lj} S_ij
+    double t[3][3];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj)
+        t[kk][jj] = gamu(kk, 0) * Sij(0, jj) + gamu(kk, 1) * Sij(1, jj) + gamu(kk, 2) * Sij(2, jj);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) Sup[kk][l] = t[kk][0] * gamu(l, 0) + t[kk][1] * gamu(l, 1) + t[kk][2] * gamu(l, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) Str += t[i][i];
+    // Sbar_{S_j} = -E d_j alpha + S_k d_j beta^k + (alpha/2) S^{kl} d_j gamma_kl,
+    // d_j gamma_kl = e^{4 phi} (d_j gt_kl + 4 gt_kl d_j phi)
+    double src[3];
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      double tt = -Em * dal[jj];
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) tt += Sl[kk] * dbeta[jj][kk];
+      double q = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) q += Sup[kk][l] * e4 * (dgt[jj][S6(kk, l)] + 4.0 * gt(kk, l) * dphi[jj]);
+      src[jj] = tt + 0.5 * alpha * q;
+    }
+    // Sbar_tau = alpha S^{kl} K_kl - S^k d_k alpha, K_kl = e^{4 phi} (A_kl + gt_kl K/3)
+    double srcT = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) srcT += Sup[kk][l] * e4 * (At(kk, l) + gt(kk, l) * K / 3.0);
+    srcT *= alpha;
+    double Su[3];
+    mv(gamu, Sl, Su);
+    srcT -= dot3(Su, dal);
+    PHASE();
+    // GLM: induction source -sqrt(gamma) gamma^{ij} d_j psi
+    double sb[3] = {0.0, 0.0, 0.0};
+    if (pp.glm) {
+      const double dpsi[3] = {LS(O_GLM + 3), LS(O_GLM + 4), LS(O_GLM + 5)};
+      mv(gamu, dpsi, sb);
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      double r = -(LS(O_DF + v) + LS(O_DF + 8 + v) + LS(O_DF + 16 + v));
+      if (v >= 1 && v <= 3) r += sqrtg * src[v - 1];
+      if (v == 4) r += sqrtg * srcT;
+      if (v >= 5) r -= sqrtg * sb[v - 5];
+      emit(24 + v, r);
+    }
+    if (pp.glm) {  // d_t psi = -c_h^2 d_i(sqrt(gamma) B^i) / sqrt(gamma) - psi / tau
+      const double divB = (LS(O_GLM) + LS(O_GLM + 1) + LS(O_GLM + 2)) * isg;
+      emit(32, -pp.ch2 * divB - LU(32) * pp.itau);
+    }
+  }
+  mt.Str = Str;
+  return mt;
+#undef LS
+#undef LU
+}
 
 template <typename DT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rhs_rk(int mode, const double* Us,
@@ -487,90 +609,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   PHASE();
 
   // ---- phase 3: matter; Valencia right-hand sides ------------------------------
-  const double isg = 1.0 / sqrtg;
-  const double Em = (LU(28) + LU(24)) * isg;
-  const double Sl[3] = {LU(25) * isg, LU(26) * isg, LU(27) * isg};
-  Sym gam, gamu;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    gam.m[s] = e4 * gt.m[s];
-    gamu.m[s] = em4 * gtu.m[s];
-  }
-  Sym Sij;
-  {
-    const double rho = prim[idx], p = prim[(size_t)P + idx];
-    const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
-    const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
-    const Mag m = magnetic(v, B, gam);
-    const double h = 1.0 + p / rho * pp.gfac;
-    const double cw = (rho * h + m.b2) * m.W * m.W;
-    const double ps = p + 0.5 * m.b2;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int jj = i; jj < 3; ++jj)
-        Sij.m[S6(i, jj)] = cw * m.vl[i] * m.vl[jj] + ps * gam.m[S6(i, jj)] - m.bl[i] * m.bl[jj];
-  }
-  double Str = 0.0;
-  {
-    double Sup[3][3];  // S^{kl} = gamma^{ki} gamma^{lj} S_ij
-    double t[3][3];
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj)
-        t[kk][jj] = gamu(kk, 0) * Sij(0, jj) + gamu(kk, 1) * Sij(1, jj) + gamu(kk, 2) * Sij(2, jj);
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int l = 0; l < 3; ++l) Sup[kk][l] = t[kk][0] * gamu(l, 0) + t[kk][1] * gamu(l, 1) + t[kk][2] * gamu(l, 2);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Str += t[i][i];
-    // Sbar_{S_j} = -E d_j alpha + S_k d_j beta^k + (alpha/2) S^{kl} d_j gamma_kl,
-    // d_j gamma_kl = e^{4 phi} (d_j gt_kl + 4 gt_kl d_j phi)
-    double src[3];
-#pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
-      double tt = -Em * dal[jj];
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) tt += Sl[kk] * dbeta[jj][kk];
-      double q = 0.0;
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) q += Sup[kk][l] * e4 * (dgt[jj][S6(kk, l)] + 4.0 * gt(kk, l) * dphi[jj]);
-      src[jj] = tt + 0.5 * alpha * q;
-    }
-    // Sbar_tau = alpha S^{kl} K_kl - S^k d_k alpha, K_kl = e^{4 phi} (A_kl + gt_kl K/3)
-    double srcT = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-      for (int l = 0; l < 3; ++l) srcT += Sup[kk][l] * e4 * (At(kk, l) + gt(kk, l) * K / 3.0);
-    srcT *= alpha;
-    double Su[3];
-    mv(gamu, Sl, Su);
-    srcT -= dot3(Su, dal);
-    PHASE();
-    // GLM: induction source -sqrt(gamma) gamma^{ij} d_j psi
-    double sb[3] = {0.0, 0.0, 0.0};
-    if (pp.glm) {
-      const double dpsi[3] = {LS(O_GLM + 3), LS(O_GLM + 4), LS(O_GLM + 5)};
-      mv(gamu, dpsi, sb);
-    }
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      double r = -(LS(O_DF + v) + LS(O_DF + 8 + v) + LS(O_DF + 16 + v));
-      if (v >= 1 && v <= 3) r += sqrtg * src[v - 1];
-      if (v == 4) r += sqrtg * srcT;
-      if (v >= 5) r -= sqrtg * sb[v - 5];
-      emit(24 + v, r);
-    }
-    if (pp.glm) {  // d_t psi = -c_h^2 d_i(sqrt(gamma) B^i) / sqrt(gamma) - psi / tau
-      const double divB = (LS(O_GLM) + LS(O_GLM + 1) + LS(O_GLM + 2)) * isg;
-      emit(32, -pp.ch2 * divB - LU(32) * pp.itau);
-    }
-  }
+  const Matter mt = valencia_rhs(Us, der, prim, idx, P, pp, sqrtg, e4, em4, gt, gtu, At, K, alpha, dal, dbeta,
+                                 dgt, dphi, emit);
+  const double Em = mt.Em;
+  const double* Sl = mt.Sl;
+  const Sym& Sij = mt.Sij;
+  const double Str = mt.Str;
   PHASE();
 
   // ---- phase 4: Ricci tensor (computed by k_ricci) ------------------------------
@@ -680,6 +724,88 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #undef LU
 }
 #undef PHASE
+
+// ---------------------------------------------------------------------------
+// Fixed-background (Cowling) form: right-hand sides and RK4 stage update of
+// the GRMHD fields (and psi) only.  The geometry comes from the fixed
+// background state Ug (phi, gt_ij, A-tilde_ij, K, alpha) and its first
+// derivatives bg (d_a of background field s at 11 a + s, s = phi, gt_ij, alpha,
+// beta^i); the fluid from the stage state Us.  Mode 0 also writes zero
+// right-hand sides for the 24 spacetime fields.  Stage modes as in k_rhs_rk.
+template <typename DT>
+__global__ __launch_bounds__(256) void k_rhs_fixed(int mode, const double* Us, const double* __restrict__ Ug,
+                                                   const double* __restrict__ bg, const DT* __restrict__ der,
+                                                   const double* __restrict__ prim, const double* Un, double* acc,
+                                                   double* out, PointParams pp, JobSet js) {
+  const long long P = pp.P;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= P) return;
+  const double dt = js.dt[blockIdx.y];
+  {  // this job's buffers
+    const long long jd = js.d[blockIdx.y];
+    Us = shift_ptr(Us, jd);
+    Ug = shift_ptr(Ug, jd);
+    bg = shift_ptr(bg, jd);
+    der = shift_ptr(der, jd);
+    prim = shift_ptr(prim, jd);
+    Un = shift_ptr(Un, jd);
+    acc = shift_ptr(acc, jd);
+    out = shift_ptr(out, jd);
+  }
+  const int j = (int)(idx % pp.nr);
+  const int k = (int)((idx / pp.nr) % pp.nth);
+  const bool frozen = (j == 0 || k == 0 || k == pp.nth - 1);
+  auto emit = [&](int f, double kf) {
+    if (frozen) kf = 0.0;
+    const size_t e = (size_t)f * P + idx;
+    if (mode == 0) {
+      out[e] = kf;
+    } else if (mode == 1) {
+      const double un = Un[e];
+      acc[e] = un + (dt / 6.0) * kf;
+      out[e] = un + 0.5 * dt * kf;
+    } else if (mode == 2) {
+      acc[e] += (dt / 3.0) * kf;
+      out[e] = Un[e] + 0.5 * dt * kf;
+    } else if (mode == 3) {
+      acc[e] += (dt / 3.0) * kf;
+      out[e] = Un[e] + dt * kf;
+    } else {
+      out[e] = acc[e] + (dt / 6.0) * kf;
+    }
+  };
+  if (mode == 0)
+    for (int f = 0; f < 24; ++f) out[(size_t)f * P + idx] = 0.0;
+#define LG(f) Ug[(size_t)(f) * P + idx]
+#define BG(a, s) bg[(size_t)(11 * (a) + (s)) * P + idx]
+  const double phi = LG(0);
+  Sym gt, At;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    gt.m[s] = LG(1 + s);
+    At.m[s] = LG(7 + s);
+  }
+  const double K = LG(13);
+  const double alpha = LG(17);
+  const double detgt = det_sym(gt);
+  const Sym gtu = inv_sym(gt, detgt);
+  const double e4 = exp(4.0 * phi), em4 = 1.0 / e4;
+  const double sqrtg = e4 * exp(2.0 * phi) * sqrt(detgt);
+  double dphi[3], dal[3], dbeta[3][3], dgt[3][6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    dphi[a] = BG(a, 0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dgt[a][q] = BG(a, 1 + q);
+    dal[a] = BG(a, 7);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dbeta[a][i] = BG(a, 8 + i);
+  }
+#undef BG
+#undef LG
+  (void)valencia_rhs(Us, der, prim, idx, P, pp, sqrtg, e4, em4, gt, gtu, At, K, alpha, dal, dbeta, dgt, dphi,
+                     emit);
+}
 
 // ---------------------------------------------------------------------------
 // Ricci tensor R_ij = Rt_ij + Rphi_ij of the stage state (the heaviest part of
@@ -873,10 +999,11 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(long long P) { return (unsigned)((P + 255) / 256); }
 
-hipError_t launch_c2p_flux(const double* U, double* prim, double* fail, double* flux,
+hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, double* fail, double* flux,
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s) {
   if (js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, prim, fail, flux, floors, pp, js);
+  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, Ug, prim, fail, flux, floors, pp,
+                     js);
   return hipGetLastError();
 }
 
@@ -901,6 +1028,19 @@ hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* d
   else
     hipLaunchKernelGGL(k_rhs_rk<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us,
                        (const double*)der, prim, K0, Ric, Un, acc, out, pp, js);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const double* Ug, const double* bg,
+                            const void* der, const double* prim, const double* Un, double* acc, double* out,
+                            const PointParams& pp, const JobSet& js, hipStream_t s) {
+  if (mode < 0 || mode > 4 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
+  if (der_f32)
+    hipLaunchKernelGGL(k_rhs_fixed<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, Ug, bg,
+                       (const float*)der, prim, Un, acc, out, pp, js);
+  else
+    hipLaunchKernelGGL(k_rhs_fixed<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, Ug, bg,
+                       (const double*)der, prim, Un, acc, out, pp, js);
   return hipGetLastError();
 }
 
