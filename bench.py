@@ -28,6 +28,11 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (matrix and vector)
 RIDGE = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
 
 
+def progress(msg):
+    """One progress line on stderr (the JSON result goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def launch_costs(nr, nth, nph):
     """Per grid point, for one launch of each kind: algorithmic HBM bytes
     (compulsory reads + writes of that launch) and the FP64 MFMA flops the
@@ -54,6 +59,20 @@ def launch_costs(nr, nth, nph):
     c["rhs_rk"] = (259 * d, 0.0)                        # mean over the 4 stage modes (251, 283, 283, 219)
     for k, n in (("filter_r", nr), ("filter_t", nth), ("filter_p", nph)):
         c[k] = (64 * d, fl(n) * 32)
+    return c
+
+
+def fixed_launch_costs(nr, nth, nph):
+    """launch_costs for the fixed-background (Cowling) stage: the same
+    recovery and flux-derivative launches, the GRMHD-only RHS kernel
+    (background 15 fields and 33 first derivatives, stage fluid 8, primitives
+    5, flux derivatives 24, and the RK traffic of the 8 GRMHD fields: mean over
+    the 4 stage modes of 109 doubles) and a filter over the 8 GRMHD fields."""
+    d = 8.0
+    c = launch_costs(nr, nth, nph)
+    c["rhs_rk"] = (109 * d, 0.0)
+    for k, n in (("filter_r", nr), ("filter_t", nth), ("filter_p", nph)):
+        c[k] = (16 * d, (n if n % 2 == 0 else 2 * n) * 8)
     return c
 
 
@@ -209,6 +228,40 @@ def glm_study(w_main, K_main, value_fp64, torch, Solver, make_grid, make_phys):
     return out
 
 
+def fixed_background(w, K, value_fp64, torch, Solver, make_grid, make_phys):
+    """Fixed-background (Cowling) form of the main workload: only the 8
+    GRMHD fields evolve on the Kerr-Schild background (its first derivatives
+    computed once).  FP64 and FP32-form throughput, per-launch times and the
+    RHS kernel's roofline."""
+    g = w["grid"]
+    P = g["nr"] * g["nth"] * g["nph"]
+    costs = fixed_launch_costs(g["nr"], g["nth"], g["nph"])
+    out = {"workload": "fixed Kerr-Schild background, " + "x".join(str(g[k]) for k in ("nr", "nth", "nph"))}
+    for name, prec in (("fp64", 0), ("fp32", 1)):
+        s = Solver(make_grid(**g), make_phys(**dict(w["phys"], cowling=True)), prec=prec)
+        s.init_state()
+        s.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = s.profile_step(2)
+        d = s.diagnostics()
+        s.close()
+        r = {"value": P * 4 * K / wall, "unit": "point-stage updates/s", "ms_per_step": wall * 1e3 / K,
+             "vs_coupled_fp64": (P * 4 * K / wall) / value_fp64, "nonfinite": d["nonfinite"],
+             "c2p_fail": d["c2p_fail"],
+             "kernels_ms": {k: round(v[0], 5) for k, v in prof.items() if v[1]}}
+        if prec == 0:
+            r["roofline"] = roofline("rhs_rk", prof["rhs_rk"][0], P, costs)
+            r["roofline"]["kernel"] = "rhs_fixed"
+            r["stage_ideal_ms_per_step"] = round(sum(ideal_ms(k, P, costs) * v[1] / 2 for k, v in prof.items()
+                                                     if v[1]), 5)
+        out[name] = r
+    return out
+
+
 def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
     """A second measured configuration (the magnetised torus at 128x96x192):
     FP64 and FP32-form throughput over the workload's step count from the
@@ -303,6 +356,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-second", action="store_true", help="skip the 128x96x192 torus configuration")
     ap.add_argument("--no-glm", action="store_true", help="skip the GLM constraint-damping measurements")
+    ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-background (Cowling) form")
     ap.add_argument("--serve-t-scale", type=float, default=1e-3)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 512 MiB copy + one RK4 step, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -388,12 +442,19 @@ def main():
         "serial_launch_sum_ms_per_step": round(measured_step, 5),
         "kernels": kernels,
     }
+    progress(f"main workload done: {out['value']:.4g} point-stage updates/s")
     if not args.no_mixed:
         out["mixed_precision"] = mixed_forms(w, K, out["value"], Solver, make_grid, make_phys, torch)
+        progress("mixed-precision forms done")
     if not args.no_second:
         out["second_config"] = second_config("ks_torus_128x96x192", torch, Solver, make_grid, make_phys)
+        progress("torus 128x96x192 done")
     if not args.no_glm:
         out["glm"] = glm_study(w, K, out["value"], torch, Solver, make_grid, make_phys)
+        progress("GLM form done")
+    if not args.no_fixed:
+        out["fixed_background"] = fixed_background(w, K, out["value"], torch, Solver, make_grid, make_phys)
+        progress("fixed-background form done")
     if not args.no_serving:
         from paper_2508_18221_amd.serve import run_stream
         jobs = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale)
@@ -402,11 +463,19 @@ def main():
                                     f"T~U[10,100] M scaled by {args.serve_t_scale:g}, HBM budget 200 GB",
                           "t_scale": args.serve_t_scale}
         for name, prec in (("fp64", 0), ("fp32", 1)):
-            out["serving"][name] = run_stream(jobs, prec=prec, budget=200e9)
+            out["serving"][name] = run_stream(jobs, prec=prec, budget=200e9, log=progress)
+            progress(f"served stream ({name}) done")
         # capacity: the same 256 jobs all arriving at t = 0 (continuous batching at full load)
         burst = [dict(j, arrival=0.0) for j in jobs]
-        out["serving"]["fp64_burst"] = run_stream(burst, prec=0, budget=200e9)
+        out["serving"]["fp64_burst"] = run_stream(burst, prec=0, budget=200e9, log=progress)
+        progress("served burst done")
+        # mixed workload: half the jobs on the fixed background (a second job class per grid)
+        mix = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale, cowling_frac=0.5)
+        out["serving"]["fp64_half_fixed_background"] = run_stream(mix, prec=0, budget=200e9, log=progress)
+        progress("served mixed workload done")
+        out["serving"]["fp64_half_fixed_background"]["fixed_background_jobs"] = sum(j["cowling"] for j in mix)
     if not args.no_cpu_baseline:
+        progress("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

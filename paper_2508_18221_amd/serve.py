@@ -28,7 +28,7 @@ def job_args(j):
     horizon radius so that it stays inside the horizon for every spin."""
     nr, nth, nph = j["grid"]
     grid = make_grid(nr, nth, nph, r_in=1.8 * horizon(j["a"]) / horizon(0.5))
-    phys = make_phys(a=j["a"], beta_min=j["beta"], seed=j["seed"])
+    phys = make_phys(a=j["a"], beta_min=j["beta"], seed=j["seed"], cowling=j.get("cowling", False))
     return grid, phys
 
 
@@ -69,7 +69,7 @@ def run_stream(jobs, prec=0, budget=200e9, max_batch=32, log=None):
 
     by_grid = {}
     for inf, j in done:
-        key = f"{inf['nr']}x{inf['nth']}x{inf['nph']}"
+        key = f"{inf['nr']}x{inf['nth']}x{inf['nph']}" + ("/fixed" if j.get("cowling") else "")
         by_grid.setdefault(key, []).append(inf["t_done"] - t0 - j["arrival"])
     return {
         "jobs": n, "completed": len(done), "rejected": int(st["rejected"]), "ticks": ticks,
@@ -90,8 +90,10 @@ def main():
     ap.add_argument("--t-scale", type=float, default=1e-3)
     ap.add_argument("--prec", type=int, default=0)
     ap.add_argument("--budget", type=float, default=200e9)
+    ap.add_argument("--cowling-frac", type=float, default=0.0,
+                    help="fraction of jobs on the fixed Kerr-Schild background")
     args = ap.parse_args()
-    jobs = workloads.served_stream(args.jobs, args.rate, t_scale=args.t_scale)
+    jobs = workloads.served_stream(args.jobs, args.rate, t_scale=args.t_scale, cowling_frac=args.cowling_frac)
     out = run_stream(jobs, prec=args.prec, budget=args.budget, log=lambda m: print(m, flush=True))
     out.update(rate=args.rate, t_scale=args.t_scale, prec=args.prec)
     print(json.dumps(out), flush=True)

@@ -174,3 +174,42 @@ def test_cowling_fp32_form_close_to_fp64():
     rel = np.sqrt(np.mean((a[24] - b[24]) ** 2)) / np.sqrt(np.mean(a[24] ** 2))
     log(f"  rho-densitised L2 rel diff {rel:.2e}")
     assert 0 < rel < 1e-6
+
+
+def test_served_fixed_background_job_in_a_mix_equals_alone():
+    """A fixed-background job served beside coupled jobs of the same grid
+    (two job classes) ends bitwise where it ends when stepped alone."""
+    from paper_2508_18221_amd import Server, Solver, make_grid, make_phys
+    log("[server] 2 coupled + 2 fixed-background jobs on 16^3; one fixed job vs alone")
+    srv = Server(budget=8 << 30, max_batch=32)
+    specs = [(0.3, 50.0, 31, 0.05, False), (0.6, 200.0, 32, 0.07, True), (0.8, 20.0, 33, 0.04, False),
+             (0.1, 500.0, 34, 0.06, True)]
+    rh = lambda a: 1.0 + np.sqrt(1.0 - a * a)  # noqa: E731
+
+    def args(a, beta, sd, cow):
+        return (make_grid(16, 16, 16, r_in=1.8 * rh(a) / rh(0.5)),
+                make_phys(a=a, beta_min=beta, seed=sd, cowling=cow))
+
+    ids = []
+    for k, (a, beta, sd, T, cow) in enumerate(specs):
+        g, p = args(a, beta, sd, cow)
+        ids.append(srv.submit(g, p, T, keep_state=(k == 1)))
+        srv.tick()
+    while srv.tick() > 0:
+        pass
+    st = srv.stats()
+    assert st["completed"] == len(specs)
+    info = srv.poll(ids[1])
+    a, beta, sd, T, cow = specs[1]
+    served = srv.result(ids[1], (16, 16, 16))
+    srv.close()
+    g, p = args(a, beta, sd, cow)
+    s = Solver(g, p)
+    s.init_state()
+    U0 = s.get_state()
+    s.set_dt(info["dt"])
+    s.step(info["steps_total"])
+    alone = s.get_state()
+    s.close()
+    assert np.array_equal(served[:24], U0[:24])
+    assert np.array_equal(served, alone)

@@ -117,12 +117,15 @@ def smooth_fields(grid_r, grid_th, grid_ph, nfields, seed):
 SERVED_GRIDS = [(16, 16, 16), (32, 32, 64), (48, 48, 96), (64, 64, 128)]
 
 
-def served_stream(n_jobs=256, rate=4.0, seed=2508, t_scale=1.0):
+def served_stream(n_jobs=256, rate=4.0, seed=2508, t_scale=1.0, cowling_frac=0.0):
     """Seeded job stream: Poisson arrivals at `rate` jobs/s; per job spin
     a ~ U[0, 0.95], plasma beta ~ logU[10, 1000], a grid drawn uniformly from
     SERVED_GRIDS, end time T ~ U[10, 100] M times t_scale, and its own
-    perturbation seed."""
+    perturbation seed.  A fraction cowling_frac of the jobs (drawn from a
+    generator of their own, so the rest of the stream does not change) evolve
+    on the fixed Kerr-Schild background."""
     rng = np.random.default_rng(seed)
+    fixed = np.random.default_rng(seed + 1).random(n_jobs) < cowling_frac
     gaps = rng.exponential(1.0 / rate, n_jobs)
     arrivals = np.cumsum(gaps) - gaps[0]
     jobs = []
@@ -130,5 +133,6 @@ def served_stream(n_jobs=256, rate=4.0, seed=2508, t_scale=1.0):
         jobs.append(dict(arrival=float(arrivals[i]), a=float(rng.uniform(0.0, 0.95)),
                          beta=float(10 ** rng.uniform(1.0, 3.0)),
                          grid=SERVED_GRIDS[int(rng.integers(0, len(SERVED_GRIDS)))],
-                         T=float(rng.uniform(10.0, 100.0) * t_scale), seed=int(rng.integers(1, 2 ** 62))))
+                         T=float(rng.uniform(10.0, 100.0) * t_scale), seed=int(rng.integers(1, 2 ** 62)),
+                         cowling=bool(fixed[i])))
     return jobs
