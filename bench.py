@@ -256,6 +256,7 @@ def fixed_background(w, K, value_fp64, torch, Solver, make_grid, make_phys):
         if prec == 0:
             r["roofline"] = roofline("rhs_rk", prof["rhs_rk"][0], P, costs)
             r["roofline"]["kernel"] = "rhs_fixed"
+            r["roofline"]["traffic"] = traffic_record("rhs_fixed")
             r["stage_ideal_ms_per_step"] = round(sum(ideal_ms(k, P, costs) * v[1] / 2 for k, v in prof.items()
                                                      if v[1]), 5)
         out[name] = r
@@ -314,7 +315,9 @@ def traffic_probe(w, torch, Solver, make_grid, make_phys):
     """Workload for the HBM traffic counters (run under rocprofv3 --pmc): one
     plain device copy of 512 MiB (the counters' scale reference: 512 MiB read,
     512 MiB written) followed by one FP64 RK4 step of the workload, its
-    launches in order on one stream (the profiled form of the step)."""
+    launches in order on one stream (the profiled form of the step), then one
+    step of its fixed-background form (after the one-off background
+    derivatives)."""
     n = 64 * 1024 * 1024
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -326,7 +329,13 @@ def traffic_probe(w, torch, Solver, make_grid, make_phys):
     s.profile_step(1)  # every launch in order on one stream
     torch.cuda.synchronize()
     s.close()
-    print(json.dumps({"traffic_probe": True, "copy_bytes_each_way": n * 8, "steps": 1}), flush=True)
+    s = Solver(make_grid(**w["grid"]), make_phys(**dict(w["phys"], cowling=True)))
+    s.init_state()
+    s.profile_step(1)
+    torch.cuda.synchronize()
+    s.close()
+    print(json.dumps({"traffic_probe": True, "copy_bytes_each_way": n * 8, "steps": 1, "fixed_steps": 1}),
+          flush=True)
 
 
 def traffic_record(kernel):
