@@ -101,7 +101,11 @@ typedef struct {
   double gamma_ad;          /* ideal-gas adiabatic index Gamma               */
   double cfl;               /* dt = cfl * min(dr, r dth, r sin th dph)       */
   double eta;               /* Gamma-driver damping                          */
-  int32_t cowling;          /* 1: spacetime right-hand sides set to zero     */
+  int32_t cowling;          /* 1: fixed background (the paper's fixed-
+                               background version, "Numerical Implementation
+                               of Coupled GRMHD-Einstein Evolution"): only
+                               fields 24.. evolve and are filtered; the 24
+                               spacetime fields keep their values bit for bit */
   int32_t gauge_k0;         /* 1: d_t alpha = ... - 2 alpha (K - K0)         */
   double r_c, rho_c;        /* Michel sonic radius, density there            */
   double beta_min;          /* min over nodes of 2p/b^2 (monopole field)     */
@@ -174,12 +178,16 @@ int grmhd_get_state(grmhd_ctx* ctx, double* host_U, size_t n, double* host_K0);
 
 /* Device pointers of the resident state (32 P doubles, then psi in a GLM
  * context) and K0 (P doubles);
- * valid for the context's lifetime.  No copy, no sync. */
+ * valid for the context's lifetime.  No copy, no sync.  With cowling = 1 the
+ * background (fields 0..23) is read, and its first derivatives recomputed, at
+ * the first step after init_state, set_state or this call: write the
+ * background through the pointer before stepping, not between steps. */
 int grmhd_state_ptr(grmhd_ctx* ctx, double** dev_U, double** dev_K0);
 
 /* One RHS evaluation dU/dt = L(U) of a device state (32 P doubles, 33 P in
  * a GLM context) into dev_dUdt (as many); uses the context's K0 and con2prim
- * guesses.
+ * guesses.  With cowling = 1 the background is dev_U's spacetime (its first
+ * derivatives are recomputed) and fields 0..23 of dev_dUdt are set to zero.
  * dev_U may be the resident state.  Async. */
 int grmhd_rhs(grmhd_ctx* ctx, const double* dev_U, double* dev_dUdt);
 
