@@ -88,6 +88,11 @@ typedef struct {
   double filt_alpha;        /* exponential filter strength (36)              */
   int32_t filt_order;       /* filter order p (16)                           */
   int32_t filter_on;        /* 1: filter after every RK4 step                */
+  int32_t dealias;          /* 1: 2/3 truncation after every RK4 step
+                               (Methods, "Dealiasing and Spectral Filtering":
+                               Chebyshev modes k > 2(N-1)/3 and Fourier modes
+                               |k| > N/3 zeroed), before the filter; the two
+                               share one operator pass                       */
 } grmhd_grid;
 
 /* Initial-data kinds: magnetised Michel accretion (monopole field, density
@@ -124,6 +129,13 @@ typedef struct {
    * induction source -sqrt(gamma) gamma^{ij} d_j psi.  0: off (32 fields). */
   int32_t glm;
   double glm_ch, glm_tau;   /* c_h (<= 1 for the CFL bound) and tau > 0      */
+  /* 1: the paper's operator-split coupled step (Methods, "Coupled Main Loop";
+   * reading: symmetric form) in place of the unsplit classic RK4: classic RK4
+   * over dt/2 of fields 24.. on the frozen spacetime, one forward-Euler step
+   * dt of the 24 spacetime fields (BSSN + gauge) with the matter frozen,
+   * classic RK4 over dt/2 of fields 24.. on the new spacetime, then the
+   * filter.  Requires cowling = 0. */
+  int32_t split;
 } grmhd_phys;
 
 /* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"). */

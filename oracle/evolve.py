@@ -35,6 +35,17 @@ Readings of the paper taken here (where it is silent or inconsistent):
     printed sign the pair d_t psi, d_t B would give d_tt psi = -c_h^2
     Laplacian psi, which is ill-posed); no lapse factors, as printed.
     Frozen at the same boundary nodes and filtered like the other fields.
+  * operator-split coupled step (optional, Methods "Coupled Main Loop" and the
+    coupled-evolution description: a GRMHD half-step on the current spacetime,
+    primitive recovery and T^{mu nu}, a first-order Euler BSSN step, then the
+    gauge update): taken in its symmetric form, classic RK4 over dt/2 of the
+    GRMHD fields (and psi) with the spacetime frozen, one forward-Euler step
+    dt of the 24 spacetime fields (BSSN and gauge together, their right-hand
+    sides evaluated after the first half-step) with the matter frozen, classic
+    RK4 over dt/2 of the GRMHD fields on the new spacetime, then the filter.
+    The literal loop has one fluid half-step per step, which would advance the
+    fluid by dt/2 while the spacetime advances by dt; the symmetric form is the
+    one in which both advance by dt.
 """
 
 import numpy as np
@@ -96,7 +107,10 @@ class Problem:
     def __init__(self, grid, M=1.0, a=0.5, Gamma=4.0 / 3.0, eta=2.0, cowling=False,
                  gauge_k0=True, rho_floor=1e-20, p_floor=1e-24, filt_alpha=36.0,
                  filt_order=16, filter_on=True, dealias=False, cfl=0.25, glm=False, glm_ch=1.0,
-                 glm_tau=2.0):
+                 glm_tau=2.0, split=False):
+        if split and cowling:
+            raise ValueError("the split step needs the coupled system")
+        self.split = split
         self.g = grid
         self.glm, self.glm_ch, self.glm_tau = glm, glm_ch, glm_tau
         self.M, self.a, self.Gamma, self.eta = M, a, Gamma, eta
@@ -197,7 +211,32 @@ class Problem:
             out = self.g.filter(out, self.filt_alpha, self.filt_order)
         return np.concatenate([U[:lo], out]) if lo else out
 
+    def fluid_rk4(self, U, K0, h):
+        """Classic RK4 over h of the GRMHD fields (and psi) with the spacetime
+        fields held at their values in U (split step)."""
+        def L(V):
+            R = self.rhs(V, K0)
+            R[:24] = 0.0
+            return R
+        k1 = L(U)
+        k2 = L(U + 0.5 * h * k1)
+        k3 = L(U + 0.5 * h * k2)
+        k4 = L(U + h * k3)
+        return U + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+    def step_split(self, U, K0, dt):
+        """Operator-split coupled step (symmetric reading of the coupled main
+        loop): fluid dt/2, Euler BSSN + gauge dt with the matter frozen, fluid
+        dt/2, filter."""
+        V = self.fluid_rk4(U, K0, 0.5 * dt)
+        R = self.rhs(V, K0)
+        W = V.copy()
+        W[:24] = V[:24] + dt * R[:24]
+        return self.apply_filter(self.fluid_rk4(W, K0, 0.5 * dt))
+
     def step(self, U, K0, dt):
+        if self.split:
+            return self.step_split(U, K0, dt)
         k1 = self.rhs(U, K0)
         k2 = self.rhs(U + 0.5 * dt * k1, K0)
         k3 = self.rhs(U + 0.5 * dt * k2, K0)

@@ -19,7 +19,7 @@ class Grid(ctypes.Structure):
                 ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
                 ("th_min", ctypes.c_double), ("th_max", ctypes.c_double),
                 ("filt_alpha", ctypes.c_double), ("filt_order", ctypes.c_int32),
-                ("filter_on", ctypes.c_int32)]
+                ("filter_on", ctypes.c_int32), ("dealias", ctypes.c_int32)]
 
 
 class Phys(ctypes.Structure):
@@ -31,7 +31,8 @@ class Phys(ctypes.Structure):
                 ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
                 ("id_kind", ctypes.c_int32), ("tor_r_in", ctypes.c_double), ("tor_r_max", ctypes.c_double),
                 ("tor_rho_max", ctypes.c_double), ("tor_atm", ctypes.c_double), ("tor_loop_cut", ctypes.c_double),
-                ("glm", ctypes.c_int32), ("glm_ch", ctypes.c_double), ("glm_tau", ctypes.c_double)]
+                ("glm", ctypes.c_int32), ("glm_ch", ctypes.c_double), ("glm_tau", ctypes.c_double),
+                ("split", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):

@@ -64,6 +64,8 @@ int validate_grid(const grmhd_grid* g) {
   if (!(g->th_min > 0 && g->th_max > g->th_min && g->th_max < M_PI))
     return fail(GRMHD_E_ARG, "need 0 < th_min < th_max < pi");
   if (g->filt_order < 1) return fail(GRMHD_E_ARG, "filter order must be >= 1");
+  if ((g->filter_on != 0 && g->filter_on != 1) || (g->dealias != 0 && g->dealias != 1))
+    return fail(GRMHD_E_ARG, "filter_on and dealias must be 0 or 1");
   return GRMHD_OK;
 }
 
@@ -360,7 +362,7 @@ int fp64_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder
 // Fixed-background form: FP64 first derivatives of the background fields
 // (phi, gt_ij, alpha, beta^i) of Ug along r, theta, phi into the SC_BG block,
 // once per background.
-int background_derivs(grmhd_ctx* c, const double* Ug, const JobSet& js) {
+int background_derivs(grmhd_ctx* c, const double* Ug, const JobSet& js, Recorder* rec = nullptr) {
   Bases B;
   B.b[0] = const_cast<double*>(Ug);
   B.b[1] = c->scr;
@@ -371,6 +373,7 @@ int background_derivs(grmhd_ctx* c, const double* Ug, const JobSet& js) {
     tl.n = 0;
     for (int s = 0; s < ND2; ++s) add(tl, 0, D2_FIELD[s], 1, SC_BG + 11 * a + s);
     HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, js, c->stream));
+    MARK(rec, GRMHD_K_DERIV_R + a);
   }
   return GRMHD_OK;
 }
@@ -446,14 +449,36 @@ int filter_state(grmhd_ctx* c, const JobSet& js, Recorder* rec = nullptr) {
 }
 
 // One classic RK4 step (+ filter) of the jobs in js, addressed through c.
+// Classic RK4 over the step of each job halved, of the GRMHD fields (and psi)
+// on the spacetime currently in the state (split step): the background
+// derivatives of that spacetime, then four fixed-background stages.
+int fluid_half_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
+  JobSet half = js;
+  for (int j = 0; j < js.n; ++j) half.dt[j] = 0.5 * js.dt[j];
+  double* Us = sf(c, SC_US);
+  int rc;
+  if ((rc = background_derivs(c, c->U, half, rec))) return rc;
+  if ((rc = rhs_eval_fixed(c, c->U, c->U, 1, Us, half, rec))) return rc;
+  if ((rc = rhs_eval_fixed(c, Us, c->U, 2, Us, half, rec))) return rc;
+  if ((rc = rhs_eval_fixed(c, Us, c->U, 3, Us, half, rec))) return rc;
+  return rhs_eval_fixed(c, Us, c->U, 4, c->U, half, rec);
+}
+
 int rk4_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   double* Us = sf(c, SC_US);
   int rc;
+  if (c->phys.split) {  // fluid dt/2, Euler BSSN + gauge dt (matter frozen), fluid dt/2
+    if ((rc = fluid_half_step(c, js, rec))) return rc;
+    if ((rc = rhs_eval(c, c->U, 5, c->U, js, rec))) return rc;
+    if ((rc = fluid_half_step(c, js, rec))) return rc;
+    if ((c->grid.filter_on || c->grid.dealias) && (rc = filter_state(c, js, rec))) return rc;
+    return GRMHD_OK;
+  }
   if ((rc = rhs_eval(c, c->U, 1, Us, js, rec))) return rc;
   if ((rc = rhs_eval(c, Us, 2, Us, js, rec))) return rc;
   if ((rc = rhs_eval(c, Us, 3, Us, js, rec))) return rc;
   if ((rc = rhs_eval(c, Us, 4, c->U, js, rec))) return rc;
-  if (c->grid.filter_on && (rc = filter_state(c, js, rec))) return rc;
+  if ((c->grid.filter_on || c->grid.dealias) && (rc = filter_state(c, js, rec))) return rc;
   return GRMHD_OK;
 }
 
@@ -542,6 +567,8 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   if (phys->id_kind != GRMHD_ID_MICHEL && phys->id_kind != GRMHD_ID_TORUS)
     return fail(GRMHD_E_ARG, "unknown initial-data kind");
   if (phys->glm != 0 && phys->glm != 1) return fail(GRMHD_E_ARG, "glm must be 0 or 1");
+  if (phys->split != 0 && phys->split != 1) return fail(GRMHD_E_ARG, "split must be 0 or 1");
+  if (phys->split && phys->cowling) return fail(GRMHD_E_ARG, "the split step needs cowling = 0");
   if (phys->glm && !(phys->glm_ch > 0.0 && phys->glm_tau > 0.0))
     return fail(GRMHD_E_ARG, "GLM needs c_h > 0 and tau > 0");
   if (phys->id_kind == GRMHD_ID_TORUS &&
@@ -778,11 +805,13 @@ int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {
     if (!c) return fail(GRMHD_E_ARG, "null context in batch");
     if (!c->have_state) return fail(GRMHD_E_STATE, "context in batch has no state");
     const bool same = c->grid.nr == c0->grid.nr && c->grid.nth == c0->grid.nth && c->grid.nph == c0->grid.nph &&
-                      c->grid.filter_on == c0->grid.filter_on && c->prec == c0->prec &&
+                      c->grid.filter_on == c0->grid.filter_on && c->grid.dealias == c0->grid.dealias &&
+                      c->prec == c0->prec &&
                       c->pp.gamma_ad == c0->pp.gamma_ad && c->pp.eta == c0->pp.eta &&
                       c->pp.cowling == c0->pp.cowling && c->pp.gauge_k0 == c0->pp.gauge_k0 &&
                       c->pp.rho_floor == c0->pp.rho_floor && c->pp.p_floor == c0->pp.p_floor &&
                       c->pp.glm == c0->pp.glm && c->pp.ch2 == c0->pp.ch2 && c->pp.itau == c0->pp.itau &&
+                      c->phys.split == c0->phys.split &&
                       c->stream == c0->stream &&
                       ((const char*)c->scr - c->res) == ((const char*)c0->scr - c0->res);
     if (!same)

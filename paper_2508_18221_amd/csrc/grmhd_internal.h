@@ -181,7 +181,8 @@ hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl,
 // (phi, gt_ij, alpha, beta^i) is read from Ug, the GRMHD fields from U
 hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, double* fail, double* flux,
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s);
-// mode 0: out = L(U_s); 1..4: classic RK4 stage s.  der: derivative arrays
+// mode 0: out = L(U_s); 1..4: classic RK4 stage s; 5: forward Euler of the
+// spacetime fields (split step; Us = Un = out).  der: derivative arrays
 // (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Ric, const double* Un, double* acc, double* out,

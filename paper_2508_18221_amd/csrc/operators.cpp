@@ -69,17 +69,21 @@ void zero_row_sums(std::vector<ld>& D, int n) {
   }
 }
 
-// Chebyshev modal filter: F = V diag(sigma) V^{-1} with V_jk = T_k(x_j) =
+// Chebyshev modal filter: F = V diag(m) V^{-1} with V_jk = T_k(x_j) =
 // cos(k j pi/(N-1)) and the discrete inverse c_k = 2/((N-1) cb_k) sum_l
-// f_l T_k(x_l)/cb_l (cb = 2 at the end indices, 1 otherwise).
-std::vector<ld> cheb_filter(int n, ld alpha, int order) {
+// f_l T_k(x_l)/cb_l (cb = 2 at the end indices, 1 otherwise).  The modal
+// factor m_k is sigma(k) when sig_on, times the 2/3 truncation mask
+// (k <= 2(N-1)/3) when trunc: both act diagonally on the modes, so the
+// truncation followed by the filter is this one matrix.
+std::vector<ld> cheb_filter(int n, ld alpha, int order, bool sig_on, bool trunc) {
   const int n1 = n - 1;
   std::vector<ld> T((size_t)n * n);
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j) T[(size_t)k * n + j] = cosl((ld)k * j * PI_L / n1);
   std::vector<ld> F((size_t)n * n, 0.0L);
   for (int k = 0; k < n; ++k) {
-    ld sig = expl(-alpha * powl((ld)k / (ld)n1, (ld)order));
+    ld sig = sig_on ? expl(-alpha * powl((ld)k / (ld)n1, (ld)order)) : 1.0L;
+    if (trunc && 3 * k > 2 * n1) sig = 0.0L;
     ld cbk = (k == 0 || k == n1) ? 2.0L : 1.0L;
     for (int j = 0; j < n; ++j) {
       ld a = sig * T[(size_t)k * n + j] * 2.0L / (n1 * cbk);
@@ -93,8 +97,9 @@ std::vector<ld> cheb_filter(int n, ld alpha, int order) {
 }
 
 // Fourier operators at the nodes: (1/N) sum_k Re[m(k) e^{i k (phi_j - phi_l)}]
-// over k = -N/2+1 .. N/2.  kind 1: m = ik; 2: m = -k^2; 3: m = sigma(|k|).
-std::vector<ld> fourier_op(int n, int kind, ld alpha, int order) {
+// over k = -N/2+1 .. N/2.  kind 1: m = ik; 2: m = -k^2; 3: m = sigma(|k|)
+// (1 unless sig_on), times the 2/3 truncation mask |k| <= N/3 when trunc.
+std::vector<ld> fourier_op(int n, int kind, ld alpha, int order, bool sig_on = true, bool trunc = false) {
   // the entries depend on (j - l) mod n only
   const ld h = 2.0L * PI_L / n;
   std::vector<ld> c(n, 0.0L);
@@ -105,7 +110,8 @@ std::vector<ld> fourier_op(int n, int kind, ld alpha, int order) {
       ld arg = (ld)m * h;
       if (kind == 1) s += -(ld)k * sinl(arg);
       else if (kind == 2) s += -(ld)k * k * cosl(arg);
-      else s += expl(-alpha * powl(fabsl((ld)k) / (ld)(n / 2), (ld)order)) * cosl(arg);
+      else if (!(trunc && 3 * (k < 0 ? -k : k) > n))
+        s += (sig_on ? expl(-alpha * powl(fabsl((ld)k) / (ld)(n / 2), (ld)order)) : 1.0L) * cosl(arg);
     }
     c[d] = s / n;
   }
@@ -228,7 +234,7 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     store_transposed(R2, nn, ops->npad[0], &ops->at[0][OP_D2]);
     store_mixed(R1, nn, ops->npad[0], ops->kpad[0], &ops->at32[0][0], &ops->bhi[0][0], &ops->blo[0][0]);
     store_mixed(R2, nn, ops->npad[0], ops->kpad[0], &ops->at32[0][1], &ops->bhi[0][1], &ops->blo[0][1]);
-    const std::vector<ld> Fr = cheb_filter(nn, g.filt_alpha, g.filt_order);
+    const std::vector<ld> Fr = cheb_filter(nn, g.filt_alpha, g.filt_order, g.filter_on, g.dealias);
     store_transposed(Fr, nn, ops->npad[0], &ops->at[0][OP_FILT]);
     if (ops->fold[0]) {
       // folded forms act with the unmapped D1, D2; the map enters as row
@@ -257,7 +263,7 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     store_transposed(D2, nn, ops->npad[1], &ops->at[1][OP_D2]);
     store_mixed(D1, nn, ops->npad[1], ops->kpad[1], &ops->at32[1][0], &ops->bhi[1][0], &ops->blo[1][0]);
     store_mixed(D2, nn, ops->npad[1], ops->kpad[1], &ops->at32[1][1], &ops->bhi[1][1], &ops->blo[1][1]);
-    const std::vector<ld> Ft = cheb_filter(nn, g.filt_alpha, g.filt_order);
+    const std::vector<ld> Ft = cheb_filter(nn, g.filt_alpha, g.filt_order, g.filter_on, g.dealias);
     store_transposed(Ft, nn, ops->npad[1], &ops->at[1][OP_FILT]);
     if (ops->fold[1]) {
       store_fold(D1, nn, ops->hpad[1], &ops->fmat[1][OP_D1]);
@@ -273,7 +279,7 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
     store_transposed(F2, nn, ops->npad[2], &ops->at[2][OP_D2]);
     store_mixed(F1, nn, ops->npad[2], ops->kpad[2], &ops->at32[2][0], &ops->bhi[2][0], &ops->blo[2][0]);
     store_mixed(F2, nn, ops->npad[2], ops->kpad[2], &ops->at32[2][1], &ops->bhi[2][1], &ops->blo[2][1]);
-    const std::vector<ld> Fp = fourier_op(nn, 3, g.filt_alpha, g.filt_order);
+    const std::vector<ld> Fp = fourier_op(nn, 3, g.filt_alpha, g.filt_order, g.filter_on, g.dealias);
     store_transposed(Fp, nn, ops->npad[2], &ops->at[2][OP_FILT]);
     if (ops->fold[2]) {
       store_fold(F1, nn, ops->hpad[2], &ops->fmat[2][OP_D1]);

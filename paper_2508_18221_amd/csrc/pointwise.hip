@@ -531,12 +531,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // accumulator holds Un + dt sum_s b_s k_s, so the last stage does not read Un
   // mode 0: out = k; 1: acc = Un + dt/6 k, out = Un + dt/2 k;
   // 2: acc += dt/3 k, out = Un + dt/2 k; 3: acc += dt/3 k, out = Un + dt k;
-  // 4: out = acc + dt/6 k
+  // 4: out = acc + dt/6 k; 5 (split step): forward Euler out = Un + dt k of the
+  // 24 spacetime fields only, the matter fields are not written
   auto emit = [&](int f, double kf) {
     if (frozen || (pp.cowling && f < 24)) kf = 0.0;  // Cowling: fixed spacetime
     const size_t e = (size_t)f * P + idx;
     if (mode == 0) {
       out[e] = kf;
+    } else if (mode == 5) {
+      if (f < 24) out[e] = Un[e] + dt * kf;
     } else if (mode == 1) {
       const double un = Un[e];
       acc[e] = un + (dt / 6.0) * kf;
@@ -1021,7 +1024,7 @@ hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double*
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s) {
-  if (mode < 0 || mode > 4 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
+  if (mode < 0 || mode > 5 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
   if (der_f32)
     hipLaunchKernelGGL(k_rhs_rk<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, (const float*)der,
                        prim, K0, Ric, Un, acc, out, pp, js);

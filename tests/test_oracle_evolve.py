@@ -152,6 +152,35 @@ def test_cowling_background_fixed_through_steps():
     assert np.abs(W[:24] - U[:24]).max() > 0
 
 
+def test_split_step_sub_steps_and_first_order():
+    """Operator-split coupled step (symmetric reading): its fluid sub-step
+    leaves the spacetime bit for bit and its Euler sub-step the matter; and
+    it converges to the unsplit RK4 solution at first order in dt (the
+    forward-Euler spacetime update): halving dt halves the difference, for the
+    spacetime and the matter fields alike."""
+    g = spectral.Grid(8, 8, 6, R_IN, R_OUT, TH0, TH1)
+    pu = evolve.Problem(g, a=0.5, filter_on=False)
+    ps = evolve.Problem(g, a=0.5, filter_on=False, split=True)
+    U, K0, _ = evolve.initial_state(g, pu, pert_amp=1e-3)
+    dt = pu.dt()
+    V = ps.fluid_rk4(U, K0, 0.5 * dt)
+    assert np.array_equal(V[:24], U[:24]) and np.abs(V[24:] - U[24:]).max() > 0
+    T = 2 * dt
+    ref = pu.evolve(U, K0, T / 32, 32)
+    groups = [list(range(24)), [24], [25, 26, 27], [28], [29, 30, 31]]
+    errs = []
+    for n in (2, 4, 8):
+        W = ps.evolve(U, K0, T / n, n)
+        errs.append([np.abs(W[q] - ref[q]).max() / np.abs(ref[q]).max() for q in groups])
+    errs = np.array(errs)
+    assert np.all(errs[0] > 0)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(ratios[:, 0] > 1.9) and np.all(ratios[:, 0] < 2.1), ratios
+    assert np.all(ratios > 1.6) and np.all(ratios < 2.6), ratios
+    with pytest.raises(ValueError):
+        evolve.Problem(g, cowling=True, split=True)
+
+
 @pytest.mark.slow
 def test_ten_steps_small_grid_sane():
     g = grid16()

@@ -55,13 +55,14 @@ def oracle_kwargs(w):
     prob = dict(M=p["M"], a=p["a"], Gamma=p["gamma_ad"], eta=p["eta"], cowling=p["cowling"],
                 gauge_k0=p["gauge_k0"], rho_floor=p["rho_floor"], p_floor=p["p_floor"],
                 filt_alpha=g["filt_alpha"], filt_order=g["filt_order"], filter_on=g["filter_on"],
+                dealias=g.get("dealias", False),
                 cfl=p["cfl"])
     init = dict(r_c=p["r_c"], rho_c=p["rho_c"], beta_min=p["beta_min"], pert_amp=p["pert_amp"],
                 seed=p["seed"])
     for k in ("id_kind", "tor_r_in", "tor_r_max", "tor_rho_max", "tor_atm", "tor_loop_cut"):
         if k in p:
             init[k] = p[k]
-    for k in ("glm", "glm_ch", "glm_tau"):
+    for k in ("glm", "glm_ch", "glm_tau", "split"):
         if k in p:
             prob[k] = p[k]
     return grid_args, prob, init
