@@ -136,6 +136,14 @@ typedef struct {
    * classic RK4 over dt/2 of fields 24.. on the new spacetime, then the
    * filter.  Requires cowling = 0. */
   int32_t split;
+  /* Primitive recovery: 0 the exact inverse (safeguarded Newton), 1 the
+   * paper's damped iteration (Methods, "The Primitive Variable Recovery";
+   * readings: predicted values from the standard conserved variables, velocity
+   * update with the index raised by gamma^{ij}, lambda = 0.5 halved on a
+   * residual increase, at most 40 tries, then one Newton step on eps) started
+   * from the previous recovery; the recovery right after init_state or
+   * set_state is exact. */
+  int32_t c2p_damped;
 } grmhd_phys;
 
 /* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"). */

@@ -46,12 +46,16 @@ Readings of the paper taken here (where it is silent or inconsistent):
     The literal loop has one fluid half-step per step, which would advance the
     fluid by dt/2 while the spacetime advances by dt; the symmetric form is the
     one in which both advance by dt.
+  * primitive recovery: the exact inverse by default; optionally the paper's
+    damped iteration (c2p = "damped", grmhd.con2prim_damped) started from the
+    primitives of the previous recovery (the first recovery of a Problem is
+    exact), so a Problem carries that chain from call to call.
 """
 
 import numpy as np
 
 from . import spectral
-from .grmhd import inv3, det3, con2prim, fluxes, matter_3p1, sources_3p1
+from .grmhd import inv3, det3, con2prim, con2prim_damped, fluxes, matter_3p1, sources_3p1
 from .bssn import bssn_rhs, SYM
 
 # State layout: 32 fields, each a (n_phi, n_theta, n_r) array.
@@ -107,7 +111,11 @@ class Problem:
     def __init__(self, grid, M=1.0, a=0.5, Gamma=4.0 / 3.0, eta=2.0, cowling=False,
                  gauge_k0=True, rho_floor=1e-20, p_floor=1e-24, filt_alpha=36.0,
                  filt_order=16, filter_on=True, dealias=False, cfl=0.25, glm=False, glm_ch=1.0,
-                 glm_tau=2.0, split=False):
+                 glm_tau=2.0, split=False, c2p="exact"):
+        if c2p not in ("exact", "damped"):
+            raise ValueError("c2p must be 'exact' or 'damped'")
+        self.c2p = c2p
+        self.guess = None  # previous primitives (damped recovery)
         if split and cowling:
             raise ValueError("the split step needs the coupled system")
         self.split = split
@@ -145,7 +153,13 @@ class Problem:
         f, m = unpack(U)
         gam, gamu, sqrtg = self.metric(f)
         D, S, tau, B = m['sD'] / sqrtg, m['sS'] / sqrtg, m['stau'] / sqrtg, m['sB'] / sqrtg
-        rho, p, v, fail = con2prim(D, S, tau, B, gam, gamu, self.Gamma, self.rho_fl, self.p_fl)
+        if self.c2p == "damped" and self.guess is not None:
+            rho, p, v, fail, _ = con2prim_damped(D, S, tau, B, gam, gamu, self.Gamma, self.rho_fl, self.p_fl,
+                                                 *self.guess)
+        else:
+            rho, p, v, fail = con2prim(D, S, tau, B, gam, gamu, self.Gamma, self.rho_fl, self.p_fl)
+        if self.c2p == "damped":
+            self.guess = (rho, p, v)
         return dict(rho=rho, p=p, v=v, fail=fail, D=D, S=S, tau=tau, B=B,
                     gam=gam, gamu=gamu, sqrtg=sqrtg)
 

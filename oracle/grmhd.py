@@ -160,6 +160,89 @@ def con2prim(D, S_lo, tau, B_up, gam, gamu, Gamma, rho_fl, p_fl):
     return rho, p, v_up, fail
 
 
+def con2prim_damped(D, S_lo, tau, B_up, gam, gamu, Gamma, rho_fl, p_fl, rho0, p0, v0,
+                    maxit=40, lam0=0.5, tol=1e-15):
+    """The paper's damped iteration for the primitive state (Methods, "The
+    Primitive Variable Recovery"), started from a previous primitive state
+    (rho0, p0, v0^i).  Readings: the predicted conserved variables are those of
+    the current primitives (prim_to_cons, so the fixed point is the exact
+    inverse); the velocity update raises Delta S_j with gamma^{ij}; the residual
+    is |Delta S|_gamma + |Delta tau| with |Delta S|_gamma^2 =
+    gamma^{ij} Delta S_i Delta S_j; one damping factor lambda = 0.5 for v and
+    eps, halved (and the step retried from the previous iterate) whenever a
+    step does not lower the residual or leaves v^2 < 1, eps > 0; stop once the
+    residual is below tol (|S|_gamma + |tau| + D), or after maxit tries; if not
+    converged, one Newton step on eps at fixed rho and v (d tau/d eps =
+    rho (Gamma W^2 - (Gamma - 1))).  An unusable guess (rho0 or p0 <= 0,
+    v0^2 >= 1) starts from v = 0, rho = D, eps = max((tau - B^2/2)/D,
+    eps_floor).  Failure policy as con2prim.  Returns rho, p, v_up, fail,
+    iterations taken."""
+    D = np.asarray(D, float)
+    bad = ~((D > 0.0) & (tau + D > 0.0))
+    Dc = np.where(bad, 1.0, D)
+    tc = np.where(bad, 1.0, tau)
+    B_lo = lower(gam, B_up)
+    B2 = dot(B_up, B_lo)
+    gm1 = Gamma - 1.0
+    with np.errstate(invalid='ignore', divide='ignore'):
+        v2g = dot(lower(gam, v0), v0)
+        ok = (rho0 > 0.0) & (p0 > 0.0) & (v2g < 1.0)
+        v = np.where(ok[None], v0, 0.0)
+        eps_fl = p_fl / (gm1 * rho_fl)
+        eps = np.where(ok, p0 / (gm1 * np.where(ok, rho0, 1.0)), np.maximum((tc - 0.5 * B2) / Dc, eps_fl))
+    S_up = np.einsum('ij...,j...->i...', gamu, S_lo)
+    scale = np.sqrt(dot(S_lo, S_up)) + np.abs(tc) + Dc
+
+    def lorentz_of(vv):
+        return 1.0 / np.sqrt(1.0 - dot(lower(gam, vv), vv))
+
+    def resid(rr, ee, vv):
+        _, Sp, tp = prim_to_cons(rr, gm1 * rr * ee, vv, B_up, gam, Gamma)
+        dS = S_lo - Sp
+        dT = tc - tp
+        return np.sqrt(dot(dS, np.einsum('ij...,j...->i...', gamu, dS))) + np.abs(dT), dS, dT
+
+    rho = Dc / lorentz_of(v)
+    r, dS, dT = resid(rho, eps, v)
+    conv = r <= tol * scale
+    lam = np.full(D.shape, lam0)
+    its = np.zeros(D.shape, dtype=int)
+    for _ in range(maxit):
+        act = ~conv
+        if not act.any():
+            break
+        its += act
+        W = lorentz_of(v)
+        h = 1.0 + Gamma * eps
+        vt = v + lam * np.einsum('ij...,j...->i...', gamu, dS) / (rho * h * W * W)
+        et = eps + lam * dT / (rho * W * W)
+        with np.errstate(invalid='ignore', divide='ignore'):
+            v2t = dot(lower(gam, vt), vt)
+            phys = (v2t < 1.0) & (et > 0.0)
+            vs = np.where(phys[None], vt, v)  # keep the arithmetic finite where rejected
+            es = np.where(phys, et, eps)
+            rt = Dc / lorentz_of(vs)
+            r_t, dS_t, dT_t = resid(rt, es, vs)
+        acc = act & phys & (r_t < r)
+        lam = np.where(act & ~acc, 0.5 * lam, lam)
+        v = np.where(acc[None], vt, v)
+        eps = np.where(acc, et, eps)
+        rho = np.where(acc, rt, rho)
+        r = np.where(acc, r_t, r)
+        dS = np.where(acc[None], dS_t, dS)
+        dT = np.where(acc, dT_t, dT)
+        conv = conv | (acc & (r_t <= tol * scale))
+    W = lorentz_of(v)
+    eps = np.where(conv, eps, eps + dT / (rho * (Gamma * W * W - gm1)))
+    p = gm1 * rho * eps
+    v2 = dot(lower(gam, v), v)
+    fail = bad | ~(v2 < 1.0) | ~(rho >= rho_fl) | ~(p >= p_fl)
+    rho = np.where(fail, rho_fl, rho)
+    p = np.where(fail, p_fl, p)
+    v = np.where(fail[None], 0.0, v)
+    return rho, p, v, fail, its
+
+
 def fluxes(D, S_lo, tau, B_up, rho, p, v_up, alpha, beta, gam, sqrtg):
     """Densitised fluxes alpha sqrt(gamma) F^i of (D, S_j, tau, B^k).
 

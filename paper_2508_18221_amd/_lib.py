@@ -32,7 +32,7 @@ class Phys(ctypes.Structure):
                 ("id_kind", ctypes.c_int32), ("tor_r_in", ctypes.c_double), ("tor_r_max", ctypes.c_double),
                 ("tor_rho_max", ctypes.c_double), ("tor_atm", ctypes.c_double), ("tor_loop_cut", ctypes.c_double),
                 ("glm", ctypes.c_int32), ("glm_ch", ctypes.c_double), ("glm_tau", ctypes.c_double),
-                ("split", ctypes.c_int32)]
+                ("split", ctypes.c_int32), ("c2p_damped", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):

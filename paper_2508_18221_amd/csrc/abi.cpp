@@ -513,9 +513,13 @@ void release_streams(grmhd_ctx* c) {
   c->side = nullptr;
 }
 
+// The recovery right after a state upload is exact (it seeds the warm start
+// of either recovery).
 int prime_guesses(grmhd_ctx* c) {
   HIPCHK(hipMemsetAsync(c->prim, 0, 5 * c->L.P * sizeof(double), c->stream));
-  HIPCHK(launch_c2p_flux(c->U, c->U, c->prim, c->fail, nullptr, c->floors, c->pp, single(c), c->stream));
+  PointParams exact = c->pp;
+  exact.c2p_damped = 0;
+  HIPCHK(launch_c2p_flux(c->U, c->U, c->prim, c->fail, nullptr, c->floors, exact, single(c), c->stream));
   return GRMHD_OK;
 }
 
@@ -569,6 +573,7 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   if (phys->glm != 0 && phys->glm != 1) return fail(GRMHD_E_ARG, "glm must be 0 or 1");
   if (phys->split != 0 && phys->split != 1) return fail(GRMHD_E_ARG, "split must be 0 or 1");
   if (phys->split && phys->cowling) return fail(GRMHD_E_ARG, "the split step needs cowling = 0");
+  if (phys->c2p_damped != 0 && phys->c2p_damped != 1) return fail(GRMHD_E_ARG, "c2p_damped must be 0 or 1");
   if (phys->glm && !(phys->glm_ch > 0.0 && phys->glm_tau > 0.0))
     return fail(GRMHD_E_ARG, "GLM needs c_h > 0 and tau > 0");
   if (phys->id_kind == GRMHD_ID_TORUS &&
@@ -652,6 +657,7 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   c->pp.rho_floor = phys->rho_floor;
   c->pp.p_floor = phys->p_floor;
   c->pp.glm = phys->glm;
+  c->pp.c2p_damped = phys->c2p_damped;
   c->pp.ch2 = phys->glm ? phys->glm_ch * phys->glm_ch : 0.0;
   c->pp.itau = phys->glm ? 1.0 / phys->glm_tau : 0.0;
   c->dt = c->ops.dt;
@@ -811,7 +817,7 @@ int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {
                       c->pp.cowling == c0->pp.cowling && c->pp.gauge_k0 == c0->pp.gauge_k0 &&
                       c->pp.rho_floor == c0->pp.rho_floor && c->pp.p_floor == c0->pp.p_floor &&
                       c->pp.glm == c0->pp.glm && c->pp.ch2 == c0->pp.ch2 && c->pp.itau == c0->pp.itau &&
-                      c->phys.split == c0->phys.split &&
+                      c->phys.split == c0->phys.split && c->pp.c2p_damped == c0->pp.c2p_damped &&
                       c->stream == c0->stream &&
                       ((const char*)c->scr - c->res) == ((const char*)c0->scr - c0->res);
     if (!same)

@@ -113,6 +113,7 @@ struct PointParams {
   double rho_floor, p_floor;
   int glm;            // GLM constraint damping on (psi is field 32)
   double ch2, itau;   // c_h^2, 1/tau of the GLM terms
+  int c2p_damped;     // primitive recovery by the paper's damped iteration
 };
 
 // A folded operator on the device (even N): E^T then O^T, each Hpad x Hpad,

@@ -156,6 +156,120 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
   return o;
 }
 
+// The paper's damped iteration for the primitive state (Methods, "The
+// Primitive Variable Recovery"), from the previous primitives (rho0, p0, v0^i).
+// Readings: predicted values are the conserved variables of the current
+// primitives (so the fixed point is the exact inverse); the velocity update
+// raises Delta S_j with gamma^{ij}; residual |Delta S|_gamma + |Delta tau|; one
+// damping factor lambda = 0.5, halved (step retried from the previous iterate)
+// when a step does not lower the residual or leaves v^2 < 1, eps > 0; stop
+// below 1e-15 (|S|_gamma + |tau| + D) or after 40 tries; if not converged one
+// Newton step on eps at fixed rho, v.  An unusable guess starts from v = 0,
+// eps = max((tau - B^2/2)/D, eps_floor).  Failure policy as con2prim.
+struct DampedState {
+  double rho, eps, v[3];
+};
+
+__device__ __forceinline__ double damped_resid(const DampedState& x, const double* S, double tau,
+                                               const double* B, const double* Bl, double B2, const Sym& gam,
+                                               const Sym& gamu, double G, double* dS, double& dT) {
+  double vl[3];
+  mv(gam, x.v, vl);
+  const double v2 = dot3(x.v, vl);
+  const double W2 = 1.0 / (1.0 - v2), W = sqrt(W2);
+  const double p = (G - 1.0) * x.rho * x.eps;
+  const double h = 1.0 + x.eps + p / x.rho;
+  const double Z = x.rho * h * W2;
+  const double Bv = dot3(B, vl);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dS[i] = S[i] - ((Z + B2) * vl[i] - Bv * Bl[i]);
+  dT = tau - (Z - p + B2 - 0.5 * (B2 / W2 + Bv * Bv) - x.rho * W);
+  double dSu[3];
+  mv(gamu, dS, dSu);
+  return sqrt(dot3(dS, dSu)) + fabs(dT);
+}
+
+__device__ C2POut con2prim_damped(double D, const double* S, double tau, const double* B, const Sym& gam,
+                                  const Sym& gamu, double G, double rho_fl, double p_fl, double rho0, double p0,
+                                  const double* v0) {
+  C2POut o;
+  const bool bad = !(D > 0.0 && tau + D > 0.0);
+  const double Dc = bad ? 1.0 : D, tc = bad ? 1.0 : tau;
+  double Bl[3];
+  mv(gam, B, Bl);
+  const double B2 = dot3(B, Bl);
+  const double gm1 = G - 1.0;
+  DampedState x;
+  {
+    double v0l[3];
+    mv(gam, v0, v0l);
+    const bool ok = rho0 > 0.0 && p0 > 0.0 && dot3(v0, v0l) < 1.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x.v[i] = ok ? v0[i] : 0.0;
+    x.eps = ok ? p0 / (gm1 * rho0) : fmax((tc - 0.5 * B2) / Dc, p_fl / (gm1 * rho_fl));
+    double vl[3];
+    mv(gam, x.v, vl);
+    x.rho = Dc / (1.0 / sqrt(1.0 - dot3(x.v, vl)));
+  }
+  double Su[3];
+  mv(gamu, S, Su);
+  const double scale = sqrt(dot3(S, Su)) + fabs(tc) + Dc;
+  double dS[3], dT;
+  double r = damped_resid(x, S, tc, B, Bl, B2, gam, gamu, G, dS, dT);
+  bool conv = r <= 1e-15 * scale;
+  double lam = 0.5;
+  for (int it = 0; it < 40 && !conv; ++it) {
+    double vl[3];
+    mv(gam, x.v, vl);
+    const double W2 = 1.0 / (1.0 - dot3(x.v, vl));
+    const double h = 1.0 + G * x.eps;
+    double dSu[3];
+    mv(gamu, dS, dSu);
+    DampedState t;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t.v[i] = x.v[i] + lam * dSu[i] / (x.rho * h * W2);
+    t.eps = x.eps + lam * dT / (x.rho * W2);
+    double tl[3];
+    mv(gam, t.v, tl);
+    const double v2t = dot3(t.v, tl);
+    bool acc = v2t < 1.0 && t.eps > 0.0;
+    double dSt[3], dTt, rt = 0.0;
+    if (acc) {
+      t.rho = Dc / (1.0 / sqrt(1.0 - v2t));
+      rt = damped_resid(t, S, tc, B, Bl, B2, gam, gamu, G, dSt, dTt);
+      acc = rt < r;
+    }
+    if (acc) {
+      x = t;
+      r = rt;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dS[i] = dSt[i];
+      dT = dTt;
+      conv = rt <= 1e-15 * scale;
+    } else {
+      lam *= 0.5;
+    }
+  }
+  double vl[3];
+  mv(gam, x.v, vl);
+  const double v2 = dot3(x.v, vl);
+  if (!conv) {
+    const double W2 = 1.0 / (1.0 - v2);
+    x.eps += dT / (x.rho * (G * W2 - gm1));
+  }
+  o.rho = x.rho;
+  o.p = gm1 * x.rho * x.eps;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) o.v[i] = x.v[i];
+  o.fail = bad || !(v2 < 1.0) || !(o.rho >= rho_fl) || !(o.p >= p_fl);
+  if (o.fail) {
+    o.rho = rho_fl;
+    o.p = p_fl;
+    o.v[0] = o.v[1] = o.v[2] = 0.0;
+  }
+  return o;
+}
+
 // Magnetic quantities for Eulerian field B^i and velocity v^i:
 // W, alpha b^0 = W (B.v), b_i = B_i/W + W (B.v) v_i, b^2 = B^2/W^2 + (B.v)^2.
 struct Mag {
@@ -278,7 +392,10 @@ constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1, 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_c2p_flux(const double* __restrict__ U,
+// DAMPED: the paper's damped iteration in place of the safeguarded Newton
+// (its own instantiation, so the default kernel keeps its register budget).
+template <bool DAMPED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DAMPED ? 2 : 4))) void k_c2p_flux(const double* __restrict__ U,
                                                   const double* __restrict__ Ug,
                                                   double* __restrict__ prim,
                                                   double* __restrict__ fail,
@@ -319,6 +436,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   double B[3] = {LD(29) * isg, LD(30) * isg, LD(31) * isg};
 #undef LG
 #undef LD
+  const double rho_fl = floors[j], p_fl = floors[pp.nr + j];
+  C2POut c;
+  if (DAMPED) {  // the paper's iteration from the last recovered primitives
+    const double vg[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    c = con2prim_damped(D, S, tau, B, gam, gamu, pp.gamma_ad, rho_fl, p_fl, prim[idx], prim[(size_t)P + idx], vg);
+  } else {
   // warm start Z = rho h W^2 from the last recovered primitives
   double zg = -1.0;
   {
@@ -330,8 +453,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (rg > 0.0 && pg > 0.0 && v2 < 1.0)
       zg = (rg + pg * pp.gfac) / (1.0 - v2);
   }
-  const double rho_fl = floors[j], p_fl = floors[pp.nr + j];
-  C2POut c = con2prim(D, S, tau, B, gam, gamu, pp.gamma_ad, pp.gm1g, rho_fl, p_fl, zg);
+  c = con2prim(D, S, tau, B, gam, gamu, pp.gamma_ad, pp.gm1g, rho_fl, p_fl, zg);
+  }
   prim[idx] = c.rho;
   prim[(size_t)P + idx] = c.p;
   prim[2 * (size_t)P + idx] = c.v[0];
@@ -1005,8 +1128,12 @@ static inline unsigned nblk(long long P) { return (unsigned)((P + 255) / 256); }
 hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, double* fail, double* flux,
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s) {
   if (js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_c2p_flux, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, Ug, prim, fail, flux, floors, pp,
-                     js);
+  if (pp.c2p_damped)
+    hipLaunchKernelGGL(k_c2p_flux<true>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, Ug, prim, fail, flux, floors,
+                       pp, js);
+  else
+    hipLaunchKernelGGL(k_c2p_flux<false>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, U, Ug, prim, fail, flux, floors,
+                       pp, js);
   return hipGetLastError();
 }
 

@@ -18,11 +18,11 @@ def make_grid(nr, nth, nph, r_in=1.8, r_out=20.0, th_min=0.05, th_max=np.pi - 0.
 def make_phys(M=1.0, a=0.5, gamma_ad=4.0 / 3.0, cfl=0.25, eta=2.0, cowling=False, gauge_k0=True,
               r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, seed=1, rho_floor=1e-20, p_floor=1e-24,
               id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-6,
-              tor_loop_cut=0.2, glm=False, glm_ch=1.0, glm_tau=2.0, split=False):
+              tor_loop_cut=0.2, glm=False, glm_ch=1.0, glm_tau=2.0, split=False, c2p="exact"):
     kind = {"michel": 0, "torus": 1}[id_kind]
     return Phys(M, a, gamma_ad, cfl, eta, int(cowling), int(gauge_k0), r_c, rho_c, beta_min,
                 pert_amp, seed, rho_floor, p_floor, kind, tor_r_in, tor_r_max, tor_rho_max, tor_atm,
-                tor_loop_cut, int(glm), glm_ch, glm_tau, int(split))
+                tor_loop_cut, int(glm), glm_ch, glm_tau, int(split), {"exact": 0, "damped": 1}[c2p])
 
 
 def _ptr(t):

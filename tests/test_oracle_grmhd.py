@@ -222,3 +222,72 @@ def test_con2prim_failure_policy():
     rho, p, v, fail = grmhd.con2prim(D, S, tau, s['B'], gam, grmhd.inv3(gam), s['G'], 1e-15, 1e-17)
     assert fail[3] and fail[5] and fail.sum() == 2
     assert rho[3] == 1e-15 and p[3] == 1e-17 and np.all(v[:, 3] == 0)
+
+
+def _damped_from(s, rho0, p0, v0, maxit=40):
+    gam = s['gam']
+    gamu = grmhd.inv3(gam)
+    D, S, tau = grmhd.prim_to_cons(s['rho'], s['p'], s['v'], s['B'], gam, s['G'])
+    return grmhd.con2prim_damped(D, S, tau, s['B'], gam, gamu, s['G'], 1e-30, 1e-40, rho0, p0, v0,
+                                 maxit=maxit)
+
+
+def _warm_state(seed, n):
+    rng = np.random.default_rng(seed)
+    s = random_state(rng, n, W_max=2.0, sig_max=1.0)
+    eps = 10 ** rng.uniform(-2, 1, n)
+    s['p'] = (s['G'] - 1) * s['rho'] * eps
+    return s, eps, rng
+
+
+def test_damped_con2prim_fixed_point_is_the_known_primitives():
+    """The paper's damped iteration (reading: predicted values are the
+    conserved variables of the current primitives) converges to the known
+    primitives of random warm states (eps >= 10^-2, W <= 2, b^2/rho <= 1) from
+    a guess 10^-3 away, given enough tries (1000; with the paper's 30-40 most
+    points are not there yet: lambda only ever halves, and the scalar Jacobian
+    rho h W^2 underestimates dS/dv by up to 1 + 2 W^2 v^2).  A wrong sign or
+    index in the update, or a fixed point other than the inverse, fails
+    this."""
+    s, eps, rng = _warm_state(11, 400)
+    d = 1e-3 * rng.uniform(-1, 1, (5, 400))
+    rho0, p0, v0 = s['rho'] * (1 + d[0]), s['p'] * (1 + d[1]), s['v'] * (1 + d[2:5])
+    rho, p, v, fail, its = _damped_from(s, rho0, p0, v0, maxit=1000)
+    assert not fail.any()
+    err = np.abs(rho / s['rho'] - 1)
+    assert np.mean(err < 1e-10) > 0.99
+    good = err < 1e-10
+    # p through the cancellation in tau: relative conditioning ~ 1e-16 / eps
+    assert np.all(np.abs(p / s["p"] - 1)[good] < 1e-9 * (1 + 1 / eps[good]))
+    assert np.all(np.abs(v - s['v']).max(axis=0)[good] < 1e-9)
+
+
+def test_damped_con2prim_exact_guess_and_unusable_guess():
+    """From the exact primitives the result stays there (to the conditioning
+    of tau); a state at rest without field from the fallback start (rho0 = 0)
+    gets the exact answer (v = 0, eps = tau/D)."""
+    s, eps, rng = _warm_state(12, 50)
+    rho, p, v, fail, its = _damped_from(s, s['rho'], s['p'], s['v'])
+    assert not fail.any()
+    assert np.all(np.abs(rho / s['rho'] - 1) < 1e-12) and np.all(np.abs(p / s["p"] - 1) < 1e-12 * (1 + 1 / eps))
+    s = random_state(rng, 50, zero_B=True, zero_v=True)
+    epsr = s['p'] / ((s['G'] - 1) * s['rho'])
+    rho, p, v, fail, its = _damped_from(s, np.zeros(50), np.zeros(50), np.zeros((3, 50)))
+    assert not fail.any()
+    assert np.all(np.abs(rho / s['rho'] - 1) < 1e-14) and np.all(np.abs(p / s['p'] - 1) < 1e-14 / epsr)
+    assert np.abs(v).max() == 0.0
+
+
+def test_damped_con2prim_halving_keeps_the_state_physical():
+    """A poor guess (velocity scaled by 0.1 at W up to 10, strong fields, cold
+    and hot gas): the halving keeps every iterate at v^2 < 1; no NaN comes
+    out, and what the tries leave unusable is flagged (atmosphere), not
+    returned."""
+    rng = np.random.default_rng(13)
+    s = random_state(rng, 300, W_max=10.0, sig_max=100.0)
+    rho, p, v, fail, its = _damped_from(s, s['rho'], s['p'], 0.1 * s['v'])
+    assert np.isfinite(rho).all() and np.isfinite(p).all() and np.isfinite(v).all()
+    v2 = np.einsum('i...,i...->...', grmhd.lower(s['gam'], v), v)
+    assert np.all(v2 < 1.0)
+    assert np.all(rho[fail] == 1e-30) and np.all(p[fail] == 1e-40)
+    assert np.all(p[~fail] > 0)

@@ -62,7 +62,7 @@ def oracle_kwargs(w):
     for k in ("id_kind", "tor_r_in", "tor_r_max", "tor_rho_max", "tor_atm", "tor_loop_cut"):
         if k in p:
             init[k] = p[k]
-    for k in ("glm", "glm_ch", "glm_tau", "split"):
+    for k in ("glm", "glm_ch", "glm_tau", "split", "c2p"):
         if k in p:
             prob[k] = p[k]
     return grid_args, prob, init
