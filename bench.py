@@ -263,6 +263,38 @@ def fixed_background(w, K, value_fp64, torch, Solver, make_grid, make_phys):
     return out
 
 
+def paper_variants(w, K, torch, Solver, make_grid, make_phys):
+    """How far the paper's literal scheme is from the unsplit hot path on the
+    main workload: the operator-split coupled step, 2/3 dealiasing and the
+    damped primitive recovery, each alone, over the same K steps from the
+    library's initial data; step time and the largest per-group relative
+    difference from the unsplit FP64 path (groups as in the parity tests)."""
+    import numpy as np
+    g = w["grid"]
+    variants = (("unsplit", {}, {}), ("operator_split", {}, {"split": True}), ("dealias_2_3", {"dealias": True}, {}),
+                ("damped_c2p", {}, {"c2p": "damped"}))
+    states, out = {}, {"workload": "x".join(str(g[k]) for k in ("nr", "nth", "nph")), "steps": K}
+    for name, gk, pk in variants:
+        s = Solver(make_grid(**dict(g, **gk)), make_phys(**dict(w["phys"], **pk)))
+        s.init_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        states[name] = s.get_state()
+        d = s.diagnostics()
+        s.close()
+        out[name] = {"ms_per_step": wall * 1e3 / K, "nonfinite": d["nonfinite"], "c2p_fail": d["c2p_fail"],
+                     "ham_l2": d["ham_l2"]}
+    ref = states["unsplit"]
+    for name, _, _ in variants[1:]:
+        diff = [float(np.abs(states[name][q] - ref[q]).max() / np.abs(ref[q]).max()) for q in GROUPS]
+        out[name]["max_group_rel_diff_vs_unsplit"] = max(diff)
+        out[name]["group_rel_diff_vs_unsplit"] = [float(f"{x:.3g}") for x in diff]
+    return out
+
+
 def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
     """A second measured configuration (the magnetised torus at 128x96x192):
     FP64 and FP32-form throughput over the workload's step count from the
@@ -366,6 +398,8 @@ def main():
     ap.add_argument("--no-second", action="store_true", help="skip the 128x96x192 torus configuration")
     ap.add_argument("--no-glm", action="store_true", help="skip the GLM constraint-damping measurements")
     ap.add_argument("--no-fixed", action="store_true", help="skip the fixed-background (Cowling) form")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the paper-literal variants (split step, 2/3 dealiasing, damped recovery)")
     ap.add_argument("--serve-t-scale", type=float, default=1e-3)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 512 MiB copy + one RK4 step, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -464,6 +498,9 @@ def main():
     if not args.no_fixed:
         out["fixed_background"] = fixed_background(w, K, out["value"], torch, Solver, make_grid, make_phys)
         progress("fixed-background form done")
+    if not args.no_variants:
+        out["paper_variants"] = paper_variants(w, K, torch, Solver, make_grid, make_phys)
+        progress("paper-literal variants done")
     if not args.no_serving:
         from paper_2508_18221_amd.serve import run_stream
         jobs = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale)
