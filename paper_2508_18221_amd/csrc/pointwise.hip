@@ -389,6 +389,14 @@ __device__ __forceinline__ void ricci(const Sym& gt, const Sym& gtu, const doubl
 // derivative array offsets relative to the first-derivative block
 constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1, O_GLM = SC_GLM - SC_D1;
 
+// Loads of arrays that a launch reads once: non-temporal, so the streams pass
+// the caches without evicting each other (the RHS and Ricci kernels read
+// 80-200 such arrays per point).
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -415,8 +423,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DAMPED ? 2 
     if (flux != nullptr) flux = shift_ptr(flux, jd);
   }
   const int j = (int)(idx % pp.nr);
-#define LD(f) U[(size_t)(f) * P + idx]
-#define LG(f) Ug[(size_t)(f) * P + idx]
+#define LD(f) ldnt(&U[(size_t)(f) * P + idx])
+#define LG(f) ldnt(&Ug[(size_t)(f) * P + idx])
   const double phi = LG(0);
   Sym gt;
 #pragma unroll
@@ -439,14 +447,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DAMPED ? 2 
   const double rho_fl = floors[j], p_fl = floors[pp.nr + j];
   C2POut c;
   if (DAMPED) {  // the paper's iteration from the last recovered primitives
-    const double vg[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
-    c = con2prim_damped(D, S, tau, B, gam, gamu, pp.gamma_ad, rho_fl, p_fl, prim[idx], prim[(size_t)P + idx], vg);
+    const double vg[3] = {ldnt(&prim[2 * (size_t)P + idx]), ldnt(&prim[3 * (size_t)P + idx]),
+                          ldnt(&prim[4 * (size_t)P + idx])};
+    c = con2prim_damped(D, S, tau, B, gam, gamu, pp.gamma_ad, rho_fl, p_fl, ldnt(&prim[idx]),
+                        ldnt(&prim[(size_t)P + idx]), vg);
   } else {
   // warm start Z = rho h W^2 from the last recovered primitives
   double zg = -1.0;
   {
-    const double rg = prim[idx], pg = prim[(size_t)P + idx];
-    double vg[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    const double rg = ldnt(&prim[idx]), pg = ldnt(&prim[(size_t)P + idx]);
+    double vg[3] = {ldnt(&prim[2 * (size_t)P + idx]), ldnt(&prim[3 * (size_t)P + idx]),
+                    ldnt(&prim[4 * (size_t)P + idx])};
     double vgl[3];
     mv(gam, vg, vgl);
     const double v2 = dot3(vg, vgl);
@@ -519,7 +530,7 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
                                                double alpha, const double* dal, const double (*dbeta)[3],
                                                const double (*dgt)[6], const double* dphi, Emit& emit) {
 #define LU(f) Us[(size_t)(f) * P + idx]
-#define LS(g) ((double)der[(size_t)(g) * P + idx])
+#define LS(g) ((double)ldnt(&der[(size_t)(g) * P + idx]))
   Matter mt;
   const double isg = 1.0 / sqrtg;
   mt.Em = (LU(28) + LU(24)) * isg;
@@ -536,8 +547,9 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
   }
   Sym& Sij = mt.Sij;
   {
-    const double rho = prim[idx], p = prim[(size_t)P + idx];
-    const double v[3] = {prim[2 * (size_t)P + idx], prim[3 * (size_t)P + idx], prim[4 * (size_t)P + idx]};
+    const double rho = ldnt(&prim[idx]), p = ldnt(&prim[(size_t)P + idx]);
+    const double v[3] = {ldnt(&prim[2 * (size_t)P + idx]), ldnt(&prim[3 * (size_t)P + idx]),
+                         ldnt(&prim[4 * (size_t)P + idx])};
     const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
     const Mag m = magnetic(v, B, gam);
     const double h = 1.0 + p / rho * pp.gfac;
@@ -642,7 +654,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int k = (int)((idx / pp.nr) % pp.nth);
   const bool frozen = (j == 0 || k == 0 || k == pp.nth - 1);
 #define LU(f) Us[(size_t)(f) * P + idx]
-#define LS(g) ((double)der[(size_t)(g) * P + idx])
+#define LS(g) ((double)ldnt(&der[(size_t)(g) * P + idx]))
 #define D1(a, f) LS(21 * (a) + (f))
   auto DD = [&](int a, int b, int s) -> double {
     if (a == b) return LS(O_D2 + 11 * a + s);
@@ -662,19 +674,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     if (mode == 0) {
       out[e] = kf;
     } else if (mode == 5) {
-      if (f < 24) out[e] = Un[e] + dt * kf;
+      if (f < 24) out[e] = ldnt(&Un[e]) + dt * kf;
     } else if (mode == 1) {
-      const double un = Un[e];
+      const double un = ldnt(&Un[e]);
       acc[e] = un + (dt / 6.0) * kf;
       out[e] = un + 0.5 * dt * kf;
     } else if (mode == 2) {
-      acc[e] += (dt / 3.0) * kf;
-      out[e] = Un[e] + 0.5 * dt * kf;
+      acc[e] = ldnt(&acc[e]) + (dt / 3.0) * kf;
+      out[e] = ldnt(&Un[e]) + 0.5 * dt * kf;
     } else if (mode == 3) {
-      acc[e] += (dt / 3.0) * kf;
-      out[e] = Un[e] + dt * kf;
+      acc[e] = ldnt(&acc[e]) + (dt / 3.0) * kf;
+      out[e] = ldnt(&Un[e]) + dt * kf;
     } else {
-      out[e] = acc[e] + (dt / 6.0) * kf;
+      out[e] = ldnt(&acc[e]) + (dt / 6.0) * kf;
     }
   };
 
@@ -746,7 +758,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // ---- phase 4: Ricci tensor (computed by k_ricci) ------------------------------
   Sym R;
 #pragma unroll
-  for (int s = 0; s < 6; ++s) R.m[s] = Ric[(size_t)s * P + idx];
+  for (int s = 0; s < 6; ++s) R.m[s] = ldnt(&Ric[(size_t)s * P + idx]);
   double dGt[3][3];  // [a][i] = d_a Gt^i
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -887,23 +899,23 @@ __global__ __launch_bounds__(256) void k_rhs_fixed(int mode, const double* Us, c
     if (mode == 0) {
       out[e] = kf;
     } else if (mode == 1) {
-      const double un = Un[e];
+      const double un = ldnt(&Un[e]);
       acc[e] = un + (dt / 6.0) * kf;
       out[e] = un + 0.5 * dt * kf;
     } else if (mode == 2) {
-      acc[e] += (dt / 3.0) * kf;
-      out[e] = Un[e] + 0.5 * dt * kf;
+      acc[e] = ldnt(&acc[e]) + (dt / 3.0) * kf;
+      out[e] = ldnt(&Un[e]) + 0.5 * dt * kf;
     } else if (mode == 3) {
-      acc[e] += (dt / 3.0) * kf;
-      out[e] = Un[e] + dt * kf;
+      acc[e] = ldnt(&acc[e]) + (dt / 3.0) * kf;
+      out[e] = ldnt(&Un[e]) + dt * kf;
     } else {
-      out[e] = acc[e] + (dt / 6.0) * kf;
+      out[e] = ldnt(&acc[e]) + (dt / 6.0) * kf;
     }
   };
   if (mode == 0)
     for (int f = 0; f < 24; ++f) out[(size_t)f * P + idx] = 0.0;
-#define LG(f) Ug[(size_t)(f) * P + idx]
-#define BG(a, s) bg[(size_t)(11 * (a) + (s)) * P + idx]
+#define LG(f) ldnt(&Ug[(size_t)(f) * P + idx])
+#define BG(a, s) ldnt(&bg[(size_t)(11 * (a) + (s)) * P + idx])
   const double phi = LG(0);
   Sym gt, At;
 #pragma unroll
@@ -950,7 +962,7 @@ __global__ __launch_bounds__(256) void k_ricci(const double* __restrict__ Us, co
     der = shift_ptr(der, jd);
     Rout = shift_ptr(Rout, jd);
   }
-#define LS(g) ((double)der[(size_t)(g) * P + idx])
+#define LS(g) ((double)ldnt(&der[(size_t)(g) * P + idx]))
   auto DD = [&](int a, int b, int s) -> double {
     if (a == b) return LS(O_D2 + 11 * a + s);
     const int lo = a < b ? a : b, hi = a < b ? b : a;
