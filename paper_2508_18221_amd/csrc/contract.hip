@@ -471,7 +471,8 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 // Folded contraction on a strided axis (theta, phi), software-pipelined.  A
 // workgroup walks PIPE_TPB consecutive column tiles of one task (tiles run
 // over slab x column block).  The next tile's raw rows are copied from HBM
-// straight into LDS (global_load_lds: 16 bytes per lane, no registers) while
+// straight into LDS (global_load_lds: 16 bytes per lane, no registers; cache
+// policy nt, since every input row is read by one workgroup once) while
 // the MFMAs run on the current tile from the other LDS buffer, and each
 // wave's operator fragments (its 16 output rows, all k) stay in registers
 // for every tile of the workgroup.
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
     char* base = lds + b * bufbytes;
     for (int q = wave; q < Q; q += NW)
       __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + cm * Q) * inner),
-                                       (lds_void_t*)(base + q * PIPE_CH), 16, 0, 0);
+                                       (lds_void_t*)(base + q * PIPE_CH), 16, 0, 2);
   };
 
   auto run = [&](auto nm) {
@@ -657,7 +658,7 @@ __global__ __launch_bounds__(256) void k_contract_pipe_r(TaskList tl, Bases B, c
 #pragma unroll
     for (int q = wave; q < Q; q += 4)
       __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + 16 * cm) * N2),
-                                       (lds_void_t*)(base + q * PIPE_CH_R), 16, 0, 0);
+                                       (lds_void_t*)(base + q * PIPE_CH_R), 16, 0, 2);
   };
 
   auto run = [&](auto nm) {

@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void k_contract_f32_pipe(MixedTaskList tl, Bas
 #pragma unroll
       for (int q = wave; q < Q; q += 4)
         __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + Q * cm) * (INNER ? N2 : inner)),
-                                         (lds_void_t*)(base + q * CH), 16, 0, 0);
+                                         (lds_void_t*)(base + q * CH), 16, 0, 2);
     };
     // operator fragments: lane (lr, lk) holds E^T / O^T [4 ks + lk][16 wa + lr]
     const size_t hh = (size_t)HP * HP;
