@@ -89,3 +89,62 @@ def test_damped_recovery_ten_steps_match_oracle(name):
     log("  e_f = " + " ".join(f"{x:.1e}" for x in e))
     assert np.isfinite(got).all() and d["nonfinite"] == 0
     assert e.max() < 1e-11
+
+
+def test_dealias_on_the_fixed_background_matches_oracle():
+    """2/3 truncation on the fixed background: the GRMHD fields are truncated
+    and filtered, the background is left bit for bit."""
+    log("[dealias + fixed background] 16^3, 10 RK4 steps")
+    w = workload("ks_michel_16x16x16", dealias=True)
+    w["phys"]["cowling"] = True
+    U, got, ref, d = run_both(w, 10)
+    assert np.array_equal(got[:24], U[:24])
+    e = field_errors(got, ref)
+    log("  e_f = " + " ".join(f"{x:.1e}" for x in e[24:]))
+    assert e.max() < 1e-11
+
+
+def test_split_step_with_glm_matches_oracle():
+    """The split step with GLM damping: psi evolves in the fluid half-steps,
+    the Euler spacetime step leaves it alone."""
+    log("[split + GLM] 16^3, 10 split steps")
+    w = workload("ks_michel_16x16x16")
+    w["phys"].update(split=True, glm=True, glm_ch=0.8, glm_tau=1.5)
+    g, pb, U, K0 = oracle_problem(w)
+    U = U.copy()
+    bump = np.exp(-np.log(g.R / 5.0) ** 2) * np.ones(g.shape)
+    U[29] = U[29] * (1.0 + 0.05 * bump * np.sin(g.TH) * np.sin(g.PH))
+    U[32] = 1e-4 * bump * np.cos(g.TH) * np.sin(g.PH)
+    ref = pb.evolve(U, K0, pb.dt(), 10)
+    s = solver(w)
+    s.set_state(U, K0)
+    s.step(10)
+    got = s.get_state()
+    s.close()
+    e = field_errors(got, ref)
+    log("  e_f = " + " ".join(f"{x:.1e}" for x in e))
+    assert got.shape[0] == 33 and e.max() < 1e-11
+
+
+def test_split_batch_bitwise_equals_alone():
+    from paper_2508_18221_amd import Solver, make_grid, make_phys, step_batch
+    log("[split batch] 2 jobs 16^3, 3 split steps, batched vs alone")
+    rh = lambda a: 1.0 + np.sqrt(1.0 - a * a)  # noqa: E731
+
+    def make(a, sd):
+        s = Solver(make_grid(16, 16, 16, r_in=1.8 * rh(a) / rh(0.5)), make_phys(a=a, seed=sd, split=True))
+        s.init_state()
+        return s
+
+    specs = [(0.3, 5), (0.8, 6)]
+    batch = [make(a, sd) for a, sd in specs]
+    step_batch(batch, 3)
+    got = [s.get_state() for s in batch]
+    for s in batch:
+        s.close()
+    for (a, sd), U in zip(specs, got):
+        s = make(a, sd)
+        s.step(3)
+        ref = s.get_state()
+        s.close()
+        assert np.array_equal(U, ref)
