@@ -306,7 +306,8 @@ int grmhd_server_submit(grmhd_server* srv, const grmhd_grid* grid, const grmhd_p
 int grmhd_server_tick(grmhd_server* srv, int32_t* n_pending);
 
 int grmhd_server_poll(grmhd_server* srv, int64_t job_id, grmhd_job_info* out);
-/* Final state of a finished job submitted with keep_state (n = 32 P). */
+/* Final state of a finished job submitted with keep_state (n = 32 P; 33 P,
+ * psi last, for a GLM job). */
 int grmhd_server_result(grmhd_server* srv, int64_t job_id, double* host_U, size_t n);
 int grmhd_server_stats(grmhd_server* srv, grmhd_server_summary* out);
 double grmhd_server_clock(const grmhd_server* srv);

@@ -101,9 +101,12 @@ struct Arena {
 
 bool same_class(const Job& a, const Job& b) {
   return a.grid.nr == b.grid.nr && a.grid.nth == b.grid.nth && a.grid.nph == b.grid.nph &&
-         a.grid.filter_on == b.grid.filter_on && a.grid.dealias == b.grid.dealias && a.prec == b.prec && a.phys.gamma_ad == b.phys.gamma_ad &&
+         a.grid.filter_on == b.grid.filter_on && a.grid.dealias == b.grid.dealias && a.prec == b.prec &&
+         a.phys.gamma_ad == b.phys.gamma_ad &&
          a.phys.eta == b.phys.eta && a.phys.cowling == b.phys.cowling && a.phys.gauge_k0 == b.phys.gauge_k0 &&
          a.phys.split == b.phys.split && a.phys.c2p_damped == b.phys.c2p_damped &&
+         a.phys.glm == b.phys.glm && (!a.phys.glm || (a.phys.glm_ch == b.phys.glm_ch &&
+                                                      a.phys.glm_tau == b.phys.glm_tau)) &&
          a.phys.rho_floor == b.phys.rho_floor && a.phys.p_floor == b.phys.p_floor;
 }
 
@@ -264,7 +267,7 @@ int grmhd_server_tick(grmhd_server* s, int32_t* n_pending) {
     if (!s->dry) {
       if (j.keep) {
         const size_t P = (size_t)j.grid.nr * j.grid.nth * j.grid.nph;
-        j.result.resize((size_t)GRMHD_NFIELDS * P);
+        j.result.resize((size_t)(j.phys.glm ? GRMHD_NFIELDS_GLM : GRMHD_NFIELDS) * P);  // psi last with GLM
         int rc = grmhd_get_state(j.ctx, j.result.data(), j.result.size(), nullptr);
         if (rc) return sfail(rc, grmhd_last_error());
       }
@@ -308,7 +311,7 @@ int grmhd_server_result(grmhd_server* s, int64_t id, double* host_U, size_t n) {
   if (!s || !host_U || id < 0 || id >= (int64_t)s->jobs.size()) return sfail(GRMHD_E_ARG, "unknown job");
   const Job& j = s->jobs[id];
   if (j.state != 2 || j.result.empty()) return sfail(GRMHD_E_STATE, "job not finished or state not kept");
-  if (n != j.result.size()) return sfail(GRMHD_E_SIZE, "state size must be 32 * P");
+  if (n != j.result.size()) return sfail(GRMHD_E_SIZE, "state size must be 32 * P (33 * P for a GLM job)");
   std::copy(j.result.begin(), j.result.end(), host_U);
   return GRMHD_OK;
 }

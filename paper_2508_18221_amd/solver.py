@@ -195,8 +195,9 @@ class Server:
         check_server(self.lib.grmhd_server_poll(self.srv, int(job_id), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in JobInfo._fields_}
 
-    def result(self, job_id, shape):
-        U = np.empty((NFIELDS,) + tuple(shape))
+    def result(self, job_id, shape, nfields=NFIELDS):
+        """Kept final state of a finished job (nfields 33 for a GLM job)."""
+        U = np.empty((nfields,) + tuple(shape))
         check_server(self.lib.grmhd_server_result(self.srv, int(job_id),
                                                   U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), U.size))
         return U

@@ -7,7 +7,16 @@ repository root (tens of minutes of CPU at full size):
 
     python tests/golden/make_oracle_samples.py ks_michel_64x64x128 10
     python tests/golden/make_oracle_samples.py ks_torus_128x96x192 10
+
+An optional third argument runs a paper-literal variant of the workload and
+names the file <workload>_<variant>_<steps>steps.json: split (the
+operator-split coupled step), dealias (2/3 truncation after every step) or
+damped (the damped primitive recovery):
+
+    python tests/golden/make_oracle_samples.py ks_michel_64x64x128 4 split
 """
+
+VARIANTS = {"split": ({}, {"split": True}), "dealias": ({"dealias": True}, {}), "damped": ({}, {"c2p": "damped"})}
 
 import json
 import os
@@ -37,9 +46,13 @@ def sample_points(nph, nth, nr, seed=7, n_random=256):
     return sorted(pts)
 
 
-def main(name, steps):
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_{steps}steps.json")
+def main(name, steps, variant=None):
+    tag = f"{name}_{variant}" if variant else name
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{tag}_{steps}steps.json")
     w = workloads.WORKLOADS[name]
+    if variant:
+        gk, pk_extra = VARIANTS[variant]
+        w = dict(grid=dict(w["grid"], **gk), phys=dict(w["phys"], **pk_extra), steps=w["steps"])
     ga, pk, ik = workloads.oracle_kwargs(w)
     g = spectral.Grid(*ga)
     pb = evolve.Problem(g, **pk)
@@ -53,7 +66,7 @@ def main(name, steps):
     idx = tuple(np.array(pts).T)
     vals = U[(slice(None),) + idx].T  # (npoints, 32)
     with open(out, "w") as f:
-        json.dump({"workload": name, "steps": steps, "dt": dt, "shape": list(U.shape),
+        json.dump({"workload": name, "variant": variant, "steps": steps, "dt": dt, "shape": list(U.shape),
                    "points": pts, "values": [[float.hex(float(v)) for v in row] for row in vals],
                    "field_norms_full": [float(np.sqrt(np.sum(U[q] ** 2))) for q in range(U.shape[0])]},
                   f, separators=(",", ":"))
@@ -61,4 +74,4 @@ def main(name, steps):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]))
+    main(sys.argv[1], int(sys.argv[2]), sys.argv[3] if len(sys.argv) > 3 else None)

@@ -125,3 +125,29 @@ def test_glm_damps_a_seeded_divergence():
     assert norms[True][1] < 0.95 * norms[True][0]
     assert norms[False][1] > norms[False][0]
     assert norms[True][1] < norms[False][1]
+
+
+def test_served_glm_job_beside_a_plain_job_equals_alone():
+    """A GLM job and a plain job of the same grid are different job classes
+    (their kernels differ); served together, the GLM job's final state (psi
+    included) equals the same job stepped alone."""
+    from paper_2508_18221_amd import Server, Solver, make_grid, make_phys
+    log("[server] GLM job beside a plain job on 16^3")
+    srv = Server(budget=4 << 30, max_batch=32)
+    g = make_grid(16, 16, 16)
+    p_glm = make_phys(a=0.5, seed=41, **GLM)
+    ids = [srv.submit(g, make_phys(a=0.5, seed=40), 0.05), srv.submit(g, p_glm, 0.06, keep_state=True)]
+    while srv.tick() > 0:
+        pass
+    assert srv.stats()["completed"] == 2
+    info = srv.poll(ids[1])
+    served = srv.result(ids[1], (16, 16, 16), nfields=33)
+    srv.close()
+    s = Solver(g, p_glm)
+    s.init_state()
+    s.set_dt(info["dt"])
+    s.step(info["steps_total"])
+    alone = s.get_state()
+    s.close()
+    assert alone.shape[0] == 33
+    assert np.array_equal(served, alone)
