@@ -14,6 +14,15 @@
 //                    (join)   k_rhs_rk: BSSN + Valencia RHS, boundary freeze,
 //                             RK4 update
 // After the fourth stage the filter runs as three contraction passes.
+//
+// Fixed background (cowling): the first derivatives of the background metric
+// are computed once per state (SC_BG); a stage is k_c2p_flux (metric read from
+// the resident state), the three flux-derivative passes and k_rhs_fixed, all
+// on the context stream; only fields 24.. are stepped and filtered.
+// Operator-split step (split): fixed-background stages over dt/2 (background
+// derivatives of the current metric), one coupled stage in RHS mode 5
+// (forward Euler of the 24 spacetime fields), fixed-background stages over
+// dt/2 again, then the filter.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>

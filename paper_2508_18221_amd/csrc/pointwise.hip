@@ -1,10 +1,15 @@
 // Pointwise kernels of the RHS evaluation (one thread per grid point,
 // structure-of-arrays FP64 streaming from HBM):
-//   k_c2p_flux : metric reconstruction, primitive recovery, densitised fluxes
-//   k_rhs_rk   : BSSN + gauge RHS with matter sources, Valencia RHS
-//                (-div + sqrt(gamma) S), boundary freeze, RK4 stage update
-//   k_k0       : static 1+log source K0 = K - beta^k d_k alpha/(2 alpha)
-//   k_diag     : per-block partial sums / extrema for diagnostics
+//   k_c2p_flux  : metric reconstruction, primitive recovery (safeguarded
+//                 Newton, or the paper's damped iteration), densitised fluxes
+//   k_ricci     : Ricci tensor of the stage state
+//   k_rhs_rk    : BSSN + gauge RHS with matter sources, Valencia RHS
+//                 (-div + sqrt(gamma) S, GLM terms), boundary freeze, RK4 stage
+//                 update (or the split step's Euler update of the spacetime)
+//   k_rhs_fixed : the Valencia RHS and RK4 stage on a fixed background
+//   k_ham, k_k0 : Hamiltonian constraint; static 1+log source
+//                 K0 = K - beta^k d_k alpha/(2 alpha)
+//   k_diag      : per-block partial sums / extrema for diagnostics
 //
 // Paper: Results, "GRMHD Conservative Form" (conserved variables, fluxes,
 // Lorentz factor, magnetic four-vector, source term); Methods, "The Primitive
