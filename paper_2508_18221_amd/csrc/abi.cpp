@@ -568,6 +568,13 @@ int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec, size_t* resident,
 
 int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
                  void* dev_scratch, void* hip_stream, grmhd_ctx** out) {
+  return create_context(grid, phys, prec, dev_resident, dev_scratch, hip_stream, nullptr, out);
+}
+
+}  // extern "C"
+
+int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
+                          void* dev_scratch, void* hip_stream, const Operators* prebuilt, grmhd_ctx** out) {
   int rc = validate_grid(grid);
   if (rc) return rc;
   if (!phys || !out || !dev_resident || !dev_scratch) return fail(GRMHD_E_ARG, "null argument");
@@ -612,7 +619,10 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
       return fail(GRMHD_E_DEVICE, std::string("stream/event create: ") + hipGetErrorString(e));
     }
   }
-  build_operators(*grid, phys->cfl, &c->ops);
+  if (prebuilt)
+    c->ops = *prebuilt;
+  else
+    build_operators(*grid, phys->cfl, &c->ops);
   // atmosphere floors rho_floor r^-3/2 and p_floor r^-5/2 at the radial nodes
   c->floor_host.resize(2 * (size_t)grid->nr);
   for (int j = 0; j < grid->nr; ++j) {
@@ -720,6 +730,8 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
   *out = c;
   return GRMHD_OK;
 }
+
+extern "C" {
 
 int grmhd_destroy(grmhd_ctx* c) {
   if (!c) return GRMHD_OK;

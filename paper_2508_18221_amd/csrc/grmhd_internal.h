@@ -156,6 +156,12 @@ struct Operators {
 
 void build_operators(const grmhd_grid& g, double cfl, Operators* ops);
 
+// grmhd_create with the operators of this grid and cfl built beforehand
+// (prebuilt: copied into the context; null: built here).  The job server keeps
+// one set per grid, so admission does not rebuild them.
+int create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
+                   void* dev_scratch, void* hip_stream, const Operators* prebuilt, grmhd_ctx** out);
+
 // Host initial data: 32 fields + K0 (P doubles each) in state layout.
 int host_initial_data(const grmhd_grid& g, const grmhd_phys& ph, const Operators& ops,
                       std::vector<double>* U, std::vector<double>* K0, std::string* err);

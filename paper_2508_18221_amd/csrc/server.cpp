@@ -24,10 +24,12 @@
 #include <chrono>
 #include <deque>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "grmhd.h"
+#include "grmhd_internal.h"
 
 namespace {
 
@@ -123,6 +125,14 @@ struct grmhd_server {
   std::vector<Job> classes;  // one representative per grid class
   std::vector<hipStream_t> streams;
   std::vector<bool> own_stream;
+  // operators per (grid, cfl), built at the first submission of that grid and
+  // shared by the time step and every context created for it
+  struct OpsEntry {
+    grmhd_grid grid;
+    double cfl;
+    std::unique_ptr<grmhd::Operators> ops;
+  };
+  std::vector<OpsEntry> ops_cache;
   std::chrono::steady_clock::time_point t0;
   double busy = 0.0;
   double first_submit = -1.0;
@@ -130,6 +140,8 @@ struct grmhd_server {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 };
+
+static const grmhd::Operators* operators_for(grmhd_server* s, const grmhd_grid& g, double cfl);
 
 extern "C" {
 
@@ -170,8 +182,8 @@ int grmhd_server_submit(grmhd_server* s, const grmhd_grid* grid, const grmhd_phy
   size_t res = 0, scr = 0;
   int rc = grmhd_query_bytes(grid, prec, &res, &scr);
   if (rc) return sfail(rc, std::string("job rejected: ") + grmhd_last_error());
-  double dt = 0.0;
-  if ((rc = grmhd_time_step(grid, phys->cfl, &dt))) return sfail(rc, grmhd_last_error());
+  if (!(phys->cfl > 0.0)) return sfail(GRMHD_E_ARG, "job rejected: cfl > 0");
+  const double dt = operators_for(s, *grid, phys->cfl)->dt;  // grid validated by the size query
   Job j;
   j.id = (int64_t)s->jobs.size();
   j.grid = *grid;
@@ -195,6 +207,25 @@ int grmhd_server_submit(grmhd_server* s, const grmhd_grid* grid, const grmhd_phy
   s->jobs.push_back(j);
   s->queue.push_back(s->jobs.size() - 1);
   return GRMHD_OK;
+}
+
+static bool same_grid(const grmhd_grid& a, const grmhd_grid& b) {
+  return a.nr == b.nr && a.nth == b.nth && a.nph == b.nph && a.r_in == b.r_in && a.r_out == b.r_out &&
+         a.th_min == b.th_min && a.th_max == b.th_max && a.filt_alpha == b.filt_alpha &&
+         a.filt_order == b.filt_order && a.filter_on == b.filter_on && a.dealias == b.dealias;
+}
+
+// The operators of a (validated) grid and cfl, built once per server.
+static const grmhd::Operators* operators_for(grmhd_server* s, const grmhd_grid& g, double cfl) {
+  for (auto& e : s->ops_cache)
+    if (e.cfl == cfl && same_grid(e.grid, g)) return e.ops.get();
+  grmhd_server::OpsEntry e;
+  e.grid = g;
+  e.cfl = cfl;
+  e.ops.reset(new grmhd::Operators());
+  grmhd::build_operators(g, cfl, e.ops.get());
+  s->ops_cache.push_back(std::move(e));
+  return s->ops_cache.back().ops.get();
 }
 
 static int class_of(grmhd_server* s, const Job& j) {
@@ -223,7 +254,8 @@ int grmhd_server_tick(grmhd_server* s, int32_t* n_pending) {
     if (!s->dry) {
       char* res = s->arena_base + off;
       char* scr = res + j.res_bytes;
-      int rc = grmhd_create(&j.grid, &j.phys, j.prec, res, scr, s->streams[j.cls], &j.ctx);
+      int rc = grmhd::create_context(&j.grid, &j.phys, j.prec, res, scr, s->streams[j.cls],
+                                     operators_for(s, j.grid, j.phys.cfl), &j.ctx);
       if (!rc) rc = grmhd_init_state(j.ctx);
       if (!rc) rc = grmhd_set_dt(j.ctx, j.dt);
       if (rc) {
