@@ -744,13 +744,19 @@ int grmhd_destroy(grmhd_ctx* c) {
 
 int grmhd_init_state(grmhd_ctx* c) {
   if (!c) return fail(GRMHD_E_ARG, "null context");
-  std::vector<double> U, K0;
+  // the data are axisymmetric up to the perturbation: the host builds the
+  // (theta, r) plane, the device expands it (staged in the scratch buffer from
+  // SC_D1 on, which holds the plane as n_phi >= 4)
+  static_assert(PL_NFIELDS <= 4 * (SC_NFIELDS - SC_D1), "plane staging must fit the scratch buffer");
+  std::vector<double> plane;
   std::string err;
-  int rc = host_initial_data(c->grid, c->phys, c->ops, &U, &K0, &err);
+  int rc = host_initial_plane(c->grid, c->phys, c->ops, &plane, &err);
   if (rc) return fail(rc, err);
-  HIPCHK(hipMemcpyAsync(c->U, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  double* dplane = sf(c, SC_D1);
+  HIPCHK(hipMemcpyAsync(dplane, plane.data(), plane.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_init_expand(dplane, c->phys.id_kind == GRMHD_ID_TORUS, c->phys.seed, c->phys.pert_amp,
+                            c->phys.gamma_ad, c->pp, c->U, c->K0, c->stream));
   HIPCHK(hipMemsetAsync(c->U + (size_t)NF * c->L.P, 0, c->L.P * sizeof(double), c->stream));  // psi = 0
-  HIPCHK(hipMemcpyAsync(c->K0, K0.data(), K0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   if ((rc = prime_guesses(c))) return rc;
   HIPCHK(hipStreamSynchronize(c->stream));
   c->t = 0.0;

@@ -162,9 +162,21 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops);
 int create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
                    void* dev_scratch, void* hip_stream, const Operators* prebuilt, grmhd_ctx** out);
 
-// Host initial data: 32 fields + K0 (P doubles each) in state layout.
-int host_initial_data(const grmhd_grid& g, const grmhd_phys& ph, const Operators& ops,
-                      std::vector<double>* U, std::vector<double>* K0, std::string* err);
+// Initial data on the (theta, r) plane (the data are axisymmetric up to the
+// seeded perturbation): PL_NFIELDS fields of nr * nth doubles, index k nr + j.
+enum : int {
+  PL_PHI = 0, PL_GT = 1, PL_AT = 7, PL_K = 13, PL_GAMT = 14, PL_ALPHA = 17, PL_BETAR = 18, PL_K0 = 19,
+  PL_RHO = 20, PL_P = 21, PL_V = 22, PL_SB = 25, PL_SQRTG = 28, PL_GM = 29,  // gm: physical metric, 9
+  PL_NFIELDS = 38
+};
+int host_initial_plane(const grmhd_grid& g, const grmhd_phys& ph, const Operators& ops,
+                       std::vector<double>* plane, std::string* err);
+// The 3D state (fields 0..31) and K0 from the plane fields (device copy):
+// spacetime copied along phi; rho (Michel) or p (torus) times
+// 1 + amp (2u - 1), u the top 53 bits of SplitMix64(seed ^ n) / 2^53 at point
+// n; then the densitised conserved variables.
+hipError_t launch_init_expand(const double* plane, int torus, uint64_t seed, double amp, double gamma_ad,
+                              const PointParams& pp, double* U, double* K0, hipStream_t s);
 
 // ---- kernel launchers (kernels.hip) --------------------------------------
 // Contraction along axis (0 r, 1 theta, 2 phi) with nmat = 1 or 2 matrices.

@@ -27,13 +27,6 @@ namespace grmhd {
 
 namespace {
 
-uint64_t splitmix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 struct Bondi {
   double M, G, rc, rhoc, n, Tc, Kp, uc, C1, C2;
   Bondi(double M_, double G_, double rc_, double rhoc_) : M(M_), G(G_), rc(rc_), rhoc(rhoc_) {
@@ -119,10 +112,10 @@ const int SI[6] = {0, 0, 0, 1, 1, 2}, SJ[6] = {0, 1, 2, 1, 2, 2};
 
 }  // namespace
 
-int host_initial_data(const grmhd_grid& gr, const grmhd_phys& ph, const Operators& ops,
-                      std::vector<double>* Uout, std::vector<double>* K0out, std::string* err) {
-  const int nr = gr.nr, nth = gr.nth, nph = gr.nph;
-  const size_t P = (size_t)nr * nth * nph, PL = (size_t)nr * nth;
+int host_initial_plane(const grmhd_grid& gr, const grmhd_phys& ph, const Operators& ops,
+                       std::vector<double>* plane, std::string* err) {
+  const int nr = gr.nr, nth = gr.nth;
+  const size_t PL = (size_t)nr * nth;
   const double M = ph.M, a = ph.a;
   // derivative along r / theta of a plane function f[k * nr + j]
   auto dr = [&](const std::vector<double>& f, std::vector<double>& out) {
@@ -383,56 +376,28 @@ int host_initial_data(const grmhd_grid& gr, const grmhd_phys& ph, const Operator
     return GRMHD_E_ARG;
   }
 
-  // ---- assemble the 3D state ----
-  Uout->assign((size_t)NF * P, 0.0);
-  K0out->assign(P, 0.0);
-  std::vector<double>& U = *Uout;
-  const double G = ph.gamma_ad;
-  for (int l = 0; l < nph; ++l)
-    for (int k = 0; k < nth; ++k)
-      for (int j = 0; j < nr; ++j) {
-        const size_t e = (size_t)k * nr + j;
-        const size_t n = ((size_t)l * nth + k) * nr + j;
-        U[0 * P + n] = phi[e];
-        for (int s = 0; s < 6; ++s) {
-          U[(1 + s) * P + n] = gt[s][e];
-          U[(7 + s) * P + n] = At[s][e];
-        }
-        U[13 * P + n] = Kf[e];
-        for (int i = 0; i < 3; ++i) U[(14 + i) * P + n] = Gt[i][e];
-        U[17 * P + n] = alpha[e];
-        U[18 * P + n] = betar[e];
-        (*K0out)[n] = K0[e];
-        // matter; seeded perturbation of rho (Michel) or p (torus)
-        double rho = rho_pl[e], p = p_pl[e];
-        if (ph.pert_amp != 0.0) {
-          const double u = (double)(splitmix64(ph.seed ^ (uint64_t)n) >> 11) * 0x1.0p-53;
-          if (torus) p = p * (1.0 + ph.pert_amp * (2.0 * u - 1.0));
-          else rho = rho * (1.0 + ph.pert_amp * (2.0 * u - 1.0));
-        }
-        const double sg = sqrtg[e];
-        double gm[9];
-        for (int c = 0; c < 9; ++c) gm[c] = gm_pl[c][e];
-        const double v[3] = {v_pl[0][e], v_pl[1][e], v_pl[2][e]};
-        const double Bu[3] = {sB_pl[0][e] / sg, sB_pl[1][e] / sg, sB_pl[2][e] / sg};
-        double vl[3], Bl[3];
-        for (int i = 0; i < 3; ++i) {
-          vl[i] = gm[i * 3 + 0] * v[0] + gm[i * 3 + 1] * v[1] + gm[i * 3 + 2] * v[2];
-          Bl[i] = gm[i * 3 + 0] * Bu[0] + gm[i * 3 + 1] * Bu[1] + gm[i * 3 + 2] * Bu[2];
-        }
-        const double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
-        const double W = 1.0 / sqrt(1.0 - v2);
-        const double Bv = Bu[0] * vl[0] + Bu[1] * vl[1] + Bu[2] * vl[2];
-        const double B2 = Bu[0] * Bl[0] + Bu[1] * Bl[1] + Bu[2] * Bl[2];
-        const double h = 1.0 + p / rho * G / (G - 1.0);
-        const double Z = rho * h * W * W;
-        const double D = rho * W;
-        const double tau = Z - p + B2 - 0.5 * (B2 / (W * W) + Bv * Bv) - D;
-        U[24 * P + n] = sg * D;
-        for (int i = 0; i < 3; ++i) U[(25 + i) * P + n] = sg * ((Z + B2) * vl[i] - Bv * Bl[i]);
-        U[28 * P + n] = sg * tau;
-        for (int i = 0; i < 3; ++i) U[(29 + i) * P + n] = sB_pl[i][e];
-      }
+  // ---- the plane fields, in the order of the PL_* indices ----
+  plane->assign((size_t)PL_NFIELDS * PL, 0.0);
+  double* out = plane->data();
+  auto put = [&](int f, const std::vector<double>& v) { std::copy(v.begin(), v.end(), out + (size_t)f * PL); };
+  put(PL_PHI, phi);
+  for (int s = 0; s < 6; ++s) {
+    put(PL_GT + s, gt[s]);
+    put(PL_AT + s, At[s]);
+  }
+  put(PL_K, Kf);
+  for (int i = 0; i < 3; ++i) put(PL_GAMT + i, Gt[i]);
+  put(PL_ALPHA, alpha);
+  put(PL_BETAR, betar);
+  put(PL_K0, K0);
+  put(PL_RHO, rho_pl);
+  put(PL_P, p_pl);
+  for (int i = 0; i < 3; ++i) {
+    put(PL_V + i, v_pl[i]);
+    put(PL_SB + i, sB_pl[i]);
+  }
+  put(PL_SQRTG, sqrtg);
+  for (int c = 0; c < 9; ++c) put(PL_GM + c, gm_pl[c]);
   return GRMHD_OK;
 }
 

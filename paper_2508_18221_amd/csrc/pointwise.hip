@@ -1056,6 +1056,75 @@ __global__ __launch_bounds__(256) void k_ham(const double* __restrict__ U, const
 }
 
 // ---------------------------------------------------------------------------
+// Initial state from the (theta, r) plane fields (see launch_init_expand).
+__device__ __forceinline__ uint64_t splitmix64_dev(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_init_expand(const double* __restrict__ pl, int torus, uint64_t seed,
+                                                     double amp, double G, PointParams pp, double* __restrict__ U,
+                                                     double* __restrict__ K0) {
+  const long long P = pp.P;
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= P) return;
+  const long long PL = (long long)pp.nr * pp.nth;
+  const long long e = n % PL;
+#define PLF(f) pl[(size_t)(f) * PL + e]
+  U[n] = PLF(PL_PHI);
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    U[(size_t)(1 + s) * P + n] = PLF(PL_GT + s);
+    U[(size_t)(7 + s) * P + n] = PLF(PL_AT + s);
+  }
+  U[(size_t)13 * P + n] = PLF(PL_K);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) U[(size_t)(14 + i) * P + n] = PLF(PL_GAMT + i);
+  U[(size_t)17 * P + n] = PLF(PL_ALPHA);
+  U[(size_t)18 * P + n] = PLF(PL_BETAR);
+#pragma unroll
+  for (int f = 19; f < 24; ++f) U[(size_t)f * P + n] = 0.0;
+  K0[n] = PLF(PL_K0);
+  double rho = PLF(PL_RHO), p = PLF(PL_P);
+  if (amp != 0.0) {
+    const double u = (double)(splitmix64_dev(seed ^ (uint64_t)n) >> 11) * 0x1.0p-53;
+    if (torus)
+      p = p * (1.0 + amp * (2.0 * u - 1.0));
+    else
+      rho = rho * (1.0 + amp * (2.0 * u - 1.0));
+  }
+  const double sg = PLF(PL_SQRTG);
+  double gm[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) gm[c] = PLF(PL_GM + c);
+  const double v[3] = {PLF(PL_V), PLF(PL_V + 1), PLF(PL_V + 2)};
+  const double sB[3] = {PLF(PL_SB), PLF(PL_SB + 1), PLF(PL_SB + 2)};
+#undef PLF
+  const double Bu[3] = {sB[0] / sg, sB[1] / sg, sB[2] / sg};
+  double vl[3], Bl[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    vl[i] = gm[i * 3 + 0] * v[0] + gm[i * 3 + 1] * v[1] + gm[i * 3 + 2] * v[2];
+    Bl[i] = gm[i * 3 + 0] * Bu[0] + gm[i * 3 + 1] * Bu[1] + gm[i * 3 + 2] * Bu[2];
+  }
+  const double v2 = v[0] * vl[0] + v[1] * vl[1] + v[2] * vl[2];
+  const double W = 1.0 / sqrt(1.0 - v2);
+  const double Bv = Bu[0] * vl[0] + Bu[1] * vl[1] + Bu[2] * vl[2];
+  const double B2 = Bu[0] * Bl[0] + Bu[1] * Bl[1] + Bu[2] * Bl[2];
+  const double h = 1.0 + p / rho * G / (G - 1.0);
+  const double Z = rho * h * W * W;
+  const double D = rho * W;
+  const double tau = Z - p + B2 - 0.5 * (B2 / (W * W) + Bv * Bv) - D;
+  U[(size_t)24 * P + n] = sg * D;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) U[(size_t)(25 + i) * P + n] = sg * ((Z + B2) * vl[i] - Bv * Bl[i]);
+  U[(size_t)28 * P + n] = sg * tau;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) U[(size_t)(29 + i) * P + n] = sB[i];
+}
+
 __global__ __launch_bounds__(256) void k_k0(const double* __restrict__ U, const double* __restrict__ scr,
                                             double* __restrict__ K0, long long P) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1201,6 +1270,13 @@ hipError_t launch_ham(const double* U, const double* der, const double* prim, do
 hipError_t launch_k0(const double* U, const double* scr, double* K0, const PointParams& pp,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_k0, dim3(nblk(pp.P)), dim3(256), 0, s, U, scr, K0, pp.P);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_expand(const double* plane, int torus, uint64_t seed, double amp, double gamma_ad,
+                              const PointParams& pp, double* U, double* K0, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_expand, dim3(nblk(pp.P)), dim3(256), 0, s, plane, torus, seed, amp, gamma_ad, pp, U,
+                     K0);
   return hipGetLastError();
 }
 
