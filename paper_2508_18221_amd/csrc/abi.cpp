@@ -573,6 +573,15 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
 
 }  // extern "C"
 
+bool grmhd::same_step_class(const grmhd_grid& ga, const grmhd_phys& pa, grmhd_prec qa, const grmhd_grid& gb,
+                            const grmhd_phys& pb, grmhd_prec qb) {
+  return ga.nr == gb.nr && ga.nth == gb.nth && ga.nph == gb.nph && ga.filter_on == gb.filter_on &&
+         ga.dealias == gb.dealias && qa == qb && pa.gamma_ad == pb.gamma_ad && pa.eta == pb.eta &&
+         pa.rho_floor == pb.rho_floor && pa.p_floor == pb.p_floor && pa.cowling == pb.cowling &&
+         pa.gauge_k0 == pb.gauge_k0 && pa.split == pb.split && pa.c2p_damped == pb.c2p_damped &&
+         pa.glm == pb.glm && (!pa.glm || (pa.glm_ch == pb.glm_ch && pa.glm_tau == pb.glm_tau));
+}
+
 int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
                           void* dev_scratch, void* hip_stream, const Operators* prebuilt, grmhd_ctx** out) {
   int rc = validate_grid(grid);
@@ -837,14 +846,7 @@ int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {
     const grmhd_ctx* c = ctxs[j];
     if (!c) return fail(GRMHD_E_ARG, "null context in batch");
     if (!c->have_state) return fail(GRMHD_E_STATE, "context in batch has no state");
-    const bool same = c->grid.nr == c0->grid.nr && c->grid.nth == c0->grid.nth && c->grid.nph == c0->grid.nph &&
-                      c->grid.filter_on == c0->grid.filter_on && c->grid.dealias == c0->grid.dealias &&
-                      c->prec == c0->prec &&
-                      c->pp.gamma_ad == c0->pp.gamma_ad && c->pp.eta == c0->pp.eta &&
-                      c->pp.cowling == c0->pp.cowling && c->pp.gauge_k0 == c0->pp.gauge_k0 &&
-                      c->pp.rho_floor == c0->pp.rho_floor && c->pp.p_floor == c0->pp.p_floor &&
-                      c->pp.glm == c0->pp.glm && c->pp.ch2 == c0->pp.ch2 && c->pp.itau == c0->pp.itau &&
-                      c->phys.split == c0->phys.split && c->pp.c2p_damped == c0->pp.c2p_damped &&
+    const bool same = same_step_class(c->grid, c->phys, c->prec, c0->grid, c0->phys, c0->prec) &&
                       c->stream == c0->stream &&
                       ((const char*)c->scr - c->res) == ((const char*)c0->scr - c0->res);
     if (!same)

@@ -156,6 +156,15 @@ struct Operators {
 
 void build_operators(const grmhd_grid& g, double cfl, Operators* ops);
 
+// Two contexts can share one launch sequence (grmhd_step_batch, the job
+// server's classes) when their buffers are laid out alike and the kernels get
+// the same parameters and take the same path: same grid sizes, filter and
+// dealiasing switches, precision, Gamma, eta, floors and form switches
+// (fixed background, 1+log source, GLM with its c_h and tau, split step,
+// damped recovery).  Operators, floors and dt are per job.
+bool same_step_class(const grmhd_grid& ga, const grmhd_phys& pa, grmhd_prec qa, const grmhd_grid& gb,
+                     const grmhd_phys& pb, grmhd_prec qb);
+
 // grmhd_create with the operators of this grid and cfl built beforehand
 // (prebuilt: copied into the context; null: built here).  The job server keeps
 // one set per grid, so admission does not rebuild them.

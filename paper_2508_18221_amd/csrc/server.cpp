@@ -101,15 +101,9 @@ struct Arena {
   }
 };
 
+// jobs of one class are stepped by one batched launch sequence
 bool same_class(const Job& a, const Job& b) {
-  return a.grid.nr == b.grid.nr && a.grid.nth == b.grid.nth && a.grid.nph == b.grid.nph &&
-         a.grid.filter_on == b.grid.filter_on && a.grid.dealias == b.grid.dealias && a.prec == b.prec &&
-         a.phys.gamma_ad == b.phys.gamma_ad &&
-         a.phys.eta == b.phys.eta && a.phys.cowling == b.phys.cowling && a.phys.gauge_k0 == b.phys.gauge_k0 &&
-         a.phys.split == b.phys.split && a.phys.c2p_damped == b.phys.c2p_damped &&
-         a.phys.glm == b.phys.glm && (!a.phys.glm || (a.phys.glm_ch == b.phys.glm_ch &&
-                                                      a.phys.glm_tau == b.phys.glm_tau)) &&
-         a.phys.rho_floor == b.phys.rho_floor && a.phys.p_floor == b.phys.p_floor;
+  return grmhd::same_step_class(a.grid, a.phys, a.prec, b.grid, b.phys, b.prec);
 }
 
 }  // namespace
