@@ -170,7 +170,9 @@ int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec,
 
 /* Build operators (host, long double) and upload them into dev_resident.
  * dev_resident / dev_scratch: device buffers of at least the queried sizes,
- * 256-byte aligned; hip_stream: a hipStream_t (0 = null stream).  Syncs. */
+ * 256-byte aligned; hip_stream: a hipStream_t (0 = null stream).  Syncs.
+ * GRMHD_E_ARG for a grid or parameter out of range (Gamma > 1, cfl > 0,
+ * 0 <= |a| <= M, finite floors > 0, switches 0 or 1, ...). */
 int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec,
                  void* dev_resident, void* dev_scratch, void* hip_stream,
                  grmhd_ctx** out);
@@ -180,8 +182,12 @@ int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec
 int grmhd_destroy(grmhd_ctx* ctx);
 
 /* Kerr-Schild background in BSSN variables + magnetised Michel flow + seeded
- * density perturbation, computed on the host and uploaded; sets K0 and
- * primes the con2prim guesses.  t = 0.  Syncs. */
+ * density perturbation (or the torus of id_kind), computed on the host (the
+ * (theta, r) plane) and expanded on the device; sets K0 and primes the
+ * con2prim guesses.  t = 0.  Syncs.  GRMHD_E_ARG, state untouched, when the
+ * data do not exist for the parameters: M = 0, pert_amp outside [0, 1),
+ * rho_c or beta_min not > 0, r_c inside the Michel bound
+ * M (3 Gamma - 2) / (2 (Gamma - 1)), or any non-finite plane value. */
 int grmhd_init_state(grmhd_ctx* ctx);
 
 /* Copy a state in (host, n = 32 P doubles, layout above; a GLM context also

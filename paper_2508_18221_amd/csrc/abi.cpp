@@ -595,6 +595,9 @@ int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_
     return fail(GRMHD_E_ARG, "need Gamma > 1, cfl > 0, M >= 0, |a| <= M");
   if (phys->id_kind != GRMHD_ID_MICHEL && phys->id_kind != GRMHD_ID_TORUS)
     return fail(GRMHD_E_ARG, "unknown initial-data kind");
+  if (!(phys->rho_floor > 0.0 && phys->p_floor > 0.0 && std::isfinite(phys->rho_floor) &&
+        std::isfinite(phys->p_floor) && std::isfinite(phys->eta)))
+    return fail(GRMHD_E_ARG, "need finite floors rho_floor > 0, p_floor > 0 and a finite eta");
   if (phys->glm != 0 && phys->glm != 1) return fail(GRMHD_E_ARG, "glm must be 0 or 1");
   if (phys->split != 0 && phys->split != 1) return fail(GRMHD_E_ARG, "split must be 0 or 1");
   if (phys->split && phys->cowling) return fail(GRMHD_E_ARG, "the split step needs cowling = 0");

@@ -117,6 +117,14 @@ int host_initial_plane(const grmhd_grid& gr, const grmhd_phys& ph, const Operato
   const int nr = gr.nr, nth = gr.nth;
   const size_t PL = (size_t)nr * nth;
   const double M = ph.M, a = ph.a;
+  auto bad = [&](const char* why) {
+    if (err) *err = std::string("initial data: ") + why;
+    return GRMHD_E_ARG;
+  };
+  if (!(M > 0.0)) return bad("needs a black hole, M > 0");
+  if (!(ph.pert_amp >= 0.0 && ph.pert_amp < 1.0)) return bad("needs 0 <= pert_amp < 1");
+  if (ph.id_kind == GRMHD_ID_MICHEL && !(ph.rho_c > 0.0 && ph.beta_min > 0.0))
+    return bad("Michel flow needs rho_c > 0 and beta_min > 0");
   // derivative along r / theta of a plane function f[k * nr + j]
   auto dr = [&](const std::vector<double>& f, std::vector<double>& out) {
     const int np = ops.npad[0];
@@ -268,6 +276,9 @@ int host_initial_plane(const grmhd_grid& gr, const grmhd_phys& ph, const Operato
   if (!torus) {
     // Michel flow + monopole sqrt(gamma) B^r = B0 sin(theta)
     const Bondi mic(M, ph.gamma_ad, ph.r_c, ph.rho_c);
+    // a transonic solution needs 0 < T_c, i.e. r_c > M (3 Gamma - 2) / (2 (Gamma - 1))
+    if (!(ph.r_c > 0.0 && mic.Tc > 0.0 && std::isfinite(mic.Tc) && std::isfinite(mic.Kp)))
+      return bad("no transonic Michel flow for this r_c (need r_c > M (3 Gamma - 2) / (2 (Gamma - 1)))");
     std::vector<double> rho1(nr), p1(nr), ur1(nr);
     for (int j = 0; j < nr; ++j) {
       const double r = ops.r[j];
@@ -398,6 +409,8 @@ int host_initial_plane(const grmhd_grid& gr, const grmhd_phys& ph, const Operato
   }
   put(PL_SQRTG, sqrtg);
   for (int c = 0; c < 9; ++c) put(PL_GM + c, gm_pl[c]);
+  for (const double v : *plane)
+    if (!std::isfinite(v)) return bad("a plane field is not finite (excision radius or parameters out of range)");
   return GRMHD_OK;
 }
 

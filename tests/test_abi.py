@@ -1,6 +1,7 @@
 """The C-ABI library loads on the CPU and exports every entry point that
 include/grmhd.h declares; host-side argument validation works without a GPU."""
 
+import ast
 import ctypes
 import os
 import re
@@ -60,5 +61,30 @@ def test_library_shares_torch_hip_runtime():
             "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
                          cwd=str(__import__("pathlib").Path(__file__).resolve().parents[1])).stdout
-    libs = eval(out.strip().splitlines()[-1])
+    libs = ast.literal_eval(out.strip().splitlines()[-1])
     assert len(libs) == 1, libs
+
+
+def test_create_rejects_parameters_out_of_range_on_host():
+    """grmhd_create checks its parameters before it touches the device, so
+    the checks run here without a GPU (the buffer arguments are never used)."""
+    from paper_2508_18221_amd import _lib, make_grid, make_phys
+    lib = _lib.load()
+    g = make_grid(16, 16, 16)
+    ctx = ctypes.c_void_p()
+    cases = [(dict(gamma_ad=1.0), b"Gamma"), (dict(M=1.0, a=1.2), b"|a|"), (dict(cfl=0.0), b"cfl"),
+             (dict(rho_floor=0.0), b"floors"), (dict(p_floor=float("nan")), b"floors"),
+             (dict(eta=float("inf")), b"eta"), (dict(split=True, cowling=True), b"split")]
+    for over, msg in cases:
+        p = make_phys(**over)
+        rc = lib.grmhd_create(ctypes.byref(g), ctypes.byref(p), 0, ctypes.c_void_p(256), ctypes.c_void_p(512),
+                              None, ctypes.byref(ctx))
+        assert rc == -1 and msg in lib.grmhd_last_error(), (over, lib.grmhd_last_error())
+    p = make_phys()
+    p.glm, p.glm_ch = 1, 0.0
+    rc = lib.grmhd_create(ctypes.byref(g), ctypes.byref(p), 0, ctypes.c_void_p(256), ctypes.c_void_p(512),
+                          None, ctypes.byref(ctx))
+    assert rc == -1 and b"GLM" in lib.grmhd_last_error()
+    rc = lib.grmhd_create(ctypes.byref(g), ctypes.byref(p), 0, ctypes.c_void_p(300), ctypes.c_void_p(512),
+                          None, ctypes.byref(ctx))
+    assert rc == -1

@@ -170,3 +170,24 @@ def test_diagnostics_match_oracle():
     assert abs(d["max_abs_divB"] - np.abs(divB).max()) < 1e-12 * np.abs(U[29]).max()
     assert abs(d["min_alpha"] - U[17].min()) < 1e-15
     s.close()
+
+
+def test_init_state_rejects_parameters_without_data():
+    """Initial data that do not exist for the parameters (no black hole, no
+    transonic Michel flow, no field) end in an error with the state
+    untouched; the context stays usable."""
+    from paper_2508_18221_amd import Solver, make_grid, make_phys
+    from paper_2508_18221_amd._lib import GrmhdError
+    log("[init errors] 16^3: M = 0, r_c below the Michel bound, beta_min = 0, pert_amp = 1")
+    g = make_grid(16, 16, 16)
+    for over, msg in [(dict(M=0.0, a=0.0), "M > 0"), (dict(r_c=2.5), "transonic"),
+                      (dict(beta_min=0.0), "beta_min"), (dict(pert_amp=1.0), "pert_amp")]:
+        s = Solver(g, make_phys(**over))
+        with pytest.raises(GrmhdError, match=msg):
+            s.init_state()
+        s.close()
+    ok = Solver(g, make_phys())
+    ok.init_state()
+    ok.step(1)
+    assert ok.diagnostics()["nonfinite"] == 0
+    ok.close()
