@@ -224,9 +224,11 @@ int grmhd_step(grmhd_ctx* ctx, int32_t nsteps);
 /* nsteps RK4 steps (+ filter) of n contexts of one grid class, each kernel
  * launched once for all of them (continuous batching; up to 32 jobs per
  * launch, larger n is split).  The contexts must share grid sizes, precision,
- * the kernel parameters (Gamma, eta, cowling, gauge_k0, floors, GLM), the stream
- * and the offset between their scratch and resident buffers; r_in, the spin,
- * the initial data and dt may differ.  Each job's arithmetic is the same
+ * the filter and dealiasing switches, the kernel parameters (Gamma, eta,
+ * floors, cowling, gauge_k0, GLM with c_h and tau), the split step and the
+ * damped recovery switches, the stream and the offset between their scratch
+ * and resident buffers (else GRMHD_E_ARG); r_in, r_out, the theta range, the
+ * filter constants, the spin, the initial data and dt may differ.  Each job's arithmetic is the same
  * as when stepped alone (bitwise).  Async. */
 int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps);
 
