@@ -213,3 +213,34 @@ def test_served_fixed_background_job_in_a_mix_equals_alone():
     s.close()
     assert np.array_equal(served[:24], U0[:24])
     assert np.array_equal(served, alone)
+
+
+def test_flat_space_advection_rate_closed_form():
+    """The library's matter right-hand side against an exact solution, not
+    only against the oracle: a density blob carried at uniform velocity
+    through flat space (M = 0, fixed background; tests/advection_case.py).
+    Same bars as the oracle's pin at 32 x 32 x 48, and the oracle's RHS to
+    the parity bar."""
+    from paper_2508_18221_amd import Solver, make_grid, make_phys
+    from advection_case import advection_errors, flat_advection_state
+    log("[flat-space advection] 32x32x48, M = 0, fixed background, one RHS vs the exact rates")
+    g, pb, U, K0, exact = flat_advection_state(32, 32, 48)
+    s = Solver(make_grid(32, 32, 48), make_phys(M=0.0, a=0.0, cowling=True))
+    s.set_state(U, K0)
+    dU = torch.tensor(U, device="cuda")
+    out = torch.full_like(dU, np.nan)
+    s.rhs(dU, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    s.close()
+    e, induction = advection_errors(got, exact)
+    log("  errors vs exact (D, S_r, S_th, S_ph, tau): " + " ".join(f"{x:.1e}" for x in e)
+        + f"; induction {induction:.1e}")
+    assert np.isfinite(got).all()
+    assert induction == 0.0
+    for q in (0, 1, 3, 4):
+        assert e[q] < 1e-4
+    assert e[2] < 0.1
+    ep = rhs_errors(got, pb.rhs(U, K0), U)
+    log(f"  vs oracle: max e_f {ep.max():.1e}")
+    assert ep.max() < 1e-11
