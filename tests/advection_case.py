@@ -21,7 +21,17 @@ part of the momentum flux, so a dropped or mis-signed source, flux or
 velocity component shows as an O(1) error that does not converge.  The
 pressure-work term of the tau flux is invisible here (the velocity field is
 divergence-free and p uniform); the flux formulas have their own pin against
-the covariant definition."""
+the covariant definition.
+
+With field=True a magnetic flux tube along the flow, B = b(x, y) z-hat
+through the blob (b Gaussian across the tube, which runs parallel to the
+polar axis at distance 8, clear of the axis and the inner boundary), rides
+with it: b varies only across the flow (div B = 0), the gas pressure
+p = P0 - b^2/2 keeps the total pressure uniform, and the tension (b . grad) b
+vanishes, so the same blob is still carried unchanged; for v parallel to B,
+b^2 = B^2 and v x B = 0, and B and p are static, so the rates above hold
+unchanged.  That case checks the magnetic stresses in the momentum flux and
+in the geometric source as well."""
 
 import numpy as np
 
@@ -29,15 +39,17 @@ from oracle import evolve, initial_data, spectral
 from oracle.grmhd import prim_to_cons
 
 R_IN, R_OUT, TH0, TH1 = 1.8, 20.0, 0.05, np.pi - 0.05
-V = 0.5          # speed, along the Cartesian y axis
+V = 0.5          # speed, along the Cartesian z axis
 W_BLOB = 3.0     # Gaussian width
 X_C = 8.0        # blob centre (8, 0, 0): on the equator, off the axis
 RHO_A, RHO_B, P0 = 1e-2, 5e-3, 1e-3
+B_TUBE = 0.03    # peak field of the flux tube (field=True)
 
 
-def flat_advection_state(nr, nth, nph):
+def flat_advection_state(nr, nth, nph, field=False):
     """Grid, oracle problem, state U, K0 and the exact right-hand side of
-    fields 24..31 for the advected blob."""
+    fields 24..31 for the advected blob (with field=True: the field along
+    the flow and the balancing pressure)."""
     g = spectral.Grid(nr, nth, nph, R_IN, R_OUT, TH0, TH1)
     pb = evolve.Problem(g, M=0.0, a=0.0, cowling=True)
     f = initial_data.kerr_schild_bssn(g, 0.0, 0.0)
@@ -47,11 +59,17 @@ def flat_advection_state(nr, nth, nph):
     x, y, z = R * np.sin(TH) * np.cos(PH), R * np.sin(TH) * np.sin(PH), R * np.cos(TH)
     blob = np.exp(-((x - X_C) ** 2 + y ** 2 + z ** 2) / W_BLOB ** 2)
     rho = RHO_A + RHO_B * blob
-    drho = V * RHO_B * blob * 2.0 * y / W_BLOB ** 2          # -V d_y rho_0
-    p = np.full(g.shape, P0)
-    # V y-hat in the coordinate basis
-    v = np.array([V * np.sin(TH) * np.sin(PH), V * np.cos(TH) * np.sin(PH) / R, V * np.cos(PH) / (R * np.sin(TH))])
-    B = np.zeros((3,) + g.shape)
+    drho = V * RHO_B * blob * 2.0 * z / W_BLOB ** 2          # -V d_z rho_0
+    # z-hat in the coordinate basis
+    zhat = np.array([np.cos(TH), -np.sin(TH) / R, np.zeros(g.shape)])
+    v = V * zhat
+    if field:
+        b = B_TUBE * np.exp(-((x - X_C) ** 2 + y ** 2) / W_BLOB ** 2)
+        B = b * zhat
+        p = P0 - 0.5 * b * b
+    else:
+        B = np.zeros((3,) + g.shape)
+        p = np.full(g.shape, P0)
     D, S, tau = prim_to_cons(rho, p, v, B, gam, pb.Gamma)
     U = evolve.pack(f, dict(sD=sqrtg * D, sS=sqrtg * S, stau=sqrtg * tau, sB=sqrtg * B))
     K0 = evolve.gauge_source_k0(g, f)
