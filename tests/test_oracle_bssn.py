@@ -145,3 +145,22 @@ def test_gauge_terms():
     assert np.abs(r0['Bd'] - (r0['Gt'] - 2.0 * f['Bd'])).max() < 1e-12
     r2 = bssn.bssn_rhs(f, d, dd, z, zS, zSS, K0, 2.0, gauge_k0=False)
     assert np.abs((r2['alpha'] - r0['alpha']) + 2 * f['alpha'] * K0).max() < 1e-14
+
+
+def test_lapse_pulse_rates_closed_form():
+    """Spacetime right-hand side pinned by closed forms away from a stationary
+    state: a lapse pulse on flat space in the solver's spherical coordinates
+    (tests/lapse_case.py).  d_t K = -Laplacian(alpha) and d_t At_ij =
+    -e^{-4 phi} (D_i D_j alpha)^TF converge spectrally to the exact rates
+    (>= 5x per refinement), every other spacetime rate is zero.  Flipping or
+    dropping the Christoffel term of D_i D_j alpha fails it."""
+    from lapse_case import lapse_errors, lapse_pulse_state
+    errs = []
+    for n in ((32, 32, 48), (40, 40, 64)):
+        g, pb, U, U_flat, K0, exact = lapse_pulse_state(*n)
+        drhs = pb.rhs(U, K0)[:24] - pb.rhs(U_flat, K0)[:24]
+        errs.append(lapse_errors(drhs, exact))
+    (cK, cA, c0), (fK, fA, f0) = errs
+    assert c0 < 1e-14 and f0 < 1e-14
+    assert fK < 1e-3 and fK < cK / 5, (cK, fK)
+    assert fA < 1e-2 and fA < cA / 5, (cA, fA)
