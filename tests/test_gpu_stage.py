@@ -196,7 +196,7 @@ def test_init_state_rejects_parameters_without_data():
 def test_lapse_pulse_rates_closed_form():
     """The library's spacetime right-hand side against closed forms, not
     only against the oracle: a lapse pulse on flat space (M = 0, coupled
-    path; tests/lapse_case.py).  The oracle's bars at 40 x 40 x 64, and the
+    path; tests/gauge_case.py).  The oracle's bars at 40 x 40 x 64, and the
     pulse's difference of right-hand sides against the oracle's.  The
     flat-space rates are largest (~0.1, the truncation of the discrete Ricci
     tensor of the conformal variables) at the nodes next to the theta ends on
@@ -204,7 +204,7 @@ def test_lapse_pulse_rates_closed_form():
     rounding of those terms, so the bar is the second derivatives' N^4 eps
     of the largest spacetime rate."""
     from paper_2508_18221_amd import Solver, make_grid, make_phys
-    from lapse_case import lapse_errors, lapse_pulse_state
+    from gauge_case import lapse_errors, lapse_pulse_state
     n = (40, 40, 64)
     log(f"[lapse pulse] {n}, M = 0, coupled, RHS(pulse) - RHS(alpha = 1) vs the exact rates")
     g, pb, U, U_flat, K0, exact = lapse_pulse_state(*n)
@@ -223,6 +223,41 @@ def test_lapse_pulse_rates_closed_form():
     log(f"  errors vs exact: K {eK:.1e}, At {eA:.1e}, zero-rate fields {e0:.1e}")
     assert e0 < 1e-14 and eK < 1e-3 and eA < 1e-2
     d_lib = got[0][:24] - got[1][:24]
+    d_ora = pb.rhs(U, K0)[:24] - pb.rhs(U_flat, K0)[:24]
+    inner = (slice(None), slice(1, -1), slice(1, None))
+    scale = max(np.abs(pb.rhs(U, K0)[:24]).max(), np.abs(exact).max())
+    e = max(np.abs(d_lib[q][inner] - d_ora[q][inner]).max() for q in range(24)) / scale
+    bar = 4e-16 * max(n) ** 4
+    log(f"  vs oracle (difference of right-hand sides): {e:.1e} of the largest rate {scale:.1e} (bar {bar:.1e})")
+    assert e < bar
+
+
+def test_shift_pulse_rates_closed_form():
+    """The library's shift terms against closed forms: a shift pulse on flat
+    space (M = 0, coupled path; tests/gauge_case.py), the oracle's bars at
+    40 x 40 x 64, and the difference of right-hand sides against the
+    oracle's at N^4 eps of the largest spacetime rate (as for the lapse
+    pulse)."""
+    from paper_2508_18221_amd import Solver, make_grid, make_phys
+    from gauge_case import shift_errors, shift_pulse_state
+    n = (40, 40, 64)
+    log(f"[shift pulse] {n}, M = 0, coupled, RHS(pulse) - RHS(beta = 0) vs the exact rates")
+    g, pb, U, U_flat, K0, exact = shift_pulse_state(*n)
+    s = Solver(make_grid(*n), make_phys(M=0.0, a=0.0))
+    got = []
+    for state in (U, U_flat):
+        s.set_state(state, K0)
+        dU = torch.tensor(state, device="cuda")
+        out = torch.full_like(dU, np.nan)
+        s.rhs(dU, out)
+        torch.cuda.synchronize()
+        got.append(out.cpu().numpy())
+    s.close()
+    assert np.isfinite(got[0]).all() and np.isfinite(got[1]).all()
+    d_lib = got[0][:24] - got[1][:24]
+    ephi, egt, eGt, e0 = shift_errors(d_lib, exact)
+    log(f"  errors vs exact: phi {ephi:.1e}, gt {egt:.1e}, Gt {eGt:.1e}, zero-rate fields {e0:.1e}")
+    assert e0 < 1e-14 and ephi < 1e-3 and egt < 1e-3 and eGt < 1e-3
     d_ora = pb.rhs(U, K0)[:24] - pb.rhs(U_flat, K0)[:24]
     inner = (slice(None), slice(1, -1), slice(1, None))
     scale = max(np.abs(pb.rhs(U, K0)[:24]).max(), np.abs(exact).max())

@@ -150,11 +150,11 @@ def test_gauge_terms():
 def test_lapse_pulse_rates_closed_form():
     """Spacetime right-hand side pinned by closed forms away from a stationary
     state: a lapse pulse on flat space in the solver's spherical coordinates
-    (tests/lapse_case.py).  d_t K = -Laplacian(alpha) and d_t At_ij =
+    (tests/gauge_case.py).  d_t K = -Laplacian(alpha) and d_t At_ij =
     -e^{-4 phi} (D_i D_j alpha)^TF converge spectrally to the exact rates
     (>= 5x per refinement), every other spacetime rate is zero.  Flipping or
     dropping the Christoffel term of D_i D_j alpha fails it."""
-    from lapse_case import lapse_errors, lapse_pulse_state
+    from gauge_case import lapse_errors, lapse_pulse_state
     errs = []
     for n in ((32, 32, 48), (40, 40, 64)):
         g, pb, U, U_flat, K0, exact = lapse_pulse_state(*n)
@@ -164,3 +164,23 @@ def test_lapse_pulse_rates_closed_form():
     assert c0 < 1e-14 and f0 < 1e-14
     assert fK < 1e-3 and fK < cK / 5, (cK, fK)
     assert fA < 1e-2 and fA < cA / 5, (cA, fA)
+
+
+def test_shift_pulse_rates_closed_form():
+    """Shift terms pinned by closed forms: a shift pulse (fixed Cartesian
+    direction, Gaussian envelope) on flat space (tests/gauge_case.py).  The
+    phi, gt and Gt (and driver) rates converge spectrally to the coordinate
+    flow's (>= 5x per refinement); K, At, alpha and beta rates are zero.  A
+    flipped trace term or a dropped gt.dbeta term in the gt rate, a dropped
+    (1/3) gt^{ij} d_j d_k beta^k or a flipped Gt^j d_j beta^i term in the Gt
+    rate, or a wrong factor on div beta in the phi rate fail it."""
+    from gauge_case import shift_errors, shift_pulse_state
+    errs = []
+    for n in ((32, 32, 48), (40, 40, 64)):
+        g, pb, U, U_flat, K0, exact = shift_pulse_state(*n)
+        drhs = pb.rhs(U, K0)[:24] - pb.rhs(U_flat, K0)[:24]
+        errs.append(shift_errors(drhs, exact))
+    coarse, fine = errs
+    assert coarse[3] < 1e-14 and fine[3] < 1e-14
+    for k in range(3):  # phi, gt, Gt
+        assert fine[k] < 1e-3 and fine[k] < coarse[k] / 5, (k, coarse, fine)
