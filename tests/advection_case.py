@@ -46,10 +46,11 @@ RHO_A, RHO_B, P0 = 1e-2, 5e-3, 1e-3
 B_TUBE = 0.03    # peak field of the flux tube (field=True)
 
 
-def flat_advection_state(nr, nth, nph, field=False):
+def flat_advection_state(nr, nth, nph, field=False, blob=True):
     """Grid, oracle problem, state U, K0 and the exact right-hand side of
     fields 24..31 for the advected blob (with field=True: the field along
-    the flow and the balancing pressure)."""
+    the flow and the balancing pressure; blob=False: the same flow without
+    the blob, an exactly steady state)."""
     g = spectral.Grid(nr, nth, nph, R_IN, R_OUT, TH0, TH1)
     pb = evolve.Problem(g, M=0.0, a=0.0, cowling=True)
     f = initial_data.kerr_schild_bssn(g, 0.0, 0.0)
@@ -57,7 +58,7 @@ def flat_advection_state(nr, nth, nph, field=False):
     sqrtg = np.exp(6.0 * f['phi']) * np.sqrt(np.linalg.det(np.moveaxis(f['gt'], (0, 1), (-2, -1))))
     R, TH, PH = g.R, g.TH, g.PH
     x, y, z = R * np.sin(TH) * np.cos(PH), R * np.sin(TH) * np.sin(PH), R * np.cos(TH)
-    blob = np.exp(-((x - X_C) ** 2 + y ** 2 + z ** 2) / W_BLOB ** 2)
+    blob = np.exp(-((x - X_C) ** 2 + y ** 2 + z ** 2) / W_BLOB ** 2) * (1.0 if blob else 0.0)
     rho = RHO_A + RHO_B * blob
     drho = V * RHO_B * blob * 2.0 * z / W_BLOB ** 2          # -V d_z rho_0
     # z-hat in the coordinate basis
@@ -95,3 +96,10 @@ def advection_errors(rhs, exact):
         scale = max(np.abs(exact[k]).max() for k in groups[q])
         e[q] = np.abs(rhs[24 + q][inner] - exact[q][inner]).max() / scale
     return e, np.abs(rhs[29:32]).max()
+
+
+def exact_density_at(g, t):
+    """rho_0(x - V t z-hat) on the grid (the blob at time t)."""
+    R, TH, PH = g.R, g.TH, g.PH
+    x, y, z = R * np.sin(TH) * np.cos(PH), R * np.sin(TH) * np.sin(PH), R * np.cos(TH)
+    return RHO_A + RHO_B * np.exp(-((x - X_C) ** 2 + y ** 2 + (z - V * t) ** 2) / W_BLOB ** 2)
