@@ -93,6 +93,11 @@ def prim_to_cons(rho, p, v_up, B_up, gam, Gamma):
     return D, S, tau
 
 
+# Bisection budget: halving [0, hi] down to adjacent doubles takes at most
+# about 1100 steps (the exponent range of a double plus its 53-bit mantissa).
+C2P_BISECTIONS = 2000
+
+
 def _c2p_residual(Z, D, tau, S2, B2, BS, Gamma):
     """f(Z) = Z + B^2 - p - B^2/(2W^2) - (B.S)^2/(2Z^2) - tau - D, with
     v^2(Z) = (Z^2 S^2 + (2Z + B^2)(B.S)^2) / (Z^2 (Z + B^2)^2) and the ideal-gas
@@ -115,8 +120,9 @@ def con2prim(D, S_lo, tau, B_up, gam, gamu, Gamma, rho_fl, p_fl):
       v_j = (S_j + (B.S) B_j / Z) / (Z + B^2),  rho = D/W,
       p = (Gamma-1)/Gamma (Z/W^2 - rho).
     Failure policy (both implementations): D <= 0, tau + D <= 0, no sign change,
-    v^2 >= 1, rho < rho_fl or p < p_fl -> atmosphere (rho_fl, p_fl, v = 0) and
-    the point is flagged.  Returns rho, p, v_up, fail (bool array)."""
+    a bracket left unresolved by the iteration budget, v^2 >= 1, rho < rho_fl
+    or p < p_fl -> atmosphere (rho_fl, p_fl, v = 0) and the point is flagged.
+    Returns rho, p, v_up, fail (bool array)."""
     D = np.asarray(D, float)
     shape = D.shape
     S2 = dot(S_lo, np.einsum('ij...,j...->i...', gamu, S_lo))
@@ -136,7 +142,7 @@ def con2prim(D, S_lo, tau, B_up, gam, gamu, Gamma, rho_fl, p_fl):
         hi = np.where(need, 2.0 * hi, hi)
         fhi = _c2p_residual(hi, Dc, tc, S2, B2, BS, Gamma)
     bad |= ~(fhi >= 0.0)
-    for _ in range(2000):
+    for _ in range(C2P_BISECTIONS):
         mid = 0.5 * (lo + hi)
         active = (mid > lo) & (mid < hi)
         if not active.any():
@@ -145,6 +151,9 @@ def con2prim(D, S_lo, tau, B_up, gam, gamu, Gamma, rho_fl, p_fl):
         up = fm < 0.0
         lo = np.where(active & up, mid, lo)
         hi = np.where(active & ~up, mid, hi)
+    # a bracket not yet reduced to adjacent doubles is not a recovered state
+    mid = 0.5 * (lo + hi)
+    bad |= (mid > lo) & (mid < hi)
     Z = hi
     v_lo = (S_lo + BS * B_lo / Z) / (Z + B2)
     v_up = np.einsum('ij...,j...->i...', gamu, v_lo)

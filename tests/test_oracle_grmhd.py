@@ -291,3 +291,20 @@ def test_damped_con2prim_halving_keeps_the_state_physical():
     assert np.all(v2 < 1.0)
     assert np.all(rho[fail] == 1e-30) and np.all(p[fail] == 1e-40)
     assert np.all(p[~fail] > 0)
+
+
+def test_con2prim_unresolved_bracket_is_flagged(monkeypatch):
+    """A point whose bracket the bisection budget leaves wider than adjacent
+    doubles is not a recovered state: with a budget of 5 halvings every point
+    takes the atmosphere and is flagged (the GPU's Newton iteration applies
+    the same policy to its own budget)."""
+    rng = np.random.default_rng(17)
+    s = random_state(rng, 50, W_max=2.0, sig_max=1.0)
+    gam = s['gam']
+    D, S, tau = grmhd.prim_to_cons(s['rho'], s['p'], s['v'], s['B'], gam, s['G'])
+    monkeypatch.setattr(grmhd, "C2P_BISECTIONS", 5)
+    rho, p, v, fail = grmhd.con2prim(D, S, tau, s['B'], gam, grmhd.inv3(gam), s['G'], 1e-30, 1e-40)
+    assert fail.all() and np.all(rho == 1e-30) and np.all(v == 0)
+    monkeypatch.setattr(grmhd, "C2P_BISECTIONS", 2000)
+    rho, p, v, fail = grmhd.con2prim(D, S, tau, s['B'], gam, grmhd.inv3(gam), s['G'], 1e-30, 1e-40)
+    assert not fail.any()
