@@ -131,3 +131,38 @@ def hamiltonian(f, d, dd, E):
     Atu = np.einsum('ik...,jl...,kl...->ij...', gtu, gtu, At)
     return np.exp(-4.0 * phi) * np.einsum('ij...,ij...->...', gtu, R) + (2.0 / 3.0) * K * K \
         - np.einsum('ij...,ij...->...', At, Atu) - 16.0 * PI * E
+
+
+def momentum(f, d, S_lo):
+    """Momentum constraint in covariant components, from the physical form
+    D_j (K^j_i - delta^j_i K) = 8 pi S_i written in the BSSN variables:
+
+      M_i = Dt_j At^j_i + 6 At^j_i d_j phi - (2/3) d_i K - 8 pi S_i,
+
+    with At^j_i = gt^{jk} At_ki (the mixed components of the trace-free part
+    of K_ij are the same in the physical and the conformal metric), Dt the
+    covariant derivative of gt_ij,
+      Dt_j At^j_i = d_j At^j_i + Gt^j_jk At^k_i - Gt^k_ji At^j_k,
+    and the 6 At^j_i d_j phi term from sqrt(gamma) = e^{6 phi} sqrt(det gt)
+    (the other conformal terms of the Christoffel symbols cancel for a
+    trace-free mixed tensor).  S_lo[i] is the momentum density S_i seen by
+    normal observers (the undensitised Valencia S_j).  Derivative arrays as
+    in bssn_rhs (derivative index first)."""
+    gt, At = f['gt'], f['At']
+    gtu = inv3(gt)
+    dgt = d['gt']
+    _, Gu = conformal_christoffel(gtu, dgt)
+    # d_k gt^{jl} = -gt^{ja} gt^{lb} d_k gt_ab
+    dgtu = -np.einsum('ja...,lb...,kab...->kjl...', gtu, gtu, dgt)
+    Amix = np.einsum('jk...,ki...->ji...', gtu, At)          # At^j_i
+    divA = np.einsum('jjk...,ki...->i...', dgtu, At) + np.einsum('jk...,jki...->i...', gtu, d['At'])
+    trG = np.einsum('jjk...->k...', Gu)                       # Gt^j_jk
+    DdivA = divA + np.einsum('k...,ki...->i...', trG, Amix) - np.einsum('kji...,jk...->i...', Gu, Amix)
+    return DdivA + 6.0 * np.einsum('ji...,j...->i...', Amix, d['phi']) - (2.0 / 3.0) * d['K'] \
+        - 8.0 * PI * S_lo
+
+
+def momentum_norm(f, M_lo):
+    """|M| = sqrt(gamma^{ij} M_i M_j), gamma^{ij} = e^{-4 phi} gt^{ij}."""
+    gtu = inv3(f['gt'])
+    return np.sqrt(np.exp(-4.0 * f['phi']) * np.einsum('ij...,i...,j...->...', gtu, M_lo, M_lo))
