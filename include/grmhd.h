@@ -146,12 +146,18 @@ typedef struct {
   int32_t c2p_damped;
 } grmhd_phys;
 
-/* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"). */
+/* Diagnostics (Results: "Magnetic Constraint", "The Entropy Curve"; the
+ * Hamiltonian and momentum constraints the coupled evolution monitors,
+ * Results, coupled-evolution passage, and Methods, "Initial Data Solver XCTS
+ * Approximation").  The primitives behind rest mass, entropy and max W come
+ * from an exact recovery of the current state. */
 typedef struct {
   double t;                 /* simulation time                              */
   int64_t step;             /* completed RK4 steps                          */
   int64_t c2p_fail;         /* points that took the atmosphere policy in the
-                               last RHS evaluation                          */
+                               evolution's last primitive recovery (the last
+                               RHS evaluation, or the recovery that primes the
+                               warm start after init_state / set_state)     */
   int64_t nonfinite;        /* NaN/Inf entries in the state                  */
   double rest_mass;         /* sum sqrt(gamma) D w (quadrature weights w)    */
   double entropy;           /* E^n = sum rho s sqrt(gamma) w                 */
@@ -160,6 +166,10 @@ typedef struct {
   double ham_l2;            /* sqrt(sum H^2 w / sum w), Hamiltonian constraint
                                H = R + 2/3 K^2 - A_ij A^ij - 16 pi E          */
   double ham_linf;          /* max |H| over the nodes                        */
+  double mom_l2;            /* sqrt(sum |M|^2 w / sum w), momentum constraint
+                               M_i = D_j (K^j_i - delta^j_i K) - 8 pi S_i in
+                               BSSN form, |M|^2 = gamma^ij M_i M_j           */
+  double mom_linf;          /* max |M| over the nodes                        */
 } grmhd_diag;
 
 typedef struct grmhd_ctx grmhd_ctx;
@@ -242,7 +252,8 @@ int grmhd_set_stream(grmhd_ctx* ctx, void* hip_stream);
 int grmhd_time_step(const grmhd_grid* grid, double cfl, double* dt);
 
 /* Reductions over the current state (FP64 derivatives whatever the context's
- * precision; uses the scratch buffer, so call it between steps).  Syncs. */
+ * precision; uses the scratch buffer, so call it between steps).  Leaves the
+ * evolution's primitive warm start and failure flags untouched.  Syncs. */
 int grmhd_diagnostics(grmhd_ctx* ctx, grmhd_diag* out);
 
 double grmhd_dt(const grmhd_ctx* ctx);
@@ -259,12 +270,18 @@ const char* grmhd_last_error(void);
 int grmhd_apply_operator(grmhd_ctx* ctx, int32_t axis, int32_t op,
                          const double* dev_in, double* dev_out, int32_t nfields);
 
-/* Primitive recovery and densitised fluxes of a device state: writes
- * dev_prim (5 P doubles: rho, p, v^r, v^theta, v^phi) and, if non-null,
- * dev_flux (24 P doubles, [direction][variable], variables in state order
- * 24..31).  Async. */
+/* Primitive recovery (Methods, "The Primitive Variable Recovery": the
+ * unique primitive state reproducing U) and densitised fluxes of a device
+ * state (32 P doubles, layout above; the metric is reconstructed from its
+ * fields 0..6): writes dev_prim (5 P doubles: rho, p, v^r, v^theta, v^phi)
+ * and, if non-null, dev_flux (24 P doubles, [direction][variable], variables
+ * in state order 24..31) and dev_fail (P doubles: 1.0 where the point took
+ * the atmosphere policy -- D <= 0, tau + D <= 0, no root with v^2 < 1, no
+ * convergence within the iteration budget, or rho, p below the floors --
+ * else 0.0).  The iteration starts from the context's last recovery and
+ * leaves its result there as the next warm start.  Async. */
 int grmhd_con2prim(grmhd_ctx* ctx, const double* dev_U, double* dev_prim,
-                   double* dev_flux);
+                   double* dev_flux, double* dev_fail);
 
 /* ---- served form: continuous-batching job server ------------------------- */
 
@@ -286,16 +303,19 @@ typedef struct {
   double p50_latency, p99_latency, mean_latency;  /* completed jobs, seconds  */
   double point_stage_updates;  /* completed work: sum over jobs of 4 P steps */
   double wall;              /* first submission to last completion, seconds  */
-  double busy;              /* seconds spent inside ticks                    */
+  double busy;              /* seconds with device work in flight, as seen
+                               by the ticks (0 in a dry run)                */
   size_t bytes_in_use, bytes_peak;
 } grmhd_server_summary;
 
 /* A server that places jobs in the caller's device arena (dev_arena,
  * arena_bytes = the memory budget; 256-byte aligned) and steps jobs of one
  * grid class together, at most max_batch per launch sequence.  Each grid
- * class runs on a stream of its own (default priority); hip_stream is the
- * fallback.  dev_arena NULL: dry run, no device work (each job step completes
- * at once), for exercising the scheduling logic without a GPU. */
+ * class runs on a stream of its own (default priority) and advances at its
+ * own pace, with up to two RK4 steps in flight; initial data are built on an
+ * admission stream of the server's.  hip_stream is the fallback stream.
+ * dev_arena NULL: dry run, no device work (each job step completes at once),
+ * for exercising the scheduling logic without a GPU. */
 int grmhd_server_create(void* dev_arena, size_t arena_bytes, int32_t max_batch, void* hip_stream,
                         grmhd_server** out);
 int grmhd_server_destroy(grmhd_server* srv);
@@ -303,14 +323,24 @@ int grmhd_server_destroy(grmhd_server* srv);
 /* Queue a job that evolves (grid, phys) from its initial data to t_end; the
  * arrival time is the server clock now.  keep_state: copy the final state to
  * host memory at completion (grmhd_server_result).  A job larger than the
- * whole budget is rejected (GRMHD_E_BUDGET). */
+ * whole budget is recorded as rejected (GRMHD_E_BUDGET); a grid, precision
+ * or parameter set that grmhd_create would refuse, or for which
+ * grmhd_init_state has no data (M = 0, pert_amp outside [0, 1), beta_min or
+ * rho_c not > 0, r_c inside the Michel bound, bad torus parameters), is
+ * refused with GRMHD_E_ARG and not queued. */
 int grmhd_server_submit(grmhd_server* srv, const grmhd_grid* grid, const grmhd_phys* phys,
                         grmhd_prec prec, double t_end, int32_t keep_state, int64_t* job_id);
 
-/* Admit queued jobs in arrival order while they fit, advance every running
- * job by one RK4 step (one batched launch sequence per grid class), retire
- * finished jobs and free their memory.  n_pending: queued + running after the
- * tick.  Syncs. */
+/* One scheduling round: count the RK4 steps that have completed on the
+ * device (event queries per grid class) and retire jobs that reached their
+ * end time, freeing their memory; admit queued jobs in arrival order while
+ * they fit (a job whose context or initial data cannot be built is marked
+ * rejected, its message left in grmhd_server_last_error, and the round goes
+ * on); launch the next step of every class with room in its two-step
+ * pipeline (one batched launch sequence per class).  Returns without waiting
+ * for launched work, except that a round with nothing to complete, admit or
+ * launch waits until some class's step completes.  n_pending: queued +
+ * running after the tick. */
 int grmhd_server_tick(grmhd_server* srv, int32_t* n_pending);
 
 int grmhd_server_poll(grmhd_server* srv, int64_t job_id, grmhd_job_info* out);

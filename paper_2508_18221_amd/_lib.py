@@ -40,7 +40,8 @@ class Diag(ctypes.Structure):
                 ("nonfinite", ctypes.c_int64), ("rest_mass", ctypes.c_double),
                 ("entropy", ctypes.c_double), ("max_abs_divB", ctypes.c_double),
                 ("min_alpha", ctypes.c_double), ("max_W", ctypes.c_double),
-                ("ham_l2", ctypes.c_double), ("ham_linf", ctypes.c_double)]
+                ("ham_l2", ctypes.c_double), ("ham_linf", ctypes.c_double),
+                ("mom_l2", ctypes.c_double), ("mom_linf", ctypes.c_double)]
 
 
 class JobInfo(ctypes.Structure):
@@ -79,7 +80,7 @@ SIGNATURES = {
     "grmhd_time": (ctypes.c_double, [_vp]),
     "grmhd_last_error": (ctypes.c_char_p, []),
     "grmhd_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_int32]),
-    "grmhd_con2prim": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "grmhd_con2prim": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "grmhd_profile_step": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.c_int32, _P(ctypes.c_int32)]),
     "grmhd_step_batch": (ctypes.c_int, [_P(_vp), ctypes.c_int32, ctypes.c_int32]),
     "grmhd_set_dt": (ctypes.c_int, [_vp, ctypes.c_double]),

@@ -582,6 +582,45 @@ bool grmhd::same_step_class(const grmhd_grid& ga, const grmhd_phys& pa, grmhd_pr
          pa.glm == pb.glm && (!pa.glm || (pa.glm_ch == pb.glm_ch && pa.glm_tau == pb.glm_tau));
 }
 
+int grmhd::validate_phys(const grmhd_phys& ph, bool need_initial_data, std::string* err) {
+  auto bad = [&](const char* why) {
+    if (err) *err = why;
+    return GRMHD_E_ARG;
+  };
+  if (!(ph.gamma_ad > 1.0) || !(ph.cfl > 0.0) || !(ph.M >= 0.0) || !(fabs(ph.a) <= ph.M))
+    return bad("need Gamma > 1, cfl > 0, M >= 0, |a| <= M");
+  if (ph.id_kind != GRMHD_ID_MICHEL && ph.id_kind != GRMHD_ID_TORUS) return bad("unknown initial-data kind");
+  if (!(ph.rho_floor > 0.0 && ph.p_floor > 0.0 && std::isfinite(ph.rho_floor) && std::isfinite(ph.p_floor) &&
+        std::isfinite(ph.eta)))
+    return bad("need finite floors rho_floor > 0, p_floor > 0 and a finite eta");
+  if ((ph.cowling != 0 && ph.cowling != 1) || (ph.gauge_k0 != 0 && ph.gauge_k0 != 1))
+    return bad("cowling and gauge_k0 must be 0 or 1");
+  if (ph.glm != 0 && ph.glm != 1) return bad("glm must be 0 or 1");
+  if (ph.split != 0 && ph.split != 1) return bad("split must be 0 or 1");
+  if (ph.split && ph.cowling) return bad("the split step needs cowling = 0");
+  if (ph.c2p_damped != 0 && ph.c2p_damped != 1) return bad("c2p_damped must be 0 or 1");
+  if (ph.glm && !(ph.glm_ch > 0.0 && ph.glm_tau > 0.0 && std::isfinite(ph.glm_ch) && std::isfinite(ph.glm_tau)))
+    return bad("GLM needs finite c_h > 0 and tau > 0");
+  if (ph.id_kind == GRMHD_ID_TORUS &&
+      !(ph.tor_r_in > 0.0 && ph.tor_r_max > ph.tor_r_in && ph.tor_rho_max > 0.0 && ph.tor_atm > 0.0 &&
+        ph.tor_loop_cut >= 0.0 && ph.tor_loop_cut < 1.0))
+    return bad("torus needs 0 < r_in < r_max, rho_max > 0, atm > 0, 0 <= loop_cut < 1");
+  if (!need_initial_data) return GRMHD_OK;
+  // existence of the data grmhd_init_state builds (the same conditions it
+  // checks itself, where they do not depend on the grid)
+  if (!(ph.M > 0.0)) return bad("initial data: needs a black hole, M > 0");
+  if (!(ph.pert_amp >= 0.0 && ph.pert_amp < 1.0)) return bad("initial data: needs 0 <= pert_amp < 1");
+  if (!(ph.beta_min > 0.0) || !std::isfinite(ph.beta_min)) return bad("initial data: needs beta_min > 0");
+  if (ph.id_kind == GRMHD_ID_MICHEL) {
+    if (!(ph.rho_c > 0.0) || !std::isfinite(ph.rho_c)) return bad("initial data: Michel flow needs rho_c > 0");
+    // a transonic Michel flow has a positive sonic-point temperature only for
+    // r_c > M (3 Gamma - 2) / (2 (Gamma - 1))
+    if (!(ph.r_c > ph.M * (3.0 * ph.gamma_ad - 2.0) / (2.0 * (ph.gamma_ad - 1.0))) || !std::isfinite(ph.r_c))
+      return bad("initial data: no transonic Michel flow for this r_c (need r_c > M (3 Gamma - 2) / (2 (Gamma - 1)))");
+  }
+  return GRMHD_OK;
+}
+
 int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec, void* dev_resident,
                           void* dev_scratch, void* hip_stream, const Operators* prebuilt, grmhd_ctx** out) {
   int rc = validate_grid(grid);
@@ -591,23 +630,10 @@ int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_
     return fail(GRMHD_E_ARG, "unknown precision");
   if (((uintptr_t)dev_resident & 255) || ((uintptr_t)dev_scratch & 255))
     return fail(GRMHD_E_ARG, "device buffers must be 256-byte aligned");
-  if (!(phys->gamma_ad > 1.0) || !(phys->cfl > 0.0) || !(phys->M >= 0.0) || !(fabs(phys->a) <= phys->M))
-    return fail(GRMHD_E_ARG, "need Gamma > 1, cfl > 0, M >= 0, |a| <= M");
-  if (phys->id_kind != GRMHD_ID_MICHEL && phys->id_kind != GRMHD_ID_TORUS)
-    return fail(GRMHD_E_ARG, "unknown initial-data kind");
-  if (!(phys->rho_floor > 0.0 && phys->p_floor > 0.0 && std::isfinite(phys->rho_floor) &&
-        std::isfinite(phys->p_floor) && std::isfinite(phys->eta)))
-    return fail(GRMHD_E_ARG, "need finite floors rho_floor > 0, p_floor > 0 and a finite eta");
-  if (phys->glm != 0 && phys->glm != 1) return fail(GRMHD_E_ARG, "glm must be 0 or 1");
-  if (phys->split != 0 && phys->split != 1) return fail(GRMHD_E_ARG, "split must be 0 or 1");
-  if (phys->split && phys->cowling) return fail(GRMHD_E_ARG, "the split step needs cowling = 0");
-  if (phys->c2p_damped != 0 && phys->c2p_damped != 1) return fail(GRMHD_E_ARG, "c2p_damped must be 0 or 1");
-  if (phys->glm && !(phys->glm_ch > 0.0 && phys->glm_tau > 0.0))
-    return fail(GRMHD_E_ARG, "GLM needs c_h > 0 and tau > 0");
-  if (phys->id_kind == GRMHD_ID_TORUS &&
-      !(phys->tor_r_in > 0.0 && phys->tor_r_max > phys->tor_r_in && phys->tor_rho_max > 0.0 &&
-        phys->tor_atm > 0.0 && phys->tor_loop_cut >= 0.0 && phys->tor_loop_cut < 1.0))
-    return fail(GRMHD_E_ARG, "torus needs 0 < r_in < r_max, rho_max > 0, atm > 0, 0 <= loop_cut < 1");
+  {
+    std::string why;
+    if (validate_phys(*phys, false, &why)) return fail(GRMHD_E_ARG, why);
+  }
   grmhd_ctx* c = new grmhd_ctx();
   c->grid = *grid;
   c->phys = *phys;
@@ -753,6 +779,16 @@ int grmhd_destroy(grmhd_ctx* c) {
   if (e != hipSuccess) return fail(GRMHD_E_DEVICE, std::string("destroy: ") + hipGetErrorString(e));
   return GRMHD_OK;
 }
+
+}  // extern "C"
+
+void grmhd::destroy_idle_context(grmhd_ctx* c) {
+  if (!c) return;
+  release_streams(c);
+  delete c;
+}
+
+extern "C" {
 
 int grmhd_init_state(grmhd_ctx* c) {
   if (!c) return fail(GRMHD_E_ARG, "null context");
@@ -952,14 +988,25 @@ int grmhd_profile_step(grmhd_ctx* c, int32_t nsteps, double* ms, int32_t nkinds,
 int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
   if (!c || !out) return fail(GRMHD_E_ARG, "null argument");
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state");
-  // con2prim and FP64 derivatives of the current state -> Hamiltonian constraint
-  // (into the accumulator slot, free between steps); then d_i (sqrt(gamma) B^i)
-  // into free first-derivative slots
+  // Exact primitive recovery of the current state into stage scratch (free
+  // between steps: primitives at SC_US, flags at SC_US + 5), started from a
+  // copy of the evolution's warm start, so the warm start and the stored
+  // failure flags of the evolution stay as they are; FP64 derivatives of the
+  // state -> Hamiltonian constraint and momentum-constraint norm (accumulator
+  // slots SC_ACC, SC_ACC + 1); then d_i (sqrt(gamma) B^i) into free
+  // first-derivative slots.
   int rc = GRMHD_OK;
-  HIPCHK(launch_c2p_flux(c->U, c->U, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, single(c), c->stream));
+  const size_t P = c->L.P;
+  double* prim = sf(c, SC_US);
+  double* dfail = sf(c, SC_US + 5);
+  HIPCHK(hipMemcpyAsync(prim, c->prim, 5 * P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  PointParams exact = c->pp;
+  exact.c2p_damped = 0;
+  HIPCHK(launch_c2p_flux(c->U, c->U, prim, dfail, nullptr, c->floors, exact, single(c), c->stream));
   if ((rc = fp64_derivs(c, c->U, single(c), nullptr))) return rc;
   double* H = sf(c, SC_ACC);
-  HIPCHK(launch_ham(c->U, sf(c, SC_D1), c->prim, H, c->pp, c->stream));
+  double* Mn = sf(c, SC_ACC + 1);
+  HIPCHK(launch_ham(c->U, sf(c, SC_D1), H, Mn, c->pp, c->stream));
   Bases B;
   B.b[0] = c->U;
   B.b[1] = c->scr;
@@ -973,12 +1020,13 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     if (e != hipSuccess) return fail(GRMHD_E_DEVICE, hipGetErrorString(e));
   }
   int nb = 0;
-  HIPCHK(launch_diag_partials(c->U, c->prim, c->fail, c->scr, H, c->wr, c->wth, c->phys.gamma_ad, c->pp,
+  HIPCHK(launch_diag_partials(c->U, prim, c->fail, c->scr, H, Mn, c->wr, c->wth, c->phys.gamma_ad, c->pp,
                               c->partials, &nb, c->stream));
   std::vector<double> h((size_t)nb * DIAG_Q);
   HIPCHK(hipMemcpyAsync(h.data(), c->partials, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0, mx4 = 0, mn5 = INFINITY, mx6 = 0, s7 = 0, mx8 = 0, s9 = 0;
+  double s10 = 0, mx11 = 0;
   for (int b = 0; b < nb; ++b) {
     const double* q = &h[(size_t)b * DIAG_Q];
     s0 += q[0];
@@ -991,9 +1039,13 @@ int grmhd_diagnostics(grmhd_ctx* c, grmhd_diag* out) {
     s7 += q[7];
     mx8 = host_nan_max(mx8, q[8]);
     s9 += q[9];
+    s10 += q[10];
+    mx11 = host_nan_max(mx11, q[11]);
   }
   out->ham_l2 = s9 > 0 ? sqrt(s7 / s9) : 0.0;
   out->ham_linf = mx8;
+  out->mom_l2 = s9 > 0 ? sqrt(s10 / s9) : 0.0;
+  out->mom_linf = mx11;
   out->t = c->t;
   out->step = c->step;
   out->rest_mass = s0;
@@ -1029,11 +1081,13 @@ int grmhd_apply_operator(grmhd_ctx* c, int32_t axis, int32_t op, const double* d
   return GRMHD_OK;
 }
 
-int grmhd_con2prim(grmhd_ctx* c, const double* dev_U, double* dev_prim, double* dev_flux) {
+int grmhd_con2prim(grmhd_ctx* c, const double* dev_U, double* dev_prim, double* dev_flux, double* dev_fail) {
   if (!c || !dev_U || !dev_prim) return fail(GRMHD_E_ARG, "null argument");
   // guesses come from the context's last recovery; results also stored there
   HIPCHK(launch_c2p_flux(dev_U, dev_U, c->prim, c->fail, dev_flux, c->floors, c->pp, single(c), c->stream));
   HIPCHK(hipMemcpyAsync(dev_prim, c->prim, 5 * c->L.P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (dev_fail)
+    HIPCHK(hipMemcpyAsync(dev_fail, c->fail, c->L.P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return GRMHD_OK;
 }
 

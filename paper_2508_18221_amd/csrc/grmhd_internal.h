@@ -165,6 +165,18 @@ void build_operators(const grmhd_grid& g, double cfl, Operators* ops);
 bool same_step_class(const grmhd_grid& ga, const grmhd_phys& pa, grmhd_prec qa, const grmhd_grid& gb,
                      const grmhd_phys& pb, grmhd_prec qb);
 
+// Parameter checks of grmhd_create; with need_initial_data also the
+// conditions under which grmhd_init_state can build its data (black hole,
+// perturbation amplitude, field strength, a transonic Michel flow), so that a
+// job can be refused when it is submitted.  GRMHD_OK or GRMHD_E_ARG with *err
+// set.
+int validate_phys(const grmhd_phys& ph, bool need_initial_data, std::string* err);
+
+// Release a context whose work on its stream is known to be complete (its
+// last launch sequence's event has been observed), without waiting for that
+// stream: other contexts may have work queued there.
+void destroy_idle_context(grmhd_ctx* c);
+
 // grmhd_create with the operators of this grid and cfl built beforehand
 // (prebuilt: copied into the context; null: built here).  The job server keeps
 // one set per grid, so admission does not rebuild them.
@@ -225,17 +237,19 @@ hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const doub
 // state from its derivative arrays (FP64 or FP32)
 hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double* R, const PointParams& pp,
                         const JobSet& js, hipStream_t s);
-// Hamiltonian constraint from FP64 derivative arrays into H (P doubles)
-hipError_t launch_ham(const double* U, const double* der, const double* prim, double* H,
-                      const PointParams& pp, hipStream_t s);
+// Hamiltonian constraint H and momentum-constraint norm |M| (P doubles each)
+// from FP64 derivative arrays
+hipError_t launch_ham(const double* U, const double* der, double* H, double* Mn, const PointParams& pp,
+                      hipStream_t s);
 hipError_t launch_k0(const double* U, const double* scr, double* K0, const PointParams& pp,
                      hipStream_t s);
-// Per-block partial reductions for diagnostics: writes nblocks x 8 doubles.
+// Per-block partial reductions for diagnostics: writes nblocks x DIAG_Q doubles.
 // [0] rest mass, [1] entropy, [2] fails, [3] non-finite, [4] max|div B|,
-// [5] min alpha, [6] max W, [7] sum H^2 w, [8] max|H|, [9] sum w
-constexpr int DIAG_Q = 10;
+// [5] min alpha, [6] max W, [7] sum H^2 w, [8] max|H|, [9] sum w,
+// [10] sum |M|^2 w, [11] max |M|
+constexpr int DIAG_Q = 12;
 hipError_t launch_diag_partials(const double* U, const double* prim, const double* fail,
-                                const double* scr, const double* H, const double* wr,
+                                const double* scr, const double* H, const double* Mn, const double* wr,
                                 const double* wth, double gamma_ad, const PointParams& pp,
                                 double* partials, int* nblocks, hipStream_t s);
 int diag_partials_blocks(long long P);

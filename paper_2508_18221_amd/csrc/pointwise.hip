@@ -7,9 +7,10 @@
 //                 (-div + sqrt(gamma) S, GLM terms), boundary freeze, RK4 stage
 //                 update (or the split step's Euler update of the spacetime)
 //   k_rhs_fixed : the Valencia RHS and RK4 stage on a fixed background
-//   k_ham, k_k0 : Hamiltonian constraint; static 1+log source
+//   k_ham, k_k0 : Hamiltonian and momentum constraints; static 1+log source
 //                 K0 = K - beta^k d_k alpha/(2 alpha)
 //   k_diag      : per-block partial sums / extrema for diagnostics
+//                 (wavefront swizzle reductions)
 //
 // Paper: Results, "GRMHD Conservative Form" (conserved variables, fluxes,
 // Lorentz factor, magnetic four-vector, source term); Methods, "The Primitive
@@ -82,6 +83,14 @@ struct C2POut {
   int fail;
 };
 
+// Iteration budget of the safeguarded Newton recovery.  From a warm start
+// Newton converges in a handful of steps; each step that leaves the bracket
+// is replaced by a bisection.  A point neither converged nor reduced to a
+// bracket of adjacent doubles after this many iterations is flagged and
+// takes the atmosphere (the same policy as the oracle's bisection, which
+// flags a point left unresolved by its own budget).
+constexpr int C2P_MAXIT = 200;
+
 __device__ C2POut con2prim(double D, const double* S, double tau, const double* B, const Sym& gam,
                            const Sym& gamu, double G, double gm1g, double rho_fl, double p_fl,
                            double zguess) {
@@ -118,7 +127,10 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
   if (!upper) bad = true;
   double Z = (zguess > lo && zguess < hi) ? zguess : 0.5 * (lo + hi);
   if (!bad) {
-    for (int it = 0; it < 200; ++it) {
+    // a point that neither converges nor collapses its bracket within the
+    // iteration budget is not a recovered state: it takes the failure policy
+    bool done = false;
+    for (int it = 0; it < C2P_MAXIT && !done; ++it) {
       double zn;
       if (!resid(Z, f, fp)) {
         lo = Z;
@@ -132,16 +144,19 @@ __device__ C2POut con2prim(double D, const double* S, double tau, const double* 
         // bracket end, which must not trigger a bisection)
         if (fabs(zn - Z) <= 1e-12 * zn) {
           Z = zn;
+          done = true;
           break;
         }
         if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
       }
       if (!(zn > lo && zn < hi)) {  // bracket collapsed onto adjacent doubles
         Z = hi;
+        done = true;
         break;
       }
       Z = zn;
     }
+    if (!done) bad = true;
   }
   double vl[3];
   const double iZ = 1.0 / Z, ia = 1.0 / (Z + B2);
@@ -996,10 +1011,14 @@ __global__ __launch_bounds__(256) void k_ricci(const double* __restrict__ Us, co
 }
 
 // ---------------------------------------------------------------------------
-// Hamiltonian constraint H = e^{-4 phi} gt^ij R_ij + 2/3 K^2 - A_ij A^ij - 16 pi E
-// with E = tau + D, from FP64 derivative arrays.
+// Constraints from FP64 derivative arrays:
+//   Hamiltonian H = e^{-4 phi} gt^ij R_ij + 2/3 K^2 - A_ij A^ij - 16 pi E, E = tau + D;
+//   momentum    M_i = Dt_j A^j_i + 6 A^j_i d_j phi - 2/3 d_i K - 8 pi S_i
+//               (A^j_i = gt^jk At_ki, Dt the covariant derivative of gt,
+//               S_i the undensitised momentum), written as its norm
+//               |M| = sqrt(e^{-4 phi} gt^ij M_i M_j).
 __global__ __launch_bounds__(256) void k_ham(const double* __restrict__ U, const double* __restrict__ der,
-                                             double* __restrict__ H, PointParams pp) {
+                                             double* __restrict__ H, double* __restrict__ Mn, PointParams pp) {
   const long long P = pp.P;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= P) return;
@@ -1051,6 +1070,44 @@ __global__ __launch_bounds__(256) void k_ham(const double* __restrict__ U, const
     }
   const double E = (LU(28) + LU(24)) / sqrtg;
   H[idx] = em4 * trR + (2.0 / 3.0) * K * K - AA - 16.0 * PI * E;
+  // momentum constraint: d_j A^j_i = (d_j gt^jk) At_ki + gt^jk d_j At_ki with
+  // d_j gt^jk = -gt^kb (gt^ja d_j gt_ab)
+  double w[3], v[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) t += gtu(j, a) * dgt[j][S6(a, b)];
+    w[b] = t;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = -(gtu(k, 0) * w[0] + gtu(k, 1) * w[1] + gtu(k, 2) * w[2]);
+  double trG[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) trG[k] = Gu[0][S6(0, k)] + Gu[1][S6(1, k)] + Gu[2][S6(2, k)];
+  // A^j_i = Amix[i][j] (At and gt^-1 symmetric)
+  double Mi[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m += v[k] * At(k, i) + trG[k] * Amix[i][k];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) m += gtu(j, k) * LS(21 * j + 7 + S6(k, i)) - Gu[k][S6(j, i)] * Amix[k][j];
+      m += 6.0 * Amix[i][j] * dphi[j];
+    }
+    Mi[i] = m - (2.0 / 3.0) * LS(21 * i + 13) - 8.0 * PI * LU(25 + i) / sqrtg;
+  }
+  double mm = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) mm += gtu(i, j) * Mi[i] * Mi[j];
+  Mn[idx] = sqrt(em4 * mm);
 #undef LS
 #undef LU
 }
@@ -1137,11 +1194,16 @@ __global__ __launch_bounds__(256) void k_k0(const double* __restrict__ U, const 
 }
 
 // ---------------------------------------------------------------------------
-// Diagnostics partials per block (fixed-order tree; no floating-point atomics),
-// DIAG_Q values per block: [0] sum sqrt(g) D w, [1] sum rho s sqrt(g) w,
-// [2] fails, [3] non-finite count, [4] max |div B| (scratch first-derivative
-// slots of sqrt(g) B^a), [5] min alpha, [6] max W, [7] sum H^2 w, [8] max |H|,
-// [9] sum w.
+// Diagnostics partials per block, DIAG_Q values per block: [0] sum sqrt(g) D w,
+// [1] sum rho s sqrt(g) w, [2] fails, [3] non-finite count, [4] max |div B|
+// (scratch first-derivative slots of sqrt(g) B^a), [5] min alpha, [6] max W,
+// [7] sum H^2 w, [8] max |H|, [9] sum w, [10] sum |M|^2 w, [11] max |M|.
+// Each thread accumulates a grid-stride set of points; each wavefront then
+// reduces its 64 lanes with cross-lane swizzles (xor butterfly within each
+// half-wave, then the two halves read from lanes 0 and 32), the four
+// wavefronts of a block are combined in a fixed order by one thread, and the
+// host adds the block partials in block order.  No floating-point atomics: the
+// result is the same on every run and for a job alone or in a batch.
 constexpr int DIAG_THREADS = 256;
 
 // Max / min that keep a NaN operand (fmax/fmin drop it), so that a state gone
@@ -1149,17 +1211,48 @@ constexpr int DIAG_THREADS = 256;
 __device__ __forceinline__ double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
 __device__ __forceinline__ double nan_min(double a, double b) { return (a != a || a < b) ? a : b; }
 
+// The value of lane (l xor MASK) within each 32-lane half (ds_swizzle bit
+// mode: and-mask 0x1f, or-mask 0, xor-mask MASK).
+template <int MASK>
+__device__ __forceinline__ double swizzle_xor(double v) {
+  static_assert(MASK > 0 && MASK < 32, "xor mask within a half-wave");
+  constexpr int pattern = (MASK << 10) | 0x1f;
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pattern);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pattern);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Reduction of one value over the 64 lanes of a wavefront (all lanes
+// active); op is commutative, so both lanes of a pair hold the same value.
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, swizzle_xor<1>(v));
+  v = op(v, swizzle_xor<2>(v));
+  v = op(v, swizzle_xor<4>(v));
+  v = op(v, swizzle_xor<8>(v));
+  v = op(v, swizzle_xor<16>(v));
+  return op(read_lane(v, 0), read_lane(v, 32));
+}
+
 __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict__ U,
                                                        const double* __restrict__ prim,
                                                        const double* __restrict__ fail,
                                                        const double* __restrict__ scr,
                                                        const double* __restrict__ H,
+                                                       const double* __restrict__ Mn,
                                                        const double* __restrict__ wr,
                                                        const double* __restrict__ wth, double G,
                                                        PointParams pp, double* __restrict__ partials) {
-  __shared__ double sh[DIAG_Q][DIAG_THREADS];
+  constexpr int NW = DIAG_THREADS / 64;
+  __shared__ double sh[NW][DIAG_Q];
   const long long P = pp.P;
-  double v[DIAG_Q] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0};
+  double v[DIAG_Q] = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (long long idx = (long long)blockIdx.x * DIAG_THREADS + threadIdx.x; idx < P;
        idx += (long long)gridDim.x * DIAG_THREADS) {
     const int j = (int)(idx % pp.nr), k = (int)((idx / pp.nr) % pp.nth);
@@ -1189,23 +1282,35 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag(const double* __restrict_
     v[7] += h * h * w;
     v[8] = nan_max(v[8], fabs(h));
     v[9] += w;
+    const double m = Mn[idx];
+    v[10] += m * m * w;
+    v[11] = nan_max(v[11], m);
   }
-  for (int q = 0; q < DIAG_Q; ++q) sh[q][threadIdx.x] = v[q];
+  auto add = [](double a, double b) { return a + b; };
+  auto mx = [](double a, double b) { return nan_max(a, b); };
+  auto mn = [](double a, double b) { return nan_min(a, b); };
+  double r[DIAG_Q];
+#pragma unroll
+  for (int q = 0; q < DIAG_Q; ++q) {
+    if (q == 5) r[q] = wave_reduce(v[q], mn);
+    else if (q == 4 || q == 6 || q == 8 || q == 11) r[q] = wave_reduce(v[q], mx);
+    else r[q] = wave_reduce(v[q], add);
+  }
+  const int wave = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < DIAG_Q; ++q) sh[wave][q] = r[q];
   __syncthreads();
-  for (int half = DIAG_THREADS / 2; half > 0; half >>= 1) {
-    if ((int)threadIdx.x < half) {
-      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + half];
-      sh[4][threadIdx.x] = nan_max(sh[4][threadIdx.x], sh[4][threadIdx.x + half]);
-      sh[5][threadIdx.x] = nan_min(sh[5][threadIdx.x], sh[5][threadIdx.x + half]);
-      sh[6][threadIdx.x] = nan_max(sh[6][threadIdx.x], sh[6][threadIdx.x + half]);
-      sh[7][threadIdx.x] += sh[7][threadIdx.x + half];
-      sh[8][threadIdx.x] = nan_max(sh[8][threadIdx.x], sh[8][threadIdx.x + half]);
-      sh[9][threadIdx.x] += sh[9][threadIdx.x + half];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0)
-    for (int q = 0; q < DIAG_Q; ++q) partials[(size_t)blockIdx.x * DIAG_Q + q] = sh[q][0];
+#pragma unroll
+    for (int q = 0; q < DIAG_Q; ++q) {
+      double t = sh[0][q];
+      for (int w2 = 1; w2 < NW; ++w2) {
+        const double u = sh[w2][q];
+        t = (q == 5) ? nan_min(t, u) : (q == 4 || q == 6 || q == 8 || q == 11) ? nan_max(t, u) : t + u;
+      }
+      partials[(size_t)blockIdx.x * DIAG_Q + q] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,10 +1365,9 @@ hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_ham(const double* U, const double* der, const double* prim, double* H,
-                      const PointParams& pp, hipStream_t s) {
-  (void)prim;
-  hipLaunchKernelGGL(k_ham, dim3(nblk(pp.P)), dim3(256), 0, s, U, der, H, pp);
+hipError_t launch_ham(const double* U, const double* der, double* H, double* Mn, const PointParams& pp,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_ham, dim3(nblk(pp.P)), dim3(256), 0, s, U, der, H, Mn, pp);
   return hipGetLastError();
 }
 
@@ -1286,12 +1390,12 @@ int diag_partials_blocks(long long P) {
 }
 
 hipError_t launch_diag_partials(const double* U, const double* prim, const double* fail,
-                                const double* scr, const double* H, const double* wr, const double* wth,
-                                double gamma_ad, const PointParams& pp, double* partials, int* nblocks,
-                                hipStream_t s) {
+                                const double* scr, const double* H, const double* Mn, const double* wr,
+                                const double* wth, double gamma_ad, const PointParams& pp, double* partials,
+                                int* nblocks, hipStream_t s) {
   const int nb = diag_partials_blocks(pp.P);
   *nblocks = nb;
-  hipLaunchKernelGGL(k_diag, dim3(nb), dim3(DIAG_THREADS), 0, s, U, prim, fail, scr, H, wr, wth, gamma_ad,
+  hipLaunchKernelGGL(k_diag, dim3(nb), dim3(DIAG_THREADS), 0, s, U, prim, fail, scr, H, Mn, wr, wth, gamma_ad,
                      pp, partials);
   return hipGetLastError();
 }

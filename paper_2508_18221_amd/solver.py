@@ -17,7 +17,7 @@ def make_grid(nr, nth, nph, r_in=1.8, r_out=20.0, th_min=0.05, th_max=np.pi - 0.
 
 def make_phys(M=1.0, a=0.5, gamma_ad=4.0 / 3.0, cfl=0.25, eta=2.0, cowling=False, gauge_k0=True,
               r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, seed=1, rho_floor=1e-20, p_floor=1e-24,
-              id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-6,
+              id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-2,
               tor_loop_cut=0.2, glm=False, glm_ch=1.0, glm_tau=2.0, split=False, c2p="exact"):
     kind = {"michel": 0, "torus": 1}[id_kind]
     return Phys(M, a, gamma_ad, cfl, eta, int(cowling), int(gauge_k0), r_c, rho_c, beta_min,
@@ -113,9 +113,10 @@ class Solver:
         nf = inp.numel() // self.P
         check(self.lib.grmhd_apply_operator(self.ctx, int(axis), int(op), _ptr(inp), _ptr(out), nf))
 
-    def con2prim(self, U_dev, prim_out, flux_out=None):
+    def con2prim(self, U_dev, prim_out, flux_out=None, fail_out=None):
         check(self.lib.grmhd_con2prim(self.ctx, _ptr(U_dev), _ptr(prim_out),
-                                      _ptr(flux_out) if flux_out is not None else None))
+                                      _ptr(flux_out) if flux_out is not None else None,
+                                      _ptr(fail_out) if fail_out is not None else None))
 
     def profile_step(self, nsteps=1):
         """Advance nsteps RK4 steps, returning {launch kind: (avg ms, count)}
