@@ -1,22 +1,34 @@
 // Continuous-batching job server for evolution jobs (the served form).
 //
 // Jobs (grid, physics, precision, end time) are submitted as they arrive and
-// wait in a FIFO queue.  Every tick:
-//   1. admission: queued jobs are placed, in arrival order, into the caller's
+// wait in a FIFO queue; a job whose parameters admit no initial data is
+// refused at submission.  Jobs of one grid class (grid sizes, precision,
+// kernel parameters: grmhd::same_step_class) advance together, one launch per
+// kernel for the whole class (grmhd_step_batch), each class on a stream of
+// its own.  Classes do not wait for one another: every tick
+//   1. completion: each class's launched RK4 steps are checked with their
+//      events (hipEventQuery); a completed step counts for the jobs it
+//      carried, and jobs at their end time retire (latency = completion
+//      minus arrival on the server clock; optionally the final state is kept
+//      on the host) and free their block;
+//   2. admission: queued jobs are placed, in arrival order, into the caller's
 //      device arena (first fit, 256-byte aligned blocks holding the job's
 //      resident and scratch buffers) as long as they fit the budget; an
-//      admitted job gets its context, initial data and a time step
-//      dt = T / ceil(T / dt_CFL) so that it ends exactly at T;
-//   2. one RK4 step for every running job: jobs of one grid class
-//      (grid sizes, precision, kernel parameters) advance together, one
-//      launch per kernel for the whole class (grmhd_step_batch), each class
-//      on its own stream so that classes overlap on the device;
-//   3. retirement: finished jobs record their latency (completion minus
-//      arrival on the server clock), optionally keep their final state on
-//      the host, and free their block, so queued jobs can enter next tick.
-// The server uses only the public C-ABI of the library.  With a null arena it
-// runs "dry": no device work, each step completes at once; this exercises
-// admission, budget and latency bookkeeping on a machine without a GPU.
+//      admitted job gets its context and initial data on the server's
+//      admission stream, a time step dt = T / ceil(T / dt_CFL) so that it
+//      ends exactly at T, and then joins its class's stream; a job whose
+//      admission fails is marked rejected and the tick goes on;
+//   3. launch: a class with fewer than two steps in flight launches the next
+//      RK4 step of its jobs that still have steps to go (so the device always
+//      holds the following step of a class while the host handles the
+//      completion of the current one), and records an event after it.
+// A tick that completes, admits and launches nothing while work is in flight
+// waits until some class's step completes.  Small-grid classes therefore run
+// at their own step rate, not at the rate of the largest class.  The server
+// uses the public C-ABI of the library plus two internal calls (context
+// creation with shared operators, release of an idle context).  With a null
+// arena it runs "dry": no device work, each step completes at once; this
+// exercises admission, budget and latency bookkeeping without a GPU.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -26,6 +38,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "grmhd.h"
@@ -53,11 +66,22 @@ struct Job {
   size_t off = 0, bytes = 0, res_bytes = 0;
   grmhd_ctx* ctx = nullptr;
   int64_t steps_total = 0, steps_done = 0;
+  int64_t steps_launched = 0;  // steps done + steps in flight
   double dt = 0.0;
   double t_arrival = 0.0, t_admit = -1.0, t_done = -1.0;
   std::vector<double> result;
   int cls = -1;
 };
+
+// One launched RK4 step of a class: the event recorded after it and the jobs
+// it carries.
+struct Launch {
+  hipEvent_t ev = nullptr;
+  std::vector<size_t> jobs;
+};
+
+// Steps a class may have in flight at once.
+constexpr int DEPTH = 2;
 
 // First-fit allocator over [0, size) with coalescing frees.
 struct Arena {
@@ -113,12 +137,19 @@ struct grmhd_server {
   bool dry;
   int max_batch;
   hipStream_t user_stream;
+  hipStream_t admit_stream = nullptr;  // initial data of admitted jobs
+  bool own_admit = false;
   Arena arena;
   std::vector<Job> jobs;
   std::deque<size_t> queue;  // indices into jobs
-  std::vector<Job> classes;  // one representative per grid class
-  std::vector<hipStream_t> streams;
-  std::vector<bool> own_stream;
+  struct Class {
+    Job rep;                   // representative job (the class predicate)
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::deque<Launch> inflight;
+    std::vector<hipEvent_t> spare;  // events of completed launches, reused
+  };
+  std::vector<Class> classes;
   // operators per (grid, cfl), built at the first submission of that grid and
   // shared by the time step and every context created for it
   struct OpsEntry {
@@ -128,10 +159,16 @@ struct grmhd_server {
   };
   std::vector<OpsEntry> ops_cache;
   std::chrono::steady_clock::time_point t0;
-  double busy = 0.0;
+  double busy = 0.0;          // seconds with device work in flight
+  double busy_since = -1.0;   // start of the current in-flight period
   double first_submit = -1.0;
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  int inflight_total() const {
+    int n = 0;
+    for (const auto& c : classes) n += (int)c.inflight.size();
+    return n;
   }
 };
 
@@ -152,6 +189,11 @@ int grmhd_server_create(void* dev_arena, size_t arena_bytes, int32_t max_batch, 
   s->max_batch = max_batch;
   s->user_stream = (hipStream_t)hip_stream;
   s->arena.init(arena_bytes);
+  if (!s->dry) {
+    hipStream_t st = nullptr;
+    s->own_admit = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    s->admit_stream = s->own_admit ? st : s->user_stream;
+  }
   s->t0 = std::chrono::steady_clock::now();
   *out = s;
   return GRMHD_OK;
@@ -159,10 +201,17 @@ int grmhd_server_create(void* dev_arena, size_t arena_bytes, int32_t max_batch, 
 
 int grmhd_server_destroy(grmhd_server* s) {
   if (!s) return GRMHD_OK;
+  for (auto& c : s->classes)
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
   for (auto& j : s->jobs)
-    if (j.ctx) grmhd_destroy(j.ctx);
-  for (size_t i = 0; i < s->streams.size(); ++i)
-    if (s->own_stream[i]) (void)hipStreamDestroy(s->streams[i]);
+    if (j.ctx) grmhd::destroy_idle_context(j.ctx);
+  for (auto& c : s->classes) {
+    for (auto& l : c.inflight)
+      if (l.ev) (void)hipEventDestroy(l.ev);
+    for (auto ev : c.spare) (void)hipEventDestroy(ev);
+    if (c.own_stream) (void)hipStreamDestroy(c.stream);
+  }
+  if (s->own_admit) (void)hipStreamDestroy(s->admit_stream);
   delete s;
   return GRMHD_OK;
 }
@@ -172,11 +221,14 @@ double grmhd_server_clock(const grmhd_server* s) { return s ? s->now() : NAN; }
 int grmhd_server_submit(grmhd_server* s, const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec,
                         double t_end, int32_t keep_state, int64_t* job_id) {
   if (!s || !grid || !phys || !job_id) return sfail(GRMHD_E_ARG, "null argument");
-  if (!(t_end > 0.0)) return sfail(GRMHD_E_ARG, "t_end > 0");
+  if (!(t_end > 0.0) || !std::isfinite(t_end)) return sfail(GRMHD_E_ARG, "job rejected: need a finite t_end > 0");
   size_t res = 0, scr = 0;
   int rc = grmhd_query_bytes(grid, prec, &res, &scr);
   if (rc) return sfail(rc, std::string("job rejected: ") + grmhd_last_error());
-  if (!(phys->cfl > 0.0)) return sfail(GRMHD_E_ARG, "job rejected: cfl > 0");
+  {
+    std::string why;
+    if (grmhd::validate_phys(*phys, true, &why)) return sfail(GRMHD_E_ARG, "job rejected: " + why);
+  }
   const double dt = operators_for(s, *grid, phys->cfl)->dt;  // grid validated by the size query
   Job j;
   j.id = (int64_t)s->jobs.size();
@@ -224,87 +276,174 @@ static const grmhd::Operators* operators_for(grmhd_server* s, const grmhd_grid& 
 
 static int class_of(grmhd_server* s, const Job& j) {
   for (size_t c = 0; c < s->classes.size(); ++c)
-    if (same_class(s->classes[c], j)) return (int)c;
-  s->classes.push_back(j);
+    if (same_class(s->classes[c].rep, j)) return (int)c;
+  grmhd_server::Class c;
+  c.rep = j;
   if (!s->dry) {
     hipStream_t st = nullptr;
-    const bool own = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
-    s->streams.push_back(own ? st : s->user_stream);
-    s->own_stream.push_back(own);
+    c.own_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    c.stream = c.own_stream ? st : s->user_stream;
   }
+  s->classes.push_back(std::move(c));
   return (int)s->classes.size() - 1;
 }
 
-int grmhd_server_tick(grmhd_server* s, int32_t* n_pending) {
-  if (!s) return sfail(GRMHD_E_ARG, "null server");
-  const double tin = s->now();
-  // 1. admission in arrival order while the head job fits
+// A job at its end time: keep its state if asked, release its context and
+// block.  Its class has no step of it in flight.
+static int retire(grmhd_server* s, Job& j, double t) {
+  if (!s->dry) {
+    if (j.keep) {
+      const size_t P = (size_t)j.grid.nr * j.grid.nth * j.grid.nph;
+      j.result.resize((size_t)(j.phys.glm ? GRMHD_NFIELDS_GLM : GRMHD_NFIELDS) * P);  // psi last with GLM
+      double* dU = nullptr;
+      int rc = grmhd_state_ptr(j.ctx, &dU, nullptr);
+      if (rc) return sfail(rc, grmhd_last_error());
+      // the class stream may already hold the next step of other jobs: copy
+      // on the admission stream (the job's last step has completed)
+      hipError_t e = hipMemcpyAsync(j.result.data(), dU, j.result.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, s->admit_stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->admit_stream);
+      if (e != hipSuccess) return sfail(GRMHD_E_DEVICE, std::string("result copy: ") + hipGetErrorString(e));
+    }
+    grmhd::destroy_idle_context(j.ctx);
+    j.ctx = nullptr;
+  }
+  s->arena.release(j.off, j.bytes);
+  j.state = 2;
+  j.t_done = t;
+  return GRMHD_OK;
+}
+
+// Count the completed launches of every class (the oldest first, in stream
+// order) and retire jobs that reached their end time.
+static int complete(grmhd_server* s, bool* progress) {
+  for (auto& c : s->classes) {
+    while (!c.inflight.empty()) {
+      Launch& l = c.inflight.front();
+      if (!s->dry) {
+        const hipError_t q = hipEventQuery(l.ev);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return sfail(GRMHD_E_DEVICE, std::string("class step: ") + hipGetErrorString(q));
+      }
+      const double t = s->now();
+      for (size_t i : l.jobs) {
+        Job& j = s->jobs[i];
+        j.steps_done += 1;
+        if (j.steps_done >= j.steps_total) {
+          int rc = retire(s, j, t);
+          if (rc) return rc;
+        }
+      }
+      if (l.ev) c.spare.push_back(l.ev);
+      c.inflight.pop_front();
+      *progress = true;
+    }
+  }
+  if (s->busy_since >= 0.0 && s->inflight_total() == 0) {
+    s->busy += s->now() - s->busy_since;
+    s->busy_since = -1.0;
+  }
+  return GRMHD_OK;
+}
+
+// Admission in arrival order while the head job fits.  A job whose context
+// or initial data cannot be built is rejected (its message is the server's
+// last error); the others go on.
+static void admit(grmhd_server* s, bool* progress) {
   while (!s->queue.empty()) {
     Job& j = s->jobs[s->queue.front()];
     size_t off = 0;
     if (!s->arena.alloc(j.bytes, &off)) break;
+    s->queue.pop_front();
+    *progress = true;
     j.off = off;
     j.cls = class_of(s, j);
     if (!s->dry) {
       char* res = s->arena_base + off;
       char* scr = res + j.res_bytes;
-      int rc = grmhd::create_context(&j.grid, &j.phys, j.prec, res, scr, s->streams[j.cls],
+      int rc = grmhd::create_context(&j.grid, &j.phys, j.prec, res, scr, s->admit_stream,
                                      operators_for(s, j.grid, j.phys.cfl), &j.ctx);
-      if (!rc) rc = grmhd_init_state(j.ctx);
+      if (!rc) rc = grmhd_init_state(j.ctx);  // syncs the admission stream
       if (!rc) rc = grmhd_set_dt(j.ctx, j.dt);
+      if (!rc) rc = grmhd_set_stream(j.ctx, s->classes[j.cls].stream);
       if (rc) {
-        const std::string msg = grmhd_last_error();
-        if (j.ctx) grmhd_destroy(j.ctx);
+        g_serr = "job " + std::to_string(j.id) + " rejected at admission: " + grmhd_last_error();
+        if (j.ctx) grmhd::destroy_idle_context(j.ctx);
         j.ctx = nullptr;
         s->arena.release(off, j.bytes);
         j.state = 3;
-        s->queue.pop_front();
-        return sfail(rc, "admission failed: " + msg);
+        continue;
       }
     }
     j.state = 1;
     j.t_admit = s->now();
-    s->queue.pop_front();
   }
-  // 2. one RK4 step per running job, batched per grid class
-  std::vector<std::vector<size_t>> by_class(s->classes.size());
-  for (size_t i = 0; i < s->jobs.size(); ++i)
-    if (s->jobs[i].state == 1) by_class[s->jobs[i].cls].push_back(i);
-  for (size_t c = 0; c < by_class.size(); ++c) {
-    const auto& ids = by_class[c];
-    for (size_t b = 0; b < ids.size(); b += (size_t)s->max_batch) {
-      const size_t m = std::min(ids.size() - b, (size_t)s->max_batch);
+}
+
+// Launch the next step of every class with room in its pipeline.
+static int launch(grmhd_server* s, bool* progress) {
+  for (size_t ci = 0; ci < s->classes.size(); ++ci) {
+    auto& c = s->classes[ci];
+    const int depth = s->dry ? 1 : DEPTH;  // a dry step completes within its tick
+    while ((int)c.inflight.size() < depth) {
+      std::vector<size_t> ids;
+      for (size_t i = 0; i < s->jobs.size(); ++i) {
+        const Job& j = s->jobs[i];
+        if (j.state == 1 && j.cls == (int)ci && j.steps_launched < j.steps_total) ids.push_back(i);
+      }
+      if (ids.empty()) break;
+      Launch l;
+      l.jobs = ids;
       if (!s->dry) {
-        std::vector<grmhd_ctx*> ctxs(m);
-        for (size_t q = 0; q < m; ++q) ctxs[q] = s->jobs[ids[b + q]].ctx;
-        int rc = grmhd_step_batch(ctxs.data(), (int32_t)m, 1);
-        if (rc) return sfail(rc, std::string("batched step failed: ") + grmhd_last_error());
+        for (size_t b = 0; b < ids.size(); b += (size_t)s->max_batch) {
+          const size_t m = std::min(ids.size() - b, (size_t)s->max_batch);
+          std::vector<grmhd_ctx*> ctxs(m);
+          for (size_t q = 0; q < m; ++q) ctxs[q] = s->jobs[ids[b + q]].ctx;
+          int rc = grmhd_step_batch(ctxs.data(), (int32_t)m, 1);
+          if (rc) return sfail(rc, std::string("batched step failed: ") + grmhd_last_error());
+        }
+        if (!c.spare.empty()) {
+          l.ev = c.spare.back();
+          c.spare.pop_back();
+        } else if (hipEventCreateWithFlags(&l.ev, hipEventDisableTiming) != hipSuccess) {
+          return sfail(GRMHD_E_DEVICE, "event create failed");
+        }
+        if (hipEventRecord(l.ev, c.stream) != hipSuccess) return sfail(GRMHD_E_DEVICE, "event record failed");
       }
-      for (size_t q = 0; q < m; ++q) s->jobs[ids[b + q]].steps_done += 1;
+      for (size_t i : ids) s->jobs[i].steps_launched += 1;
+      if (s->busy_since < 0.0) s->busy_since = s->now();
+      c.inflight.push_back(std::move(l));
+      *progress = true;
     }
   }
-  if (!s->dry)
-    for (auto st : s->streams)
-      if (hipStreamSynchronize(st) != hipSuccess) return sfail(GRMHD_E_DEVICE, "stream synchronize failed");
-  // 3. retirement
-  const double tdone = s->now();
-  for (auto& j : s->jobs) {
-    if (j.state != 1 || j.steps_done < j.steps_total) continue;
-    if (!s->dry) {
-      if (j.keep) {
-        const size_t P = (size_t)j.grid.nr * j.grid.nth * j.grid.nph;
-        j.result.resize((size_t)(j.phys.glm ? GRMHD_NFIELDS_GLM : GRMHD_NFIELDS) * P);  // psi last with GLM
-        int rc = grmhd_get_state(j.ctx, j.result.data(), j.result.size(), nullptr);
-        if (rc) return sfail(rc, grmhd_last_error());
-      }
-      grmhd_destroy(j.ctx);
-      j.ctx = nullptr;
+  return GRMHD_OK;
+}
+
+int grmhd_server_tick(grmhd_server* s, int32_t* n_pending) {
+  if (!s) return sfail(GRMHD_E_ARG, "null server");
+  for (int pass = 0; pass < 2; ++pass) {
+    bool progress = false;
+    int rc = complete(s, &progress);
+    if (rc) return rc;
+    admit(s, &progress);
+    if ((rc = launch(s, &progress))) return rc;
+    if (s->dry) {  // a dry step completes at once
+      if ((rc = complete(s, &progress))) return rc;
+      break;
     }
-    s->arena.release(j.off, j.bytes);
-    j.state = 2;
-    j.t_done = tdone;
+    if (progress || s->inflight_total() == 0) break;
+    // nothing to do until some class's step completes: wait for that
+    for (;;) {
+      bool any = false;
+      for (auto& c : s->classes)
+        if (!c.inflight.empty()) {
+          const hipError_t q = hipEventQuery(c.inflight.front().ev);
+          if (q != hipErrorNotReady) any = true;
+        }
+      if (any) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
   }
-  s->busy += s->now() - tin;
   if (n_pending) {
     int32_t n = 0;
     for (auto& j : s->jobs) n += (j.state == 0 || j.state == 1);
@@ -312,7 +451,6 @@ int grmhd_server_tick(grmhd_server* s, int32_t* n_pending) {
   }
   return GRMHD_OK;
 }
-
 int grmhd_server_poll(grmhd_server* s, int64_t id, grmhd_job_info* out) {
   if (!s || !out || id < 0 || id >= (int64_t)s->jobs.size()) return sfail(GRMHD_E_ARG, "unknown job");
   const Job& j = s->jobs[id];

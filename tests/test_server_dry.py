@@ -96,3 +96,34 @@ def test_invalid_submissions():
         srv.submit(make_grid(16, 16, 15), make_phys(), 1.0)
     with pytest.raises(Exception):
         srv.submit(make_grid(16, 16, 16), make_phys(), -1.0)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(a=1.5),                                  # |a| > M
+    dict(M=0.0, a=0.0),                           # no black hole: no initial data
+    dict(gamma_ad=1.0),                           # Gamma <= 1
+    dict(r_c=1.0),                                # inside the transonic Michel bound
+    dict(beta_min=0.0),                           # no field normalisation
+    dict(pert_amp=1.0),                           # perturbation outside [0, 1)
+    dict(rho_c=0.0),
+    dict(id_kind="torus", tor_r_in=12.0, tor_r_max=6.0),
+    dict(glm=True, glm_tau=0.0),
+    dict(split=True, cowling=True),
+    dict(cfl=0.0),
+])
+def test_jobs_without_initial_data_are_refused_at_submission(bad):
+    """A job whose parameters grmhd_create would refuse, or for which no
+    initial data exist, is refused by submit (not queued), so it can never
+    fail later inside a tick; the server keeps serving the valid jobs."""
+    from paper_2508_18221_amd._lib import GrmhdError
+    g = make_grid(16, 16, 16)
+    srv = Server(budget=4 * footprint(g), dry=True)
+    ok1 = srv.submit(g, make_phys(), 2 * dt_of(g))
+    with pytest.raises(GrmhdError, match="rejected"):
+        srv.submit(g, make_phys(**bad), 1.0)
+    ok2 = srv.submit(g, make_phys(seed=3), dt_of(g))
+    while srv.tick() > 0:
+        pass
+    assert srv.poll(ok1)["state"] == 2 and srv.poll(ok2)["state"] == 2
+    st = srv.stats()
+    assert st["submitted"] == 2 and st["completed"] == 2 and st["queued"] == 0
