@@ -785,7 +785,9 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
   if (axis == 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad) {
     // pipelined form of the r axis: the line count a multiple of the tile's
     const int tlines = 2048 / N;
-    const long long all = (long long)(inner / tlines) * tl.n * js.n;
+    // the kernel and its tiles per workgroup follow from one job's tiles, so
+    // a job's arithmetic is the same alone and in a batch of any size
+    const long long all = (long long)(inner / tlines) * tl.n;
     if (inner % tlines == 0 && all >= 2048) {
       const int ntiles = inner / tlines;
       const int tpb = (int)std::min(8LL, all / 1024);
@@ -805,8 +807,10 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     // copy-ahead form: inner a multiple of the tile width
     const int nw = (Hpad == 48 || Hpad == 96) ? 6 : 4;
     const int tc = 16 * nw / (Hpad / 16), rows = 1024 / (8 * tc);
-    const long long all = (long long)(inner / tc) * outer * tl.n * js.n;  // tiles of the launch
-    // small launches (a few tiles per workgroup) keep the one-tile kernel
+    const long long all = (long long)(inner / tc) * outer * tl.n;  // tiles of one job's launch
+    // small launches (a few tiles per workgroup) keep the one-tile kernel;
+    // the choice and the tiles per workgroup follow from one job's tiles, so
+    // a job's arithmetic is the same alone and in a batch of any size
     if (inner % tc == 0 && all >= 2048) {
       const int ncb = inner / tc, ntiles = ncb * outer;
       const int bufbytes = (N / rows) * PIPE_CH;

@@ -722,7 +722,9 @@ hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl,
       ncb = inner / tc;
       ntiles = ncb * outer;
     }
-    const long long all = (long long)ntiles * tl.n * js.n;
+    // the kernel and its tiles per workgroup follow from one job's tiles, so
+    // a job's arithmetic is the same alone and in a batch of any size
+    const long long all = (long long)ntiles * tl.n;
     if (ok && all >= 2048) {
       const int tpb = (int)std::min(8LL, all / 1024);
       dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
