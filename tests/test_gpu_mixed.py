@@ -39,17 +39,29 @@ def test_mixed_rhs_close_to_oracle(name, size):
     e = rhs_errors(got, ref, U)
     log("  e_f = " + " ".join(f"{x:.1e}" for x in e))
     assert np.isfinite(got).all()
-    # rounding of the low-precision contraction grows like eps_low |f - c| ||D2||,
-    # ||D2|| ~ N^4: a sanity bound here; the accuracy bounds are on the evolution
+    # A characterisation, not the form's accuracy bound (that is on the
+    # evolution, below): the contraction inputs are rounded to the low
+    # precision (unit roundoff eps_low, after the shift by the line's middle
+    # value), and the second-derivative operator amplifies an input error by
+    # up to ||D2||_inf ~ N^4 / 3 (the CGL second-derivative matrix) relative to
+    # the field's variation; the group scale of the right-hand side is at
+    # least that variation, so e_f <= eps_low N^4.
     eps = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[name]
-    assert e.max() < 20 * eps * max(size) ** 4
+    assert e.max() < eps * max(size) ** 4
 
 
 def rho_of(pb, U):
     return pb.primitives(U)["rho"]
 
 
-@pytest.mark.parametrize("name", ["fp32", "bf16x3"])
+BF16_MISS = ("split-BF16x3 keeps about 16 significand bits of each operand (2^-17 relative per hi/lo pair "
+             "product left out), which the second-derivative operators amplify by ~N^4: measured rho L2 "
+             "7.0e-6 at 16^3 after 10 steps and 8.7e-5 (Hamiltonian-norm ratio 6.05) at 64x64x128 after "
+             "100 steps, against the bounds 1e-6 and 2")
+
+
+@pytest.mark.parametrize("name", ["fp32", pytest.param("bf16x3", marks=pytest.mark.xfail(strict=True,
+                                                                                         reason=BF16_MISS))])
 def test_mixed_evolution_within_bounds(name):
     log(f"[mixed evolve] {name} 16^3, 10 RK4 steps")
     w = workload("ks_michel_16x16x16")
@@ -69,13 +81,11 @@ def test_mixed_evolution_within_bounds(name):
     r_ref, r_got = rho_of(pb, ref), rho_of(pb, got)
     l2 = np.sqrt(np.sum((r_got - r_ref) ** 2) / np.sum(r_ref ** 2))
     log(f"  rho L2 rel {l2:.2e}; H L2 {d['ham_l2']:.4e} vs FP64 {d64['ham_l2']:.4e}")
-    # FP32 meets the 1e-6 density bound.  Split-BF16x3 carries ~2^-16 relative
-    # error per operand (8 + 8 significand bits), which reaches the density
-    # through sqrt(gamma) = e^{6 phi} sqrt(det gt): measured 7e-6 here, so its
-    # bound is the level it attains, not the 1e-6 target.
-    assert l2 < {"fp32": 1e-6, "bf16x3": 2e-5}[name]
-    assert d["ham_l2"] < 2.0 * d64["ham_l2"]
     assert d["nonfinite"] == 0 and d["c2p_fail"] == 0
+    # the form's bounds: density within 1e-6 (relative L2), Hamiltonian-
+    # constraint norm within 2x of the FP64 run's
+    assert l2 < 1e-6
+    assert d["ham_l2"] < 2.0 * d64["ham_l2"]
 
 
 def test_hamiltonian_diagnostic_matches_oracle():
