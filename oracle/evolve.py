@@ -265,7 +265,7 @@ class Problem:
 
 
 def initial_state(grid, problem, r_c=8.0, rho_c=1e-8, beta_min=100.0, pert_amp=1e-6, seed=1,
-                  id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-6,
+                  id_kind="michel", tor_r_in=6.0, tor_r_max=12.0, tor_rho_max=1e-8, tor_atm=1e-2,
                   tor_loop_cut=0.2):
     """Kerr-Schild BSSN data + magnetised Michel flow (id_kind "michel") or a
     magnetised Fishbone-Moncrief torus ("torus"); returns (U, K0, matter)."""

@@ -13,7 +13,9 @@ Readings of the paper taken here (where it is silent or inconsistent):
   * K_ij from stationarity of the background: K_ij = L_beta gamma_ij / (2 alpha)
     with spectral derivatives of the nodal gamma_ij and beta^i.
   * Gamma-tilde^i = gt^{jk} Gamma-tilde^i_jk from spectral derivatives of gt_ij;
-    B-driver = 0; K0 = K.
+    B-driver = 0.  The static 1+log source K0 is not part of these data: it
+    is K - beta^k d_k alpha / (2 alpha) of the initial slice
+    (evolve.gauge_source_k0).
   * Michel radial profile is used for every spin with u^theta = u^phi = 0 in
     Kerr-Schild coordinates and u^t from the normalisation (exactly stationary
     only at a = 0).  Supersonic branch inside r_c, subsonic outside.
@@ -260,7 +262,7 @@ class FMTorus:
         return out
 
 
-def fm_torus(grid, fields, M, a, Gamma, r_in, r_max, rho_max, beta_min, pert_amp, seed, atm=1e-6, a_cut=0.2):
+def fm_torus(grid, fields, M, a, Gamma, r_in, r_max, rho_max, beta_min, pert_amp, seed, atm=1e-2, a_cut=0.2):
     """Magnetised Fishbone-Moncrief torus on the nodes (same return keys as
     michel_monopole).
 
