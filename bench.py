@@ -7,9 +7,11 @@ A step is one classic RK4 step (four RHS evaluations + RK updates) followed by
 the spectral filter, over the whole grid of the workload, with the state
 resident in HBM.  value = points x 4 x K / (wall time of K steps).  Prints one
 JSON line.  Also reported: per-launch durations measured with HIP events on
-the library's stream (the dominant kernel's roofline), and the plain FP64
-oracle timed on this host on a bounded sample (one RHS evaluation of the same
-workload)."""
+the library's stream (the dominant kernel's roofline), the bandwidth a plain
+device copy reaches on this GPU, and the plain FP64 oracle timed on this
+host: two full RK4 steps of the same workload and the ten steps of the 16^3
+workload with the BLAS pool on every core this process may use, and one RK
+stage of the same workload on one thread."""
 
 import argparse
 import json
@@ -99,26 +101,88 @@ def roofline(kind, ms, P, costs):
 
 
 def cpu_baseline(w):
-    """The oracle as it stands: one RHS evaluation (one RK stage) of the same
-    workload on this host."""
+    """The oracle as it stands, timed on this host.  Cores: the CPUs this
+    process may run on (os.sched_getaffinity), and the BLAS pool is set to
+    that many threads (the oracle's einsum, FFT and elementwise work runs on
+    one thread whatever the pool).  value: two full RK4 steps of the workload
+    (8 RHS evaluations, 8 stage updates, 2 filter passes) from the oracle's
+    initial data, points x 4 x 2 / wall time.  Also: all ten steps of the
+    16^3 workload, and one RK stage of the workload with the pool set to one
+    thread."""
     from oracle import spectral, evolve
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        blas = 1
-    ga, pk, ik = workloads.oracle_kwargs(w)
-    g = spectral.Grid(*ga)
-    pb = evolve.Problem(g, **pk)
-    U, K0, _ = evolve.initial_state(g, pb, **ik)
-    t0 = time.perf_counter()
-    pb.rhs(U, K0)
-    t = time.perf_counter() - t0
-    return {"value": g.npts / t, "unit": "point-stage updates/s", "cores": int(blas),
-            "kind": "oracle",
-            "sample": f"one RHS evaluation (one RK stage) of {w['grid']['nr']}x{w['grid']['nth']}x"
-                      f"{w['grid']['nph']} after untimed oracle initial data; {t:.1f} s; NumPy FP64, "
-                      f"dense BLAS solves on {blas} threads, einsum/FFT single-threaded"}
+    from threadpoolctl import threadpool_limits
+    cores = len(os.sched_getaffinity(0))
+
+    def setup(wl):
+        ga, pk, ik = workloads.oracle_kwargs(wl)
+        g = spectral.Grid(*ga)
+        pb = evolve.Problem(g, **pk)
+        U, K0, _ = evolve.initial_state(g, pb, **ik)
+        return g, pb, U, K0
+
+    def timed_steps(wl, nsteps, threads):
+        g, pb, U, K0 = setup(wl)
+        dt = pb.dt()
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            pb.evolve(U, K0, dt, nsteps)
+            t = time.perf_counter() - t0
+        return g.npts * 4 * nsteps / t, t
+
+    name = "x".join(str(w["grid"][k]) for k in ("nr", "nth", "nph"))
+    rate, t = timed_steps(w, 2, cores)
+    progress(f"oracle: 2 RK4 steps of {name} on {cores} cores, {t:.1f} s")
+    w16 = workloads.WORKLOADS["ks_michel_16x16x16"]
+    rate16, t16 = timed_steps(w16, w16["steps"], cores)
+    rate16_1, t16_1 = timed_steps(w16, w16["steps"], 1)
+    g, pb, U, K0 = setup(w)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        k1 = pb.rhs(U, K0)
+        U1 = U + 0.5 * pb.dt() * k1
+        t1 = time.perf_counter() - t0
+    progress(f"oracle: 16^3 10 steps {t16:.1f} s ({cores} cores), {t16_1:.1f} s (1 thread); "
+             f"one stage of {name} on 1 thread {t1:.1f} s")
+    del U1
+    return {"value": rate, "unit": "point-stage updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"two full RK4 steps of {name} (8 RHS evaluations and stage updates, 2 filter passes) "
+                      f"from the oracle's initial data (untimed), {t:.1f} s; NumPy FP64, BLAS pool "
+                      f"{cores} threads (the CPUs this process may use), einsum/FFT/elementwise on one thread",
+            "seconds": round(t, 2),
+            "ks_michel_16x16x16_10_steps": {"value": rate16, "seconds": round(t16, 3), "threads": cores},
+            "single_thread": {"ks_michel_16x16x16_10_steps": {"value": rate16_1, "seconds": round(t16_1, 3)},
+                              f"one_rk_stage_{name}": {"value": g.npts / t1, "seconds": round(t1, 2)}}}
+
+
+def stream_ceiling(torch):
+    """Bandwidth of plain device streams on this GPU (torch's own kernels):
+    a copy of 1 GiB (read + write) and a three-array add c = a + b of 1 GiB
+    arrays, beyond the last-level cache; median of 10 timed launches with HIP
+    events on the current stream, after 3 untimed ones."""
+    n = 128 * 1024 * 1024  # doubles: 1 GiB per array
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: c.copy_(a), 2 * 8 * n),
+                             ("add", lambda: torch.add(a, b, out=c), 3 * 8 * n)):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(10):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = sorted(ts)[len(ts) // 2]
+        out[name + "_GB_per_s"] = round(nbytes / t / 1e9, 1)
+    del a, b, c
+    torch.cuda.empty_cache()
+    out["bytes_per_array"] = 8 * n
+    return out
 
 
 # tensor groups of the 32 evolved fields (phi | gt | At | K | Gt and the driver
@@ -486,6 +550,8 @@ def main():
         "kernels": kernels,
     }
     progress(f"main workload done: {out['value']:.4g} point-stage updates/s")
+    out["stream_ceiling"] = stream_ceiling(torch)
+    progress("stream ceiling done")
     if not args.no_mixed:
         out["mixed_precision"] = mixed_forms(w, K, out["value"], Solver, make_grid, make_phys, torch)
         progress("mixed-precision forms done")
@@ -508,13 +574,14 @@ def main():
                                     "grids {16^3, 32x32x64, 48x48x96, 64x64x128}, Michel+field, "
                                     f"T~U[10,100] M scaled by {args.serve_t_scale:g}, HBM budget 200 GB",
                           "t_scale": args.serve_t_scale}
-        for name, prec in (("fp64", 0), ("fp32", 1)):
-            out["serving"][name] = run_stream(jobs, prec=prec, budget=200e9, log=progress)
-            progress(f"served stream ({name}) done")
-        # capacity: the same 256 jobs all arriving at t = 0 (continuous batching at full load)
+        out["serving"]["fp64"] = run_stream(jobs, prec=0, budget=200e9, log=progress)
+        progress("served stream (fp64) done")
+        # capacity and per-grid latency under overload: the same 256 jobs all
+        # arriving at t = 0 (continuous batching at full load), FP64 and FP32
         burst = [dict(j, arrival=0.0) for j in jobs]
-        out["serving"]["fp64_burst"] = run_stream(burst, prec=0, budget=200e9, log=progress)
-        progress("served burst done")
+        for name, prec in (("fp64_burst", 0), ("fp32_burst", 1)):
+            out["serving"][name] = run_stream(burst, prec=prec, budget=200e9, log=progress)
+            progress(f"served burst ({name}) done")
         # mixed workload: half the jobs on the fixed background (a second job class per grid)
         mix = workloads.served_stream(256, 4.0, t_scale=args.serve_t_scale, cowling_frac=0.5)
         out["serving"]["fp64_half_fixed_background"] = run_stream(mix, prec=0, budget=200e9, log=progress)
