@@ -8,7 +8,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgrmhd.so")
+# GRMHD_LIBRARY selects another build of the library (the host-sanitizer
+# build of the CPU tests); the default is the in-tree libgrmhd.so
+LIB_PATH = os.environ.get("GRMHD_LIBRARY") or os.path.join(HERE, "libgrmhd.so")
 
 GRMHD_FP64, GRMHD_MIX_FP32, GRMHD_MIX_BF16X3 = 0, 1, 2
 NFIELDS = 32
@@ -75,12 +77,15 @@ SIGNATURES = {
     "grmhd_state_ptr": (ctypes.c_int, [_vp, _P(_vp), _P(_vp)]),
     "grmhd_rhs": (ctypes.c_int, [_vp, _vp, _vp]),
     "grmhd_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "grmhd_step_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "grmhd_diagnostics": (ctypes.c_int, [_vp, _P(Diag)]),
     "grmhd_dt": (ctypes.c_double, [_vp]),
     "grmhd_time": (ctypes.c_double, [_vp]),
     "grmhd_last_error": (ctypes.c_char_p, []),
     "grmhd_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_int32]),
     "grmhd_con2prim": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "grmhd_xcts_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "grmhd_profile_step": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, ctypes.c_int32, _P(ctypes.c_int32)]),
     "grmhd_step_batch": (ctypes.c_int, [_P(_vp), ctypes.c_int32, ctypes.c_int32]),
     "grmhd_set_dt": (ctypes.c_int, [_vp, ctypes.c_double]),

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgrmhd.so")
-SOURCES = ["contract.hip", "contract_mixed.hip", "pointwise.hip", "operators.cpp", "init_data.cpp", "abi.cpp", "server.cpp"]
+SOURCES = ["contract.hip", "contract_mixed.hip", "pointwise.hip", "xcts.hip", "operators.cpp", "init_data.cpp",
+           "abi.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,15 +26,25 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-I", INCLUDE, "-I", CSRC]
 
 
-def build(verbose=False, jobs=5):
-    objdir = os.path.join(HERE, "_build")
+# host-only sanitizers (AddressSanitizer + UndefinedBehaviorSanitizer on the
+# host pass; the device code is built as usual): a separate library for the
+# CPU tests of the C-ABI and the job server, loaded with the sanitizer runtime
+# preloaded
+HOSTSAN_LIB = os.path.join(HERE, "libgrmhd_hostsan.so")
+HOSTSAN_FLAGS = ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
+                 "-Xarch_host -fno-omit-frame-pointer -Xarch_host -fno-sanitize-recover=undefined").split()
+
+
+def build(verbose=False, jobs=5, hostsan=False):
+    objdir = os.path.join(HERE, "_build_hostsan" if hostsan else "_build")
     os.makedirs(objdir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         # every translation unit goes through hipcc as HIP: the host sources
         # include the HIP runtime header and launch the kernels
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + (HOSTSAN_FLAGS if hostsan else []) + ["-x", "hip", "-c",
+                                                                     os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -50,12 +61,13 @@ def build(verbose=False, jobs=5):
             failed.append(src)
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
-    tmp = LIB + ".tmp"
+    lib = HOSTSAN_LIB if hostsan else LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, hostsan="--hostsan" in sys.argv))
