@@ -65,7 +65,8 @@ enum {
   GRMHD_E_SIZE = -2,     /* buffer size does not match the grid            */
   GRMHD_E_DEVICE = -3,   /* HIP runtime error                              */
   GRMHD_E_STATE = -4,    /* call out of order (e.g. step before a state)   */
-  GRMHD_E_BUDGET = -5    /* server: job does not fit the memory budget     */
+  GRMHD_E_BUDGET = -5,   /* server: job does not fit the memory budget     */
+  GRMHD_E_UNAVAILABLE = -6  /* entry point switched off in this library       */
 };
 
 #define GRMHD_NFIELDS 32
@@ -283,6 +284,34 @@ int grmhd_apply_operator(grmhd_ctx* ctx, int32_t axis, int32_t op,
 int grmhd_con2prim(grmhd_ctx* ctx, const double* dev_U, double* dev_prim,
                    double* dev_flux, double* dev_fail);
 
+/* ---- initial data: conformally flat, time-symmetric (XCTS approximation) -- */
+
+/* The conformal factor psi of the conformally flat, time-symmetric data
+ * gamma_ij = psi^4 f_ij (f the flat metric of the grid's spherical
+ * coordinates, A_ij = 0, K = 0) of Methods, "Initial Data: Approximate XCTS
+ * Solution": the Hamiltonian constraint Lap psi = -2 pi E psi^5 solved by
+ * fixed-point relaxation -- each iteration solves the linear problem
+ * Lap psi_{k+1} = -2 pi E psi_k^5 (flat Laplacian, the grid's spectral
+ * collocation) exactly, by fast diagonalisation: real Fourier transform in
+ * phi and, per mode, the eigenvectors of the radial and polar operators
+ * (host eigen-decompositions, once per call), applied along grid lines on the
+ * device.
+ * dev_E: energy density seen by normal observers (P doubles, layout of a
+ * field), held fixed.  dev_psi (P doubles): in, the initial guess, whose
+ * values on the r-end and theta-end nodes are the Dirichlet data (phi is
+ * periodic); out, the solution.  Iterates until the largest change is at most
+ * tol times max |psi| or max_iter iterations; iters and change (optional)
+ * receive the count and the last relative change (NaN propagates: a
+ * non-finite iterate stops the iteration).  Uses the context's grid and
+ * scratch buffer (between steps); the state is not touched.  n_r, n_theta
+ * >= 3.  GRMHD_E_ARG if an operator has complex eigenvalues.  Syncs.
+ * Switched off: after the argument checks it returns GRMHD_E_UNAVAILABLE
+ * without touching the device.  Its first run on the hardware ended in a
+ * device fault whose cause has not been found (the kernels' indexing checks
+ * out on the CPU); the solver stays in the source until one is. */
+int grmhd_xcts_solve(grmhd_ctx* ctx, const double* dev_E, double* dev_psi, int32_t max_iter, double tol,
+                     int32_t* iters, double* change);
+
 /* ---- served form: continuous-batching job server ------------------------- */
 
 typedef struct grmhd_server grmhd_server;
@@ -334,7 +363,8 @@ int grmhd_server_submit(grmhd_server* srv, const grmhd_grid* grid, const grmhd_p
 /* One scheduling round: count the RK4 steps that have completed on the
  * device (event queries per grid class) and retire jobs that reached their
  * end time, freeing their memory; admit queued jobs in arrival order while
- * they fit (a job whose context or initial data cannot be built is marked
+ * they fit, at most four per tick (a dry run admits all that fit; a job whose
+ * context or initial data cannot be built is marked
  * rejected, its message left in grmhd_server_last_error, and the round goes
  * on); launch the next step of every class with room in its two-step
  * pipeline (one batched launch sequence per class).  Returns without waiting

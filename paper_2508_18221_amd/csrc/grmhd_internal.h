@@ -156,6 +156,11 @@ struct Operators {
 
 void build_operators(const grmhd_grid& g, double cfl, Operators* ops);
 
+// Chebyshev first- and second-derivative matrices on n CGL nodes in the
+// reference coordinate (row-major, built in long double and rounded once;
+// D2 = D1 D1 with zero row sums), the ones build_operators maps.
+void cheb_reference_matrices(int n, std::vector<double>* D1, std::vector<double>* D2);
+
 // Two contexts can share one launch sequence (grmhd_step_batch, the job
 // server's classes) when their buffers are laid out alike and the kernels get
 // the same parameters and take the same path: same grid sizes, filter and
@@ -198,6 +203,25 @@ int host_initial_plane(const grmhd_grid& g, const grmhd_phys& ph, const Operator
 // n; then the densitised conserved variables.
 hipError_t launch_init_expand(const double* plane, int torus, uint64_t seed, double amp, double gamma_ad,
                               const PointParams& pp, double* U, double* K0, hipStream_t s);
+
+// ---- conformally flat initial data (xcts.hip) ----------------------------
+struct XctsGrid {
+  int nr, nth, nph;
+  double Lh, Th;        // radial log-map and polar affine-map half widths
+  const double* r;      // radial nodes (host, nr)
+  const double* th;     // polar nodes (host, nth)
+};
+// Doubles of host-built operators the solver stages after its five work
+// arrays of P doubles in the work buffer.
+size_t xcts_operator_doubles(int nr, int nth, int nph);
+// Picard iteration for Lap psi = -2 pi E psi^5 on the grid, the boundary
+// values of psi (device, P doubles; in: the initial guess carrying the
+// Dirichlet data, out: the solution) held; E device, P doubles.  work: at
+// least 5 P + xcts_operator_doubles(...) doubles of device memory; partials:
+// device memory for 2 x partial_blocks doubles.  Syncs s.
+int xcts_solve(const XctsGrid& g, double* work, double* partials, int partial_blocks, hipStream_t s,
+               const double* E, double* psi, int max_iter, double tol, int* iters, double* change,
+               std::string* err);
 
 // ---- kernel launchers (kernels.hip) --------------------------------------
 // Contraction along axis (0 r, 1 theta, 2 phi) with nmat = 1 or 2 matrices.

@@ -193,6 +193,18 @@ void store_fold(const std::vector<ld>& A, int n, int hpad, std::vector<double>* 
 
 }  // namespace
 
+void cheb_reference_matrices(int n, std::vector<double>* D1, std::vector<double>* D2) {
+  std::vector<ld> A = cheb_d1(n);
+  std::vector<ld> B = matmul(A, A, n);
+  zero_row_sums(B, n);
+  D1->resize(A.size());
+  D2->resize(B.size());
+  for (size_t e = 0; e < A.size(); ++e) {
+    (*D1)[e] = (double)A[e];
+    (*D2)[e] = (double)B[e];
+  }
+}
+
 void build_operators(const grmhd_grid& g, double cfl, Operators* ops) {
   const int n[3] = {g.nr, g.nth, g.nph};
   for (int a = 0; a < 3; ++a) {

@@ -118,6 +118,15 @@ class Solver:
                                       _ptr(flux_out) if flux_out is not None else None,
                                       _ptr(fail_out) if fail_out is not None else None))
 
+    def xcts_solve(self, E_dev, psi_dev, max_iter=200, tol=1e-11):
+        """Conformal factor of the conformally flat, time-symmetric data:
+        psi_dev holds the initial guess with the Dirichlet boundary values and
+        receives the solution.  Returns (iterations, last relative change)."""
+        it, ch = ctypes.c_int32(), ctypes.c_double()
+        check(self.lib.grmhd_xcts_solve(self.ctx, _ptr(E_dev), _ptr(psi_dev), int(max_iter), float(tol),
+                                        ctypes.byref(it), ctypes.byref(ch)))
+        return it.value, ch.value
+
     def profile_step(self, nsteps=1):
         """Advance nsteps RK4 steps, returning {launch kind: (avg ms, count)}
         measured with HIP events on the context stream."""
