@@ -13,7 +13,8 @@
 //      on the host) and free their block;
 //   2. admission: queued jobs are placed, in arrival order, into the caller's
 //      device arena (first fit, 256-byte aligned blocks holding the job's
-//      resident and scratch buffers) as long as they fit the budget; an
+//      resident and scratch buffers) as long as they fit the budget, at most
+//      four per tick (a burst is admitted while the device works); an
 //      admitted job gets its context and initial data on the server's
 //      admission stream, a time step dt = T / ceil(T / dt_CFL) so that it
 //      ends exactly at T, and then joins its class's stream; a job whose
@@ -82,6 +83,10 @@ struct Launch {
 
 // Steps a class may have in flight at once.
 constexpr int DEPTH = 2;
+// Jobs admitted per tick: admission builds each job's context and initial
+// data on the host (milliseconds per job), so a burst of arrivals is admitted
+// a few at a time while the classes already admitted keep the device busy.
+constexpr int ADMIT_PER_TICK = 4;
 
 // First-fit allocator over [0, size) with coalescing frees.
 struct Arena {
@@ -350,7 +355,7 @@ static int complete(grmhd_server* s, bool* progress) {
 // or initial data cannot be built is rejected (its message is the server's
 // last error); the others go on.
 static void admit(grmhd_server* s, bool* progress) {
-  while (!s->queue.empty()) {
+  for (int admitted = 0; !s->queue.empty() && (s->dry || admitted < ADMIT_PER_TICK); ++admitted) {
     Job& j = s->jobs[s->queue.front()];
     size_t off = 0;
     if (!s->arena.alloc(j.bytes, &off)) break;
