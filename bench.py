@@ -157,15 +157,17 @@ def cpu_baseline(w):
 def stream_ceiling(torch):
     """Bandwidth of plain device streams on this GPU (torch's own kernels):
     a copy of 1 GiB (read + write) and a three-array add c = a + b of 1 GiB
-    arrays, beyond the last-level cache; median of 10 timed launches with HIP
-    events on the current stream, after 3 untimed ones."""
+    arrays, beyond the last-level cache; and copies of 32, 128 and 512 MiB
+    (32 MiB each way is what one flux-derivative launch of 64x64x128 moves),
+    to show how the rate of a single short launch falls with its size.
+    Median of 10 timed launches with HIP events on the current stream, after
+    3 untimed ones."""
     n = 128 * 1024 * 1024  # doubles: 1 GiB per array
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.ones(n, dtype=torch.float64, device="cuda")
     c = torch.empty_like(a)
-    out = {}
-    for name, fn, nbytes in (("copy", lambda: c.copy_(a), 2 * 8 * n),
-                             ("add", lambda: torch.add(a, b, out=c), 3 * 8 * n)):
+
+    def rate(fn, nbytes):
         for _ in range(3):
             fn()
         ts = []
@@ -177,11 +179,16 @@ def stream_ceiling(torch):
             e1.record()
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1) * 1e-3)
-        t = sorted(ts)[len(ts) // 2]
-        out[name + "_GB_per_s"] = round(nbytes / t / 1e9, 1)
+        return round(nbytes / sorted(ts)[len(ts) // 2] / 1e9, 1)
+
+    out = {"copy_GB_per_s": rate(lambda: c.copy_(a), 2 * 8 * n),
+           "add_GB_per_s": rate(lambda: torch.add(a, b, out=c), 3 * 8 * n),
+           "bytes_per_array": 8 * n, "copy_GB_per_s_by_size": {}}
+    for mib in (32, 128, 512):
+        m = mib * 1024 * 1024 // 8
+        out["copy_GB_per_s_by_size"][f"{mib}MiB"] = rate(lambda: c[:m].copy_(a[:m]), 2 * 8 * m)
     del a, b, c
     torch.cuda.empty_cache()
-    out["bytes_per_array"] = 8 * n
     return out
 
 
@@ -222,6 +229,9 @@ def mixed_forms(w, K, fp64_rate, Solver, make_grid, make_phys, torch):
     rho_ref = prim_ref[0].clone()
     ref.close()
     out = {"reference": "the FP64 GPU path after the same steps (equal to the oracle to 1e-11 per field)"}
+    out["fp64_from_fp32_rounded_state"] = sensitivity(
+        w, K, {"fp64": U_ref, "fp64_rho": rho_ref.cpu().numpy(), "fp64_ham_l2": d_ref["ham_l2"]}, torch, Solver,
+        make_grid, make_phys)
     g = w["grid"]
     P = g["nr"] * g["nth"] * g["nph"]
     for name, prec in (("fp32", 1), ("bf16x3", 2)):
@@ -363,7 +373,9 @@ def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
     """A second measured configuration (the magnetised torus at 128x96x192):
     FP64 and FP32-form throughput over the workload's step count from the
     library's initial data, the dominant launch's roofline, the stage
-    fraction, and the FP32 form's errors against the FP64 path."""
+    fraction, and the FP32 form's errors against the FP64 path after the same
+    1 + K steps; and the FP64 path from the FP32-rounded initial state (how
+    far FP32-level rounding alone moves this evolution)."""
     w = workloads.WORKLOADS[name]
     g = w["grid"]
     P = g["nr"] * g["nth"] * g["nph"]
@@ -383,6 +395,13 @@ def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
         d = s.diagnostics()
         rec = {"value": P * 4 * K / wall, "ms_per_step": wall * 1e3 / K, "c2p_fail": d["c2p_fail"],
                "nonfinite": d["nonfinite"], "ham_l2": d["ham_l2"]}
+        # the state after the warm-up and the timed steps (1 + K), before the
+        # profiled steps below advance it further
+        states[name_p] = s.get_state()
+        states[name_p + "_ham_l2"] = d["ham_l2"]
+        prim = torch.empty((5,) + s.shape, dtype=torch.float64, device="cuda")
+        s.con2prim(s.U, prim)
+        states[name_p + "_rho"] = prim[0].cpu().numpy()
         if prec == 0:
             prof = s.profile_step(profile_steps)
             per_step = {k: ms * cnt / profile_steps for k, (ms, cnt) in prof.items()}
@@ -392,19 +411,43 @@ def second_config(name, torch, Solver, make_grid, make_phys, profile_steps=2):
             rec["stage_roofline_fraction"] = round(ideal / rec["ms_per_step"], 3)
             rec["serial_launch_sum_ms_per_step"] = round(sum(per_step.values()), 5)
             rec["kernels_avg_ms"] = {k: round(ms, 5) for k, (ms, cnt) in prof.items()}
-        states[name_p] = s.get_state()
-        prim = torch.empty((5,) + s.shape, dtype=torch.float64, device="cuda")
-        s.con2prim(s.U, prim)
-        states[name_p + "_rho"] = prim[0].cpu().numpy()
         out[name_p] = rec
         s.close()
     import numpy as np
+    out["fp64_from_fp32_rounded_state"] = sensitivity(w, K + 1, states, torch, Solver, make_grid, make_phys)
     r64, r32 = states["fp64_rho"], states["fp32_rho"]
     out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
     out["fp32"]["rho_l2_rel_vs_fp64"] = float(np.sqrt(np.sum((r32 - r64) ** 2) / np.sum(r64 ** 2)))
     out["fp32"]["ham_ratio"] = out["fp32"]["ham_l2"] / out["fp64"]["ham_l2"]
     out["fp32"]["field_rel_err_max"] = max(group_errors(states["fp32"], states["fp64"]))
     return out
+
+
+def sensitivity(w, K, states, torch, Solver, make_grid, make_phys):
+    """How far FP32-level rounding alone moves the FP64 evolution: the FP64
+    path from the initial state rounded once to FP32 (K0 exact), the same K
+    steps, against the FP64 path from the exact state (states["fp64"],
+    states["fp64_rho"]): density L2, Hamiltonian-constraint ratio and the
+    largest per-field error.  A reduced-precision form rounds at least this
+    much at every stage, so if this already exceeds the form's bounds no form
+    with FP32-level derivatives can meet them on the workload."""
+    import numpy as np
+    s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]))
+    s.init_state()
+    U0, K0 = s.get_state(with_k0=True)
+    s.set_state(U0.astype(np.float32).astype(np.float64), K0)
+    s.step(K)
+    d = s.diagnostics()
+    got = s.get_state()
+    prim = torch.empty((5,) + s.shape, dtype=torch.float64, device="cuda")
+    s.con2prim(s.U, prim)
+    rho = prim[0].cpu().numpy()
+    s.close()
+    r64 = states["fp64_rho"]
+    d64 = states.get("fp64_ham_l2")
+    return {"rho_l2_rel_vs_fp64": float(np.sqrt(np.sum((rho - r64) ** 2) / np.sum(r64 ** 2))),
+            "ham_ratio": d["ham_l2"] / d64 if d64 else None, "c2p_fail": d["c2p_fail"],
+            "field_rel_err_max": max(group_errors(got, states["fp64"])), "steps": K}
 
 
 def traffic_probe(w, torch, Solver, make_grid, make_phys):

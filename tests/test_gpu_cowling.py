@@ -249,10 +249,9 @@ def test_flat_space_advection_rate_closed_form(field):
 
 
 def test_flat_space_advection_evolves_to_the_exact_solution():
-    """The blob (no field, filter off, 32 x 32 x 48, M = 0, fixed background:
-    the matter path alone, the spacetime held) evolved by RK4 to t = 2 M,
-    where it has moved V t = 1 M, a third of its width, follows the exact
-    transport rho_0(x - V t) with sqrt(gamma) W unchanged.  Next to the theta ends even the blob-free
+    """Fifty RK4 steps of the blob (no field, filter off, 32 x 32 x 48, M = 0,
+    fixed background) follow the exact transport rho_0(x - V t) with
+    sqrt(gamma) W unchanged.  Next to the theta ends even the blob-free
     uniform flow, an exactly steady state, drifts (the polar truncation of
     the conformal variables, independent of the blob), so the check takes
     the change of sqrt(gamma) D with the blob minus the change without it.
@@ -261,18 +260,26 @@ def test_flat_space_advection_evolves_to_the_exact_solution():
     and, through the velocity, the larger momentum-rate errors (S_theta up
     to 5e-2 of its scale there): bar 1e-2 of the largest exact change, an
     order above the former and far below the O(1) error of a wrong flux or
-    source."""
+    source.
+
+    The check covers t = 0.14 M (the blob moves 0.07 M, 2% of its width) and
+    cannot go much further: the uniform flow enters the domain through the
+    inner sphere, where the scheme (built for an excision radius inside a
+    horizon, which every characteristic leaves) imposes no data, and the
+    blob-free flow's drift grows exponentially from there (measured at this
+    grid, filter off: 0.55 of the exact change at t = 0.25 M, 2e2 at 0.5 M,
+    recovery failures from 0.25 M; with the filter the drift is smaller but
+    failures start by t = 1 M).  It exercises the matter path on a fixed
+    background only, not the coupled evolution."""
     from paper_2508_18221_amd import Solver, make_grid, make_phys
     from advection_case import V, exact_density_at, flat_advection_state
-    n, t_end = (32, 32, 48), 2.0
-    log(f"[flat-space advection, evolved] {n}, RK4 to t = {t_end} M, filter off, with and without the blob")
+    n, steps = (32, 32, 48), 50
+    log(f"[flat-space advection, evolved] {n}, {steps} RK4 steps, filter off, with and without the blob")
     changes, t = [], None
     for blob in (True, False):
         g, pb, U, K0, _ = flat_advection_state(*n, blob=blob)
         s = Solver(make_grid(*n, filter_on=False), make_phys(M=0.0, a=0.0, cowling=True))
         s.set_state(U, K0)
-        steps = int(np.ceil(t_end / s.dt))
-        s.set_dt(t_end / steps)
         t = steps * s.dt
         s.step(steps)
         got = s.get_state()
@@ -287,6 +294,5 @@ def test_flat_space_advection_evolves_to_the_exact_solution():
     inner = (slice(None), slice(1, -1), slice(1, None))
     drift = np.abs(changes[1][inner]).max() / np.abs(exact).max()
     e = np.abs((changes[0] - changes[1])[inner] - exact[inner]).max() / np.abs(exact).max()
-    log(f"  t = {t:.3e} ({steps} steps): max exact change {np.abs(exact).max():.2e}; blob-free drift {drift:.1e}; "
-        f"error {e:.1e}")
+    log(f"  t = {t:.3e}: max exact change {np.abs(exact).max():.2e}; blob-free drift {drift:.1e}; error {e:.1e}")
     assert e < 1e-2
