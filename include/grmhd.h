@@ -183,7 +183,12 @@ int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec,
  * dev_resident / dev_scratch: device buffers of at least the queried sizes,
  * 256-byte aligned; hip_stream: a hipStream_t (0 = null stream).  Syncs.
  * GRMHD_E_ARG for a grid or parameter out of range (Gamma > 1, cfl > 0,
- * 0 <= |a| <= M, finite floors > 0, switches 0 or 1, ...). */
+ * 0 <= |a| <= M, finite floors > 0, switches 0 or 1, ...).
+ * dev_scratch may be NULL: such a context is stepped by grmhd_step_noalloc
+ * only; its state comes from grmhd_set_state with a host K0 (init_state,
+ * set_state without K0, rhs, step, step_batch, diagnostics and profile_step
+ * return GRMHD_E_STATE), and get_state, state_ptr, con2prim and
+ * apply_operator work as usual. */
 int grmhd_create(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_prec prec,
                  void* dev_resident, void* dev_scratch, void* hip_stream,
                  grmhd_ctx** out);
@@ -242,6 +247,25 @@ int grmhd_step(grmhd_ctx* ctx, int32_t nsteps);
  * filter constants, the spin, the initial data and dt may differ.  Each job's arithmetic is the same
  * as when stepped alone (bitwise).  Async. */
 int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps);
+
+/* Size of the library's own device array behind grmhd_step_noalloc (one per
+ * GPU the library runs on, held until the process ends): the largest scratch
+ * size (grmhd_query_bytes) of a grid it steps, about 29,000 grid points. */
+#define GRMHD_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): nsteps
+ * RK4 steps exactly as grmhd_step takes them (the same kernels, bitwise the
+ * same result), with the stage temporaries in the library's own device
+ * array instead of the context's scratch buffer, so the context may have
+ * been created with dev_scratch = NULL.  Allocates nothing.  GRMHD_E_SIZE
+ * when the grid's scratch size exceeds GRMHD_NOALLOC_SCRATCH_BYTES;
+ * GRMHD_E_ARG unless the context's device is the current one.  The array is
+ * shared by every call on a GPU and keeps the last call's contents (nothing
+ * in it is assumed to start at zero; a fixed background's derivatives are
+ * recomputed at each call): calls that overlap on one GPU -- from other
+ * threads, or queued on different streams -- race.  Async. */
+int grmhd_step_noalloc(grmhd_ctx* ctx, int32_t nsteps);
 
 /* Override the time step (e.g. dt = T / ceil(T / dt) to land on an end time). */
 int grmhd_set_dt(grmhd_ctx* ctx, double dt);

@@ -77,6 +77,7 @@ SIGNATURES = {
     "grmhd_state_ptr": (ctypes.c_int, [_vp, _P(_vp), _P(_vp)]),
     "grmhd_rhs": (ctypes.c_int, [_vp, _vp, _vp]),
     "grmhd_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "grmhd_step_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "grmhd_diagnostics": (ctypes.c_int, [_vp, _P(Diag)]),
     "grmhd_dt": (ctypes.c_double, [_vp]),
     "grmhd_time": (ctypes.c_double, [_vp]),

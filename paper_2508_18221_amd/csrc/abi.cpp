@@ -27,6 +27,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -171,11 +173,13 @@ namespace {
 
 double* sf(grmhd_ctx* c, int f) { return c->scr + (size_t)f * c->L.P; }
 
-// Calls that need the context's scratch buffer refuse a context without one.
+// Calls that need the context's scratch buffer refuse a context created
+// without one (it can only be stepped by grmhd_step_noalloc).
 #define NEED_SCRATCH(c)                                                                              \
   do {                                                                                               \
     if (!(c)->scr)                                                                                   \
-      return fail(GRMHD_E_STATE, "context has no scratch buffer");                                   \
+      return fail(GRMHD_E_STATE, "context has no scratch buffer (created with dev_scratch = NULL): " \
+                                 "use grmhd_step_noalloc");                                          \
   } while (0)
 
 JobSet single(const grmhd_ctx* c) {
@@ -632,7 +636,7 @@ int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_
                           void* dev_scratch, void* hip_stream, const Operators* prebuilt, grmhd_ctx** out) {
   int rc = validate_grid(grid);
   if (rc) return rc;
-  if (!phys || !out || !dev_resident || !dev_scratch) return fail(GRMHD_E_ARG, "null argument");
+  if (!phys || !out || !dev_resident) return fail(GRMHD_E_ARG, "null argument");
   if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3)
     return fail(GRMHD_E_ARG, "unknown precision");
   if (((uintptr_t)dev_resident & 255) || ((uintptr_t)dev_scratch & 255))
@@ -887,6 +891,66 @@ int grmhd_step(grmhd_ctx* c, int32_t nsteps) {
     if (rc) return rc;
   }
   return GRMHD_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free stepping ---------------------------------------------
+// Stage temporaries of grmhd_step_noalloc: a file-scope device array, one copy
+// per GPU the library runs on, held until the process ends.  Host code never
+// uses its name as an address: the device address of each GPU's copy comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[GRMHD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+std::map<int, double*> g_noalloc_ptr;  // device -> address of its scratch copy
+
+int noalloc_scratch(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(device);
+  if (it != g_noalloc_ptr.end()) {
+    *out = it->second;
+    return GRMHD_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(GRMHD_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_noalloc_ptr[device] = (double*)ptr;
+  *out = (double*)ptr;
+  return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grmhd_step_noalloc(grmhd_ctx* c, int32_t nsteps) {
+  if (!c) return fail(GRMHD_E_ARG, "null context");
+  if (nsteps < 0) return fail(GRMHD_E_ARG, "nsteps < 0");
+  if (!c->have_state) return fail(GRMHD_E_STATE, "no state (set_state first)");
+  if (c->L.scr_total > (size_t)GRMHD_NOALLOC_SCRATCH_BYTES)
+    return fail(GRMHD_E_SIZE, "grid too large for grmhd_step_noalloc: its stage temporaries need " +
+                                  std::to_string(c->L.scr_total) + " bytes, the library's array holds " +
+                                  std::to_string((size_t)GRMHD_NOALLOC_SCRATCH_BYTES));
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != c->device) return fail(GRMHD_E_ARG, "grmhd_step_noalloc: make the context's device current");
+  double* ptr = nullptr;
+  int rc = noalloc_scratch(dev, &ptr);
+  if (rc) return rc;
+  // the array is shared by every call on this GPU: nothing in it belongs to
+  // this context (a fixed background's derivatives are recomputed)
+  double* own = c->scr;
+  const bool own_bg = c->bg_ready;
+  c->scr = ptr;
+  c->bg_ready = false;
+  for (int n = 0; n < nsteps && rc == GRMHD_OK; ++n) rc = one_step(c, nullptr);
+  c->scr = own;
+  c->bg_ready = own_bg;  // the context's own buffer was not touched
+  return rc;
 }
 
 int grmhd_step_batch(grmhd_ctx* const* ctxs, int32_t n, int32_t nsteps) {

@@ -32,7 +32,9 @@ def _ptr(t):
 class Solver:
     """One evolution context on the current CUDA (HIP) device and stream."""
 
-    def __init__(self, grid, phys, prec=_lib.GRMHD_FP64, stream=None):
+    def __init__(self, grid, phys, prec=_lib.GRMHD_FP64, stream=None, scratch=True):
+        """scratch=False: no scratch buffer (the context is stepped by
+        step_noalloc only, its state set with set_state and an explicit K0)."""
         import torch
         self.torch = torch
         lib = _lib.load()
@@ -48,13 +50,13 @@ class Solver:
         # one block: resident buffer, then scratch (contexts laid out alike can
         # be stepped together by step_batch)
         rb = (res.value + 255) // 256 * 256
-        self.block = torch.empty(rb + scr.value, dtype=torch.uint8, device="cuda")
+        self.block = torch.empty(rb + (scr.value if scratch else 0), dtype=torch.uint8, device="cuda")
         self.resident = self.block[:rb]
-        self.scratch = self.block[rb:]
+        self.scratch = self.block[rb:] if scratch else None
         ctx = ctypes.c_void_p()
         check(lib.grmhd_create(ctypes.byref(grid), ctypes.byref(phys), prec, _ptr(self.resident),
-                               _ptr(self.scratch), ctypes.c_void_p(self.stream.cuda_stream),
-                               ctypes.byref(ctx)))
+                               _ptr(self.scratch) if scratch else None,
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
         self.ctx = ctx
         dU, dK = ctypes.c_void_p(), ctypes.c_void_p()
         check(lib.grmhd_state_ptr(ctx, ctypes.byref(dU), ctypes.byref(dK)))
@@ -103,6 +105,11 @@ class Solver:
 
     def step(self, n=1):
         check(self.lib.grmhd_step(self.ctx, int(n)))
+
+    def step_noalloc(self, n=1):
+        """RK4 steps with the stage temporaries in the library's own device
+        array (no scratch buffer of the context is used)."""
+        check(self.lib.grmhd_step_noalloc(self.ctx, int(n)))
 
     def diagnostics(self):
         d = Diag()
