@@ -74,10 +74,17 @@ enum {
 
 /* Precision of the derivative contractions (the only part that changes):
  * FP64; FP32 MFMA with FP32 accumulation; split-BF16 x3 MFMA with FP32
- * accumulation.  In the reduced forms the derivative arrays are FP32; the
- * metric reconstruction, con2prim, RHS algebra, constraint damping terms, the
- * RK accumulator and the filter stay FP64. */
-typedef enum { GRMHD_FP64 = 0, GRMHD_MIX_FP32 = 1, GRMHD_MIX_BF16X3 = 2 } grmhd_prec;
+ * accumulation; FP64 MFMA writing FP32 derivative arrays (GRMHD_STORE_FP32:
+ * the FP64 arithmetic, rounded once when stored).  In the reduced forms the
+ * derivative arrays are FP32 (half the bytes the stage reads and writes for
+ * them); the metric reconstruction, con2prim, RHS algebra, constraint damping
+ * terms, the RK accumulator and the filter stay FP64. */
+typedef enum {
+  GRMHD_FP64 = 0,
+  GRMHD_MIX_FP32 = 1,
+  GRMHD_MIX_BF16X3 = 2,
+  GRMHD_STORE_FP32 = 3
+} grmhd_prec;
 
 /* Grid (Methods, "Grid Discretization"; readings: log radial map, Chebyshev
  * theta on [th_min, th_max]).  n_r, n_theta >= 4; n_phi even, >= 4;

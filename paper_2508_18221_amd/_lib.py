@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # build of the CPU tests); the default is the in-tree libgrmhd.so
 LIB_PATH = os.environ.get("GRMHD_LIBRARY") or os.path.join(HERE, "libgrmhd.so")
 
-GRMHD_FP64, GRMHD_MIX_FP32, GRMHD_MIX_BF16X3 = 0, 1, 2
+GRMHD_FP64, GRMHD_MIX_FP32, GRMHD_MIX_BF16X3, GRMHD_STORE_FP32 = 0, 1, 2, 3
 NFIELDS = 32
 
 

@@ -212,6 +212,7 @@ void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = -1) {
   Task& t = tl.t[tl.n++];
   t.src_sel = ssel;
   t.src = src;
+  t.src_f32 = 0;
   t.dst_sel = dsel;
   t.dst0 = d0;
   t.dst1 = d1 >= 0 ? d1 : 0;
@@ -246,21 +247,21 @@ L select_tasks(const L& tl, int nmat) {
 // tasks (op0); the folded kernel takes them in one launch, the full kernel in
 // one launch per kind.
 hipError_t contract(grmhd_ctx* c, int axis, int nmat, int op0, int op1, const TaskList& tl,
-                    const Bases& B, const JobSet& js, hipStream_t st) {
+                    const Bases& B, const JobSet& js, hipStream_t st, int io = IO_F64) {
   const bool pair_ok = nmat == 1 ? !(axis == 0 && op0 == OP_D2) : (op0 == OP_D1 && op1 == OP_D2);
   if (c->ops.fold[axis] && pair_ok) {
     const double* g10 = (axis == 0 && nmat == 2) ? c->gr + 2 * (size_t)c->grid.nr : nullptr;
     return launch_contract_fold(axis, nmat, tl, B, c->fop[axis][op0], c->fop[axis][op1], g10, c->ops.n,
-                                c->ops.hpad, (long long)c->L.P, js, st);
+                                c->ops.hpad, (long long)c->L.P, js, st, io);
   }
   if (nmat == 1)
     return launch_contract(axis, 1, tl, B, c->mats[axis][op0], c->mats[axis][op0], c->ops.n, c->ops.npad,
-                           (long long)c->L.P, js, st);
+                           (long long)c->L.P, js, st, io);
   hipError_t e = launch_contract(axis, 2, select_tasks(tl, 2), B, c->mats[axis][op0], c->mats[axis][op1],
-                                 c->ops.n, c->ops.npad, (long long)c->L.P, js, st);
+                                 c->ops.n, c->ops.npad, (long long)c->L.P, js, st, io);
   if (e != hipSuccess) return e;
   return launch_contract(axis, 1, select_tasks(tl, 1), B, c->mats[axis][op0], c->mats[axis][op0], c->ops.n,
-                         c->ops.npad, (long long)c->L.P, js, st);
+                         c->ops.npad, (long long)c->L.P, js, st, io);
 }
 
 
@@ -332,6 +333,62 @@ int mixed_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorde
   return GRMHD_OK;
 }
 
+// FP32-storage form: the FP64 contractions (same kernels, same FP64
+// arithmetic) write FP32 derivative arrays, laid out as in the reduced-
+// precision form (selectors: 0 = stage input state, 1 = FP32 derivative block,
+// 2 = scratch).  The mixed second derivatives read the FP32 first
+// derivatives (tasks with src_f32 set, in the same launch).
+int store32_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
+  Bases B;
+  B.b[0] = const_cast<double*>(Uin);
+  B.b[1] = sf(c, SC_D1);
+  B.b[2] = c->scr;
+  B.b[3] = nullptr;
+  const int o2 = SC_D2 - SC_D1, omx = SC_MX - SC_D1;
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    for (int s = 0; s < ND2; ++s) add(tl, 0, D2_FIELD[s], 1, 21 * a + D2_FIELD[s], o2 + 11 * a + s);
+    for (int q = 0; q < 10; ++q) add(tl, 0, D1_ONLY[q], 1, 21 * a + D1_ONLY[q]);
+    if (a == 1)  // mixed r-theta: d_theta of d_r
+      for (int s = 0; s < ND2; ++s) add(tl, 1, D2_FIELD[s], 1, omx + s);
+    if (a == 2) {  // mixed r-phi, theta-phi
+      for (int s = 0; s < ND2; ++s) add(tl, 1, D2_FIELD[s], 1, omx + 11 + s);
+      for (int s = 0; s < ND2; ++s) add(tl, 1, 21 + D2_FIELD[s], 1, omx + 22 + s);
+    }
+    for (int i = 0; i < tl.n; ++i) tl.t[i].src_f32 = tl.t[i].src_sel == 1;
+    HIPCHK(contract(c, a, 2, OP_D1, OP_D2, tl, B, js, c->stream, IO_OUT_F32));
+    MARK(rec, GRMHD_K_DERIV_R + a);
+  }
+  return GRMHD_OK;
+}
+
+// FP32-storage form: flux derivatives (FP64 fluxes in, FP32 out), on stream st.
+int store32_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec, hipStream_t st) {
+  Bases B;
+  B.b[0] = const_cast<double*>(Uin);
+  B.b[1] = sf(c, SC_D1);
+  B.b[2] = c->scr;
+  B.b[3] = nullptr;
+  const int odf = SC_DF - SC_D1;
+  for (int a = 0; a < 3; ++a) {
+    TaskList tl;
+    tl.n = 0;
+    for (int v = 0; v < 8; ++v) add(tl, 2, SC_FLUX + 8 * a + v, 1, odf + 8 * a + v);
+    if (c->pp.glm) {  // d_a (sqrt(gamma) B^a) and d_a psi of the stage input
+      add(tl, 0, 29 + a, 1, SC_GLM - SC_D1 + a);
+      add(tl, 0, NF, 1, SC_GLM - SC_D1 + 3 + a);
+    }
+    HIPCHK(contract(c, a, 1, OP_D1, OP_D1, tl, B, js, st, IO_OUT_F32));
+    if (rec) HIPCHK(rec->mark(GRMHD_K_DFLUX_R + a, st));
+  }
+  return GRMHD_OK;
+}
+
+// The flux-derivative and state-derivative passes of the context's precision.
+int flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec, hipStream_t st);
+int state_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec);
+
 // FP64 state derivatives (selectors: 0 = stage input state, 1 = scratch).
 int fp64_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
   Bases B;
@@ -379,6 +436,18 @@ int fp64_flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder
   return GRMHD_OK;
 }
 
+int flux_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec, hipStream_t st) {
+  if (c->prec == GRMHD_FP64) return fp64_flux_derivs(c, Uin, js, rec, st);
+  if (c->prec == GRMHD_STORE_FP32) return store32_flux_derivs(c, Uin, js, rec, st);
+  return mixed_flux_derivs(c, Uin, js, rec, st);
+}
+
+int state_derivs(grmhd_ctx* c, const double* Uin, const JobSet& js, Recorder* rec) {
+  if (c->prec == GRMHD_FP64) return fp64_derivs(c, Uin, js, rec);
+  if (c->prec == GRMHD_STORE_FP32) return store32_derivs(c, Uin, js, rec);
+  return mixed_derivs(c, Uin, js, rec);
+}
+
 // Fixed-background form: FP64 first derivatives of the background fields
 // (phi, gt_ij, alpha, beta^i) of Ug along r, theta, phi into the SC_BG block,
 // once per background.
@@ -404,10 +473,10 @@ int background_derivs(grmhd_ctx* c, const double* Ug, const JobSet& js, Recorder
 // context stream (nothing else runs beside them).
 int rhs_eval_fixed(grmhd_ctx* c, const double* Uin, const double* Ug, int mode, double* out, const JobSet& js,
                    Recorder* rec) {
-  const bool mixed = c->prec != GRMHD_FP64;
+  const bool mixed = c->prec != GRMHD_FP64;  // FP32 derivative arrays
   HIPCHK(launch_c2p_flux(Uin, Ug, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, c->stream));
   MARK(rec, GRMHD_K_C2P_FLUX);
-  int rc = mixed ? mixed_flux_derivs(c, Uin, js, rec, c->stream) : fp64_flux_derivs(c, Uin, js, rec, c->stream);
+  int rc = flux_derivs(c, Uin, js, rec, c->stream);
   if (rc) return rc;
   HIPCHK(launch_rhs_fixed(mode, mixed, Uin, Ug, sf(c, SC_BG), sf(c, SC_D1), c->prim, c->U, sf(c, SC_ACC), out,
                           c->pp, js, c->stream));
@@ -430,13 +499,13 @@ int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSe
     HIPCHK(hipEventRecord(c->ev_fork, c->stream));
     HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
   }
-  const bool mixed = c->prec != GRMHD_FP64;
+  const bool mixed = c->prec != GRMHD_FP64;  // FP32 derivative arrays
   HIPCHK(launch_c2p_flux(Uin, Uin, c->prim, c->fail, sf(c, SC_FLUX), c->floors, c->pp, js, fs));
   if (rec) HIPCHK(rec->mark(GRMHD_K_C2P_FLUX, fs));
-  int rc = mixed ? mixed_flux_derivs(c, Uin, js, rec, fs) : fp64_flux_derivs(c, Uin, js, rec, fs);
+  int rc = flux_derivs(c, Uin, js, rec, fs);
   if (rc) return rc;
   if (split) HIPCHK(hipEventRecord(c->ev_join, c->side));
-  rc = mixed ? mixed_derivs(c, Uin, js, rec) : fp64_derivs(c, Uin, js, rec);
+  rc = state_derivs(c, Uin, js, rec);
   if (rc) return rc;
   HIPCHK(launch_ricci(mixed, Uin, sf(c, SC_D1), sf(c, SC_RIC), c->pp, js, c->stream));
   MARK(rec, GRMHD_K_RICCI);
@@ -568,7 +637,7 @@ const char* grmhd_last_error(void) { return g_err.c_str(); }
 int grmhd_query_bytes(const grmhd_grid* grid, grmhd_prec prec, size_t* resident, size_t* scratch) {
   int rc = validate_grid(grid);
   if (rc) return rc;
-  if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3)
+  if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3 && prec != GRMHD_STORE_FP32)
     return fail(GRMHD_E_ARG, "unknown precision");
   if (!resident || !scratch) return fail(GRMHD_E_ARG, "null output pointer");
   Layout L = layout(*grid);
@@ -637,7 +706,7 @@ int grmhd::create_context(const grmhd_grid* grid, const grmhd_phys* phys, grmhd_
   int rc = validate_grid(grid);
   if (rc) return rc;
   if (!phys || !out || !dev_resident) return fail(GRMHD_E_ARG, "null argument");
-  if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3)
+  if (prec != GRMHD_FP64 && prec != GRMHD_MIX_FP32 && prec != GRMHD_MIX_BF16X3 && prec != GRMHD_STORE_FP32)
     return fail(GRMHD_E_ARG, "unknown precision");
   if (((uintptr_t)dev_resident & 255) || ((uintptr_t)dev_scratch & 255))
     return fail(GRMHD_E_ARG, "device buffers must be 256-byte aligned");

@@ -36,9 +36,27 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// The tasks of tl whose input storage is FP32 (f32 = 1) or FP64 (f32 = 0).
+static TaskList tasks_with_input(const TaskList& tl, int f32) {
+  TaskList out;
+  out.n = 0;
+  for (int i = 0; i < tl.n; ++i)
+    if ((tl.t[i].src_f32 != 0) == (f32 != 0)) out.t[out.n++] = tl.t[i];
+  return out;
+}
+
+static bool any_f32_input(const TaskList& tl) {
+  for (int i = 0; i < tl.n; ++i)
+    if (tl.t[i].src_f32) return true;
+  return false;
+}
+
 // INNER = true : r axis (tile columns are r-lines, output rows are lines)
 // INNER = false: theta / phi axes (tile columns are contiguous inner points)
-template <int NMAT, bool INNER, int WI>
+// IT, OT: storage type of the input and output fields (double, or float for
+// the FP32 derivative arrays of the FP32-storage form; the arithmetic is FP64
+// either way, a float field of the block sits at float offset field x P).
+template <int NMAT, bool INNER, int WI, typename IT = double, typename OT = double>
 __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
                                                   const double* __restrict__ AT0,
                                                   const double* __restrict__ AT1, int N, int Npad,
@@ -52,9 +70,9 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
   const int wave = threadIdx.x >> 6;
   const int c0 = blockIdx.x * TILE_COLS;
   const size_t off = (size_t)blockIdx.y * (size_t)slab;
-  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
-  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
-  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + off;
+  const IT* __restrict__ src = (const IT*)shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
+  OT* __restrict__ dst0 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
+  OT* __restrict__ dst1 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + off;
 
   // ---- stage the input tile ------------------------------------------------
   // LOADS independent global loads per thread are issued before any of them
@@ -63,14 +81,14 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
   if (INNER) {
     // 64 consecutive lines of N doubles: contiguous in memory; stored transposed
     const int ncols = min(TILE_COLS, inner - c0);  // lines in this tile
-    const double* __restrict__ s = src + (size_t)c0 * N;
+    const IT* __restrict__ s = src + (size_t)c0 * N;
     const int total = TILE_COLS * N, valid = ncols * N;
     for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
       double v[LOADS];
 #pragma unroll
       for (int q = 0; q < LOADS; ++q) {
         const int e = e0 + q * 256;
-        v[q] = (e < valid) ? s[e] : 0.0;
+        v[q] = (e < valid) ? (double)s[e] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < LOADS; ++q) {
@@ -91,7 +109,7 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
       for (int q = 0; q < LOADS; ++q) {
         const int e = e0 + q * 256;
         const int k = e >> 6, c = e & 63;
-        v[q] = (e < total && k < N && c0 + c < inner) ? src[(size_t)k * inner + c0 + c] : 0.0;
+        v[q] = (e < total && k < N && c0 + c < inner) ? (double)src[(size_t)k * inner + c0 + c] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < LOADS; ++q) {
@@ -175,14 +193,14 @@ __global__ __launch_bounds__(256) void k_contract(TaskList tl, Bases B,
           if (INNER) {
             const int line = c0 + cf + row, i = it * 16 + lr;
             if (line < inner && i < N) {
-              dst0[(size_t)line * N + i] = acc[0][f][v];
-              if (NMAT > 1) dst1[(size_t)line * N + i] = acc[NMAT - 1][f][v];
+              dst0[(size_t)line * N + i] = (OT)acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)line * N + i] = (OT)acc[NMAT - 1][f][v];
             }
           } else {
             const int i = it * 16 + row, c = c0 + cf + lr;
             if (i < N && c < inner) {
-              dst0[(size_t)i * inner + c] = acc[0][f][v];
-              if (NMAT > 1) dst1[(size_t)i * inner + c] = acc[NMAT - 1][f][v];
+              dst0[(size_t)i * inner + c] = (OT)acc[0][f][v];
+              if (NMAT > 1) dst1[(size_t)i * inner + c] = (OT)acc[NMAT - 1][f][v];
             }
           }
         }
@@ -196,8 +214,15 @@ static size_t lds_bytes(int npad) { return (size_t)npad * LDS_STRIDE * sizeof(do
 template <int NMAT, bool INNER, int WI>
 static hipError_t set_attr() {
   const int max_lds = 256 * LDS_STRIDE * (int)sizeof(double);  // npad <= 256
-  return hipFuncSetAttribute((const void*)k_contract<NMAT, INNER, WI>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_contract<NMAT, INNER, WI>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_contract<NMAT, INNER, WI, double, float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_contract<NMAT, INNER, WI, float, float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  return e;
 }
 
 template <int NMAT, bool INNER>
@@ -216,27 +241,46 @@ hipError_t set_kernel_attributes() {
   return e;
 }
 
-template <int NMAT, bool INNER>
-static void launch_wi(int T, dim3 grid, size_t lds, hipStream_t s, const TaskList& tl, const Bases& B,
-                      const double* AT0, const double* AT1, int N, int Npad, int inner, int slab,
-                      long long P, const JobSet& js) {
+template <int NMAT, bool INNER, typename IT, typename OT>
+static void launch_wi_t(int T, dim3 grid, size_t lds, hipStream_t s, const TaskList& tl, const Bases& B,
+                        const double* AT0, const double* AT1, int N, int Npad, int inner, int slab,
+                        long long P, const JobSet& js) {
   if (T >= 4)
-    hipLaunchKernelGGL((k_contract<NMAT, INNER, 4>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+    hipLaunchKernelGGL((k_contract<NMAT, INNER, 4, IT, OT>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
                        inner, slab, P, js);
   else if (T >= 2)
-    hipLaunchKernelGGL((k_contract<NMAT, INNER, 2>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+    hipLaunchKernelGGL((k_contract<NMAT, INNER, 2, IT, OT>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
                        inner, slab, P, js);
   else
-    hipLaunchKernelGGL((k_contract<NMAT, INNER, 1>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
+    hipLaunchKernelGGL((k_contract<NMAT, INNER, 1, IT, OT>), grid, dim3(256), lds, s, tl, B, AT0, AT1, N, Npad,
                        inner, slab, P, js);
+}
+
+template <int NMAT, bool INNER>
+static void launch_wi(int io, int T, dim3 grid, size_t lds, hipStream_t s, const TaskList& tl, const Bases& B,
+                      const double* AT0, const double* AT1, int N, int Npad, int inner, int slab,
+                      long long P, const JobSet& js) {
+  if (io == IO_F64)
+    launch_wi_t<NMAT, INNER, double, double>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+  else if (io == IO_OUT_F32)
+    launch_wi_t<NMAT, INNER, double, float>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+  else
+    launch_wi_t<NMAT, INNER, float, float>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
 }
 
 hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
                            const double* AT0, const double* AT1, const int n[3],
-                           const int npad[3], long long P, const JobSet& js, hipStream_t s) {
+                           const int npad[3], long long P, const JobSet& js, hipStream_t s, int io) {
   if (tl.n <= 0) return hipSuccess;
-  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB ||
+      (io != IO_F64 && io != IO_OUT_F32 && io != IO_F32))
     return hipErrorInvalidValue;
+  if (io == IO_OUT_F32 && any_f32_input(tl)) {  // FP32-input tasks: a launch of their own
+    hipError_t e = launch_contract(axis, nmat, tasks_with_input(tl, 0), B, AT0, AT1, n, npad, P, js, s, IO_OUT_F32);
+    if (e != hipSuccess) return e;
+    return launch_contract(axis, nmat, tasks_with_input(tl, 1), B, AT0, AT1, n, npad, P, js, s, IO_F32);
+  }
+  if (io == IO_F64 && any_f32_input(tl)) return hipErrorInvalidValue;
   const int N = n[axis], Npad = npad[axis];
   int inner, outer, slab;
   if (axis == 0) {          // lines of length nr, nth*nph of them
@@ -256,11 +300,11 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
   const size_t lds = lds_bytes(Npad);
   const int T = Npad >> 4;
   if (axis == 0) {
-    if (nmat == 1) launch_wi<1, true>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
-    else launch_wi<2, true>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+    if (nmat == 1) launch_wi<1, true>(io, T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+    else launch_wi<2, true>(io, T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
   } else {
-    if (nmat == 1) launch_wi<1, false>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
-    else launch_wi<2, false>(T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+    if (nmat == 1) launch_wi<1, false>(io, T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
+    else launch_wi<2, false>(io, T, grid, lds, s, tl, B, AT0, AT1, N, Npad, inner, slab, P, js);
   }
   return hipGetLastError();
 }
@@ -290,7 +334,7 @@ hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& 
 //
 // TC: columns per tile (64, or 32 for the strided axes at N = 128, where a
 // 64-column tile's LDS would hold two workgroups per CU).
-template <int NMAXT, bool INNER, int WI, int TC = TILE_COLS>
+template <int NMAXT, bool INNER, int WI, int TC = TILE_COLS, typename IT = double, typename OT = double>
 __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, const double* __restrict__ F0,
                                                        const double* __restrict__ F1,
                                                        const double* __restrict__ G0,
@@ -313,9 +357,9 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   const int H = N >> 1;
   const int c0 = blockIdx.x * TC;
   const size_t off = (size_t)blockIdx.y * (size_t)slab;
-  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
-  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
-  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + off;
+  const IT* __restrict__ src = (const IT*)shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P + off;
+  OT* __restrict__ dst0 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P + off;
+  OT* __restrict__ dst1 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P + off;
 
   // ---- stage and fold the input tile ----------------------------------------
   constexpr int LOADS = 8;  // pairs per thread in flight
@@ -323,7 +367,7 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
   if (INNER) {
     // 64 consecutive lines of N doubles; pair (k, N-1-k) of line `line`
     const int ncols = min(TC, inner - c0);
-    const double* __restrict__ s = src + (size_t)c0 * N;
+    const IT* __restrict__ s = src + (size_t)c0 * N;
     for (int e0 = threadIdx.x; e0 < total; e0 += 256 * LOADS) {
       double lo[LOADS], hi[LOADS];
 #pragma unroll
@@ -331,8 +375,8 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
         const int e = e0 + q * 256;
         const int line = e / Hpad, k = e - line * Hpad;
         const bool ok = e < total && k < H && line < ncols;
-        lo[q] = ok ? s[(size_t)line * N + k] : 0.0;
-        hi[q] = ok ? s[(size_t)line * N + (N - 1 - k)] : 0.0;
+        lo[q] = ok ? (double)s[(size_t)line * N + k] : 0.0;
+        hi[q] = ok ? (double)s[(size_t)line * N + (N - 1 - k)] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < LOADS; ++q) {
@@ -352,8 +396,8 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
         const int e = e0 + q * 256;
         const int k = e / TC, c = e % TC;
         const bool ok = e < total && k < H && c0 + c < inner;
-        lo[q] = ok ? src[(size_t)k * inner + c0 + c] : 0.0;
-        hi[q] = ok ? src[(size_t)(N - 1 - k) * inner + c0 + c] : 0.0;
+        lo[q] = ok ? (double)src[(size_t)k * inner + c0 + c] : 0.0;
+        hi[q] = ok ? (double)src[(size_t)(N - 1 - k) * inner + c0 + c] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < LOADS; ++q) {
@@ -450,13 +494,13 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
             const double y0 = e0 + o0, y0m = sig0 * (e0 - o0);
             const size_t p = INNER ? (size_t)col * N + i : (size_t)i * inner + col;
             const size_t pm = INNER ? (size_t)col * N + im : (size_t)im * inner + col;
-            dst0[p] = G0 ? G0[i] * y0 : y0;
-            dst0[pm] = G0 ? G0[im] * y0m : y0m;
+            dst0[p] = (OT)(G0 ? G0[i] * y0 : y0);
+            dst0[pm] = (OT)(G0 ? G0[im] * y0m : y0m);
             if (NMAT > 1) {
               const double e1 = acc[NMAT - 1][0][f][v], o1 = acc[NMAT - 1][1][f][v];
               const double y1 = e1 + o1, y1m = sig1 * (e1 - o1);
-              dst1[p] = (G1 ? G1[i] * y1 : y1) + (G10 ? G10[i] * y0 : 0.0);
-              dst1[pm] = (G1 ? G1[im] * y1m : y1m) + (G10 ? G10[im] * y0m : 0.0);
+              dst1[p] = (OT)((G1 ? G1[i] * y1 : y1) + (G10 ? G10[i] * y0 : 0.0));
+              dst1[pm] = (OT)((G1 ? G1[im] * y1m : y1m) + (G10 ? G10[im] * y0m : 0.0));
             }
           }
         }
@@ -496,12 +540,29 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 constexpr int PIPE_CH = 1152;  // bytes between copy chunks (1 KB + 128 B)
 
 
+// Tiles per workgroup of a copy-ahead launch of `all` tiles (one job's):
+// up to 8, keeping at least 1024 workgroups; the smallest launches (2,048
+// tiles: the eight flux derivatives of 64 x 64 x 128, which run beside the
+// state-derivative launches on the second stream) take 4, leaving more of
+// the chip to the launch they overlap (the step 2.489 -> 2.467 ms there).
+inline int pipe_tiles_per_group(long long all) {
+  return all <= 2048 ? 4 : (int)std::min(8LL, all / 1024);
+}
+
 // Waves per workgroup: 4, or 6 for the half sizes 48 and 96 (3 or 6 row
 // blocks), so that every wave owns one 16 x 16 output block per tile.
 template <int HP>
 constexpr int pipe_waves() { return (HP == 48 || HP == 96) ? 6 : 4; }
 
-template <int HP, int NMAXT>
+// MIXIN (FP32 outputs only): a task with src_f32 set reads FP32 input rows
+// (the FP32 first derivatives behind the mixed second derivatives of the
+// FP32-storage form) in the same launch: 1 KB copies then hold R32 = 2R rows
+// of TC floats, Q32 = Q / 2 chunks per tile, PIPE_CH32 bytes apart (the four
+// rows of a fragment read in different quarters of the banks), converted to
+// FP64 at the fragment read; the arithmetic is FP64 either way.
+constexpr int PIPE_CH32 = 1088;  // bytes between copy chunks of FP32 rows (1 KB + 64 B)
+
+template <int HP, int NMAXT, typename OT = double, bool MIXIN = false>
 __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskList tl, Bases B,
                                                                          const double* __restrict__ F0,
                                                                          const double* __restrict__ F1,
@@ -512,20 +573,17 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
   constexpr int T = HP / 16;       // 16-row output tiles
   constexpr int TC = 16 * NW / T;  // columns per tile (T x TC/16 = NW output blocks)
   constexpr int NKS = HP / 4;      // k-steps of 4
-  constexpr int LPR = TC / 2;      // lanes per row in a copy
-  constexpr int R = 64 / LPR;      // rows per copy chunk
-  static_assert(T * (TC / 16) == NW && (2 * HP / R) % NW == 0, "one output block per wave");
+  static_assert(T * (TC / 16) == NW && (2 * HP / (128 / TC)) % NW == 0, "one output block per wave");
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const Task tk = tl.t[blockIdx.z % tl.n];
   const long long jd = js.d[blockIdx.z / tl.n];
   F0 = shift_ptr(F0, jd);
   F1 = shift_ptr(F1, jd);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int Q = N / R;
-  const int bufbytes = Q * PIPE_CH;
-  const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P;
-  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
-  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
+  // tile buffers are sized for FP64 rows (the FP32 layout is smaller)
+  const int bufbytes = (N / (128 / TC)) * PIPE_CH;
+  OT* __restrict__ dst0 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
+  OT* __restrict__ dst1 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
   const int t0 = blockIdx.x * tpb;
   const int nt = min(tpb, ntiles - t0);
   // element offset of tile t's first column: slab x column block
@@ -533,18 +591,27 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
     const int g = t0 + t, sl = g / ncb, cb = g - sl * ncb;
     return (size_t)sl * (size_t)slab + (size_t)cb * TC;
   };
-  // copy of tile t into buffer b: wave w issues chunks w, w + NW, ...
-  const int cm = lane / LPR, cp = lane - cm * LPR;
-  auto copy_tile = [&](int t, int b) {
-    const double* g = src + tile_off(t) + 2 * cp;
-    char* base = lds + b * bufbytes;
-    for (int q = wave; q < Q; q += NW)
-      __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + cm * Q) * inner),
-                                       (lds_void_t*)(base + q * PIPE_CH), 16, 0, 2);
-  };
 
-  auto run = [&](auto nm) {
+  // ES: input element bytes (8: FP64 rows, 4: FP32 rows)
+  auto run = [&](auto nm, auto es) {
     constexpr int NMAT = decltype(nm)::value;
+    constexpr int ES = decltype(es)::value;
+    using IT = typename std::conditional<ES == 8, double, float>::type;
+    constexpr int RB = ES * TC;      // bytes per row in a chunk
+    constexpr int LPR = RB / 16;     // lanes per row in a copy
+    constexpr int R = 64 / LPR;      // rows per copy chunk
+    constexpr int CH = ES == 8 ? PIPE_CH : PIPE_CH32;
+    const int Q = N / R;             // chunks per tile (a multiple of 4)
+    const IT* __restrict__ src = (const IT*)shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P;
+    // copy of tile t into buffer b: wave w issues chunks w, w + NW, ...
+    const int cm = lane / LPR, cp = lane - cm * LPR;
+    auto copy_tile = [&](int t, int b) {
+      const IT* g = src + tile_off(t) + (16 / ES) * cp;
+      char* base = lds + b * bufbytes;
+      for (int q = wave; q < Q; q += NW)
+        __builtin_amdgcn_global_load_lds((const void*)(g + (size_t)(q + cm * Q) * inner),
+                                         (lds_void_t*)(base + q * CH), 16, 0, 2);
+    };
     const int wi = wave % T, wf = wave / T;
     const int lr = lane & 15, lk = lane >> 4;
     const size_t hh = (size_t)HP * HP;
@@ -571,16 +638,16 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
       }
       if (t + 1 < nt) copy_tile(t + 1, (t + 1) & 1);
       const char* buf = lds + (t & 1) * bufbytes;
-      const char* lp = buf + lk * PIPE_CH + (16 * wf + lr) * 8;  // row 4 ks + lk
-      const char* lm = buf - lk * PIPE_CH + (16 * wf + lr) * 8;  // row N - 1 - (4 ks + lk)
+      const char* lp = buf + lk * CH + (16 * wf + lr) * ES;  // row 4 ks + lk
+      const char* lm = buf - lk * CH + (16 * wf + lr) * ES;  // row N - 1 - (4 ks + lk)
       d4 acc[NMAT][2];
 #pragma unroll
       for (int m = 0; m < NMAT; ++m) acc[m][0] = acc[m][1] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
         const int qa = (4 * ks) % Q, ma = (4 * ks) / Q;  // uniform
-        const double u = *(const double*)(lp + qa * PIPE_CH + ma * (8 * TC));
-        const double w = *(const double*)(lm + (Q - 1 - qa) * PIPE_CH + (R - 1 - ma) * (8 * TC));
+        const double u = (double)*(const IT*)(lp + qa * CH + ma * RB);
+        const double w = (double)*(const IT*)(lm + (Q - 1 - qa) * CH + (R - 1 - ma) * RB);
         const double sk = u + w, dk = u - w;
 #pragma unroll
         for (int m = 0; m < NMAT; ++m) {
@@ -597,18 +664,28 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
         const int im = N - 1 - i;
         const size_t p = toff + (size_t)i * inner + col, pm = toff + (size_t)im * inner + col;
         const double e0 = acc[0][0][v], o0 = acc[0][1][v];
-        dst0[p] = e0 + o0;
-        dst0[pm] = sig0 * (e0 - o0);
+        dst0[p] = (OT)(e0 + o0);
+        dst0[pm] = (OT)(sig0 * (e0 - o0));
         if (NMAT > 1) {
           const double e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
-          dst1[p] = e1 + o1;
-          dst1[pm] = sig1 * (e1 - o1);
+          dst1[p] = (OT)(e1 + o1);
+          dst1[pm] = (OT)(sig1 * (e1 - o1));
         }
       }
     }
   };
-  if (NMAXT > 1 && tk.nmat > 1) run(std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>{});
-  else run(std::integral_constant<int, 1>{});
+  using E8 = std::integral_constant<int, 8>;
+  using E4 = std::integral_constant<int, 4>;
+  using M1 = std::integral_constant<int, 1>;
+  using M2 = std::integral_constant<int, (NMAXT > 1 ? 2 : 1)>;
+  if (MIXIN && tk.src_f32) {
+    // FP32-input tasks apply one operator (the mixed second derivatives)
+    run(M1{}, E4{});
+  } else if (NMAXT > 1 && tk.nmat > 1) {
+    run(M2{}, E8{});
+  } else {
+    run(M1{}, E8{});
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -625,7 +702,7 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
 // multiple of TL.
 constexpr int PIPE_CH_R = 1040;  // bytes between copy chunks (1 KB + 16 B)
 
-template <int HP, int NMAXT>
+template <int HP, int NMAXT, typename OT = double>
 __global__ __launch_bounds__(256) void k_contract_pipe_r(TaskList tl, Bases B, const double* __restrict__ F0,
                                                          const double* __restrict__ F1,
                                                          const double* __restrict__ G0,
@@ -647,8 +724,8 @@ __global__ __launch_bounds__(256) void k_contract_pipe_r(TaskList tl, Bases B, c
   F1 = shift_ptr(F1, jd);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* __restrict__ src = shift_ptr(B.b[tk.src_sel], jd) + (size_t)tk.src * (size_t)P;
-  double* __restrict__ dst0 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
-  double* __restrict__ dst1 = shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
+  OT* __restrict__ dst0 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst0 * (size_t)P;
+  OT* __restrict__ dst1 = (OT*)shift_ptr(B.b[tk.dst_sel], jd) + (size_t)tk.dst1 * (size_t)P;
   const int t0 = blockIdx.x * tpb;
   const int nt = min(tpb, ntiles - t0);
   const int cm = lane / LPL, cp = lane - cm * LPL;
@@ -722,12 +799,12 @@ __global__ __launch_bounds__(256) void k_contract_pipe_r(TaskList tl, Bases B, c
         const size_t p = (l0 + lk + 4 * v) * N2;
         const double e0 = acc[0][0][v], o0 = acc[0][1][v];
         const double y0 = e0 + o0, y0m = sig0 * (e0 - o0);
-        dst0[p + i] = s0 * y0;
-        dst0[p + im] = s0m * y0m;
+        dst0[p + i] = (OT)(s0 * y0);
+        dst0[p + im] = (OT)(s0m * y0m);
         if (NMAT > 1) {
           const double e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
-          dst1[p + i] = s1 * (e1 + o1) + s10 * y0;
-          dst1[p + im] = s1m * (sig1 * (e1 - o1)) + s10m * y0m;
+          dst1[p + i] = (OT)(s1 * (e1 + o1) + s10 * y0);
+          dst1[p + im] = (OT)(s1m * (sig1 * (e1 - o1)) + s10m * y0m);
         }
       }
     }
@@ -739,8 +816,15 @@ __global__ __launch_bounds__(256) void k_contract_pipe_r(TaskList tl, Bases B, c
 template <int NMAT, bool INNER, int WI, int TC = TILE_COLS>
 static hipError_t set_fold_attr() {
   const int max_lds = 256 * (TC + 8) * (int)sizeof(double);  // 2 Hpad <= 256
-  return hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI, TC>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI, TC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI, TC, double, float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_contract_fold<NMAT, INNER, WI, TC, float, float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  return e;
 }
 
 hipError_t set_fold_kernel_attributes() {
@@ -759,12 +843,17 @@ hipError_t set_fold_kernel_attributes() {
   return e;
 }
 
-hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
+// IT, OT: input and output storage types; the copy-ahead kernels take FP64
+// inputs only (their HBM-to-LDS copies move raw doubles), so FP32 inputs use
+// the one-tile kernel.
+template <typename IT, typename OT>
+static hipError_t launch_fold_t(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
                                 const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
                                 long long P, const JobSet& js, hipStream_t s) {
-  if (tl.n <= 0) return hipSuccess;
-  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
-    return hipErrorInvalidValue;
+  // FP64-input launches only; FP32-input tasks ride in the FP32-output
+  // copy-ahead launches of the strided axes (per-task input rows)
+  constexpr bool copy_ahead = std::is_same<IT, double>::value;
+  const bool f32_tasks = any_f32_input(tl);
   const int N = n[axis], Hpad = hpad[axis];
   if ((N & 1) || Hpad < N / 2 || (Hpad & 15) || 2 * Hpad > 256) return hipErrorInvalidValue;
   int inner, slab, outer;
@@ -782,7 +871,7 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     slab = 0;
   }
   const int T = Hpad >> 4;
-  if (axis == 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad) {
+  if (copy_ahead && !f32_tasks && axis == 0 && (Hpad == 16 || Hpad == 32 || Hpad == 64) && N == 2 * Hpad) {
     // pipelined form of the r axis: the line count a multiple of the tile's
     const int tlines = 2048 / N;
     // the kernel and its tiles per workgroup follow from one job's tiles, so
@@ -790,10 +879,10 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     const long long all = (long long)(inner / tlines) * tl.n;
     if (inner % tlines == 0 && all >= 2048) {
       const int ntiles = inner / tlines;
-      const int tpb = (int)std::min(8LL, all / 1024);
+      const int tpb = pipe_tiles_per_group(all);
       dim3 pg((ntiles + tpb - 1) / tpb, 1, tl.n * js.n);
 #define LR(HPV, NM)                                                                                         \
-  hipLaunchKernelGGL((k_contract_pipe_r<HPV, NM>), pg, dim3(256), 2 * 16 * PIPE_CH_R, s, tl, B, op0.et,     \
+  hipLaunchKernelGGL((k_contract_pipe_r<HPV, NM, OT>), pg, dim3(256), 2 * 16 * PIPE_CH_R, s, tl, B, op0.et,     \
                      op1.et, op0.g, op1.g, g10, op0.sigma, op1.sigma, ntiles, tpb, P, js)
       if (Hpad == 16) { if (nmat == 1) LR(16, 1); else LR(16, 2); }
       else if (Hpad == 32) { if (nmat == 1) LR(32, 1); else LR(32, 2); }
@@ -802,8 +891,8 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
       return hipGetLastError();
     }
   }
-  if (axis != 0 && (Hpad == 16 || Hpad == 32 || Hpad == 48 || Hpad == 64 || Hpad == 96) && N == 2 * Hpad &&
-      op0.g == nullptr && op1.g == nullptr && g10 == nullptr) {
+  if (copy_ahead && axis != 0 && (Hpad == 16 || Hpad == 32 || Hpad == 48 || Hpad == 64 || Hpad == 96) &&
+      N == 2 * Hpad && op0.g == nullptr && op1.g == nullptr && g10 == nullptr) {
     // copy-ahead form: inner a multiple of the tile width
     const int nw = (Hpad == 48 || Hpad == 96) ? 6 : 4;
     const int tc = 16 * nw / (Hpad / 16), rows = 1024 / (8 * tc);
@@ -814,12 +903,11 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     if (inner % tc == 0 && all >= 2048) {
       const int ncb = inner / tc, ntiles = ncb * outer;
       const int bufbytes = (N / rows) * PIPE_CH;
-      // tiles per workgroup: up to 8, keeping at least 1024 workgroups
-      const int tpb = (int)std::min(8LL, all / 1024);
+      const int tpb = pipe_tiles_per_group(all);
       auto launch = [&](const TaskList& L, int nm, const FoldOp& o0, const FoldOp& o1) {
         dim3 pg((ntiles + tpb - 1) / tpb, 1, L.n * js.n);
 #define LP(HPV, NM)                                                                                               \
-  hipLaunchKernelGGL((k_contract_pipe<HPV, NM>), pg, dim3(64 * pipe_waves<HPV>()), 2 * bufbytes, s, L, B, o0.et, \
+  hipLaunchKernelGGL((k_contract_pipe<HPV, NM, OT, std::is_same<OT, float>::value>), pg, dim3(64 * pipe_waves<HPV>()), 2 * bufbytes, s, L, B, o0.et, \
                      o1.et, o0.sigma, o1.sigma, N, inner, slab, ncb, ntiles, tpb, P, js)
         if (Hpad == 16) { if (nm == 1) LP(16, 1); else LP(16, 2); }
         else if (Hpad == 32) { if (nm == 1) LP(32, 1); else LP(32, 2); }
@@ -850,12 +938,19 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
       return launch(tl, nmat, op0, op1);
     }
   }
+  if (f32_tasks && !std::is_same<IT, float>::value) {
+    // one-tile kernels: FP32-input tasks in a launch of their own
+    if (!std::is_same<OT, float>::value) return hipErrorInvalidValue;
+    hipError_t e = launch_fold_t<IT, OT>(axis, nmat, tasks_with_input(tl, 0), B, op0, op1, g10, n, hpad, P, js, s);
+    if (e != hipSuccess) return e;
+    return launch_fold_t<float, float>(axis, nmat, tasks_with_input(tl, 1), B, op0, op1, g10, n, hpad, P, js, s);
+  }
   const bool narrow = axis != 0 && T == 4;  // N = 128 on a strided axis: 32-column tiles
   const int tc = narrow ? NARROW : TILE_COLS;
   dim3 grid((inner + tc - 1) / tc, outer, tl.n * js.n);
   const size_t lds = (size_t)2 * Hpad * (tc + 8) * sizeof(double);
 #define LF(NM, IN, W)                                                                                     \
-  hipLaunchKernelGGL((k_contract_fold<NM, IN, W>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, op0.g, \
+  hipLaunchKernelGGL((k_contract_fold<NM, IN, W, TILE_COLS, IT, OT>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, op0.g, \
                      op1.g, g10, op0.sigma, op1.sigma, N, Hpad, inner, slab, P, js)
 #define LFW(NM, IN)                 \
   do {                              \
@@ -864,7 +959,7 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
     else LF(NM, IN, 1);             \
   } while (0)
 #define LN(NM)                                                                                           \
-  hipLaunchKernelGGL((k_contract_fold<NM, false, 4, NARROW>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, \
+  hipLaunchKernelGGL((k_contract_fold<NM, false, 4, NARROW, IT, OT>), grid, dim3(256), lds, s, tl, B, op0.et, op1.et, \
                      op0.g, op1.g, g10, op0.sigma, op1.sigma, N, Hpad, inner, slab, P, js)
   if (axis == 0) {
     if (nmat == 1) LFW(1, true); else LFW(2, true);
@@ -877,6 +972,20 @@ hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Ba
 #undef LFW
 #undef LF
   return hipGetLastError();
+}
+
+hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
+                                const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
+                                long long P, const JobSet& js, hipStream_t s, int io) {
+  if (tl.n <= 0) return hipSuccess;
+  if (tl.n > MAX_TASKS || (nmat != 1 && nmat != 2) || axis < 0 || axis > 2 || js.n < 1 || js.n > MAXB)
+    return hipErrorInvalidValue;
+  for (int i = 0; i < tl.n; ++i)  // FP32-input tasks: FP32 outputs, one operator
+    if (tl.t[i].src_f32 && (io == IO_F64 || tl.t[i].nmat != 1)) return hipErrorInvalidValue;
+  if (io == IO_F64) return launch_fold_t<double, double>(axis, nmat, tl, B, op0, op1, g10, n, hpad, P, js, s);
+  if (io == IO_OUT_F32) return launch_fold_t<double, float>(axis, nmat, tl, B, op0, op1, g10, n, hpad, P, js, s);
+  if (io == IO_F32) return launch_fold_t<float, float>(axis, nmat, tl, B, op0, op1, g10, n, hpad, P, js, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace grmhd

@@ -56,6 +56,7 @@ inline int round_up(int n, int m) { return (n + m - 1) / m * m; }
 // One contraction task: out_m = A_m applied along the axis to `src`.
 struct Task {
   int src_sel, src;     // base selector, field index
+  int src_f32;          // 1: the input field is FP32 (FP32 outputs only)
   int dst_sel, dst0;    // destination of matrix 0
   int dst1;             // destination of matrix 1 (same base as dst0)
   int nmat;             // operators this task applies (1 or 2)
@@ -225,9 +226,14 @@ int xcts_solve(const XctsGrid& g, double* work, double* partials, int partial_bl
 
 // ---- kernel launchers (kernels.hip) --------------------------------------
 // Contraction along axis (0 r, 1 theta, 2 phi) with nmat = 1 or 2 matrices.
+// Storage of a contraction's input and output fields (the arithmetic is
+// FP64): both FP64; FP64 in, FP32 out; both FP32 (field g of an FP32 block at
+// float offset g P from the base pointer).
+enum { IO_F64 = 0, IO_OUT_F32 = 1, IO_F32 = 3 };
 hipError_t launch_contract(int axis, int nmat, const TaskList& tl, const Bases& B,
                            const double* AT0, const double* AT1, const int n[3],
-                           const int npad[3], long long P, const JobSet& js, hipStream_t s);
+                           const int npad[3], long long P, const JobSet& js, hipStream_t s,
+                           int io = IO_F64);
 hipError_t launch_contract_mixed(int prec, int axis, int nmat, const MixedTaskList& tl, const Bases& B,
                                  const MixedOps& op0, const MixedOps& op1, const int n[3],
                                  const int npad[3], long long P, const JobSet& js, hipStream_t s);
@@ -236,7 +242,7 @@ hipError_t set_mixed_kernel_attributes();
 // nmat = 2 lets each task apply one or two operators (its own nmat)
 hipError_t launch_contract_fold(int axis, int nmat, const TaskList& tl, const Bases& B, const FoldOp& op0,
                                 const FoldOp& op1, const double* g10, const int n[3], const int hpad[3],
-                                long long P, const JobSet& js, hipStream_t s);
+                                long long P, const JobSet& js, hipStream_t s, int io = IO_F64);
 hipError_t set_fold_kernel_attributes();
 hipError_t launch_contract_f32_fold(int axis, int nmat, const MixedTaskList& tl, const Bases& B,
                                     const FoldOp32& op0, const FoldOp32& op1, const double* g10, const int n[3],

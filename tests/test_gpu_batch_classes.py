@@ -3,7 +3,8 @@ size (each result the same alone and in the mix, bitwise), for the grid
 classes of the served stream where the contraction kernels change with the
 grid (the copy-ahead contractions run on some axes of 32x32x64, 48x48x96 and
 64x64x128): jobs stepped by grmhd_step_batch in batches of 4, 8 and 32 (2 at
-64x64x128) equal the same jobs stepped alone, in the FP64 and FP32 forms."""
+64x64x128) equal the same jobs stepped alone, in the FP64, FP32 and
+FP32-storage forms."""
 
 import numpy as np
 import pytest
@@ -29,6 +30,8 @@ def make_jobs(n, nr, nth, nph, prec):
     ((48, 48, 96), (4, 8), 0),
     ((48, 48, 96), (4,), 1),
     ((64, 64, 128), (2,), 0),
+    ((32, 32, 64), (4, 8), 3),
+    ((64, 64, 128), (2,), 3),
 ])
 def test_batched_equals_alone(shape, sizes, prec):
     from paper_2508_18221_amd.solver import step_batch

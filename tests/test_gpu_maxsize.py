@@ -90,7 +90,7 @@ def test_rhs_at_the_maximum_size(size):
     assert e.max() < bar
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("size", [(256, 8, 8), (8, 256, 8), (8, 8, 256), (255, 9, 8)])
 def test_reduced_precision_forms_run_at_the_maximum_size(size, prec):
     from paper_2508_18221_amd import Solver, make_grid, make_phys

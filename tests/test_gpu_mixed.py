@@ -1,8 +1,15 @@
-"""Mixed-precision form: derivative contractions in FP32 or split-BF16x3 on
-MFMA with FP32 accumulation; everything else FP64.  Bounds: after the
-evolution the density differs from the FP64 reference by at most 1e-6 in
-relative L2 (unweighted over the nodes) and the Hamiltonian-constraint L2
-norm is within a factor 2 of the FP64 run's."""
+"""Reduced-precision forms: derivative contractions in FP32 or split-BF16x3
+on MFMA with FP32 accumulation, or FP64 MFMA contractions whose derivative
+arrays are stored in FP32 (the FP32-storage form); everything else FP64.
+Bounds: after the evolution the density differs from the FP64 reference by
+at most 1e-6 in relative L2 (unweighted over the nodes) and the
+Hamiltonian-constraint L2 norm is within a factor 2 of the FP64 run's.
+
+The FP32-storage form meets them also on the magnetised torus at
+128 x 96 x 192 over 200 steps, where the FP32 form does not: rounding the
+contraction inputs to FP32 is amplified by the derivative operators (up to
+N^2 for D1 and N^4 for D2 relative to the field's variation), while rounding
+the derivatives themselves once costs only their own unit roundoff."""
 
 import numpy as np
 import pytest
@@ -13,7 +20,7 @@ pytestmark = [pytest.mark.gpu,
 
 from gpu_util import workload, oracle_problem, rhs_errors, log  # noqa: E402
 
-PRECS = {"fp32": 1, "bf16x3": 2}
+PRECS = {"fp32": 1, "bf16x3": 2, "store32": 3}
 
 
 def solver_prec(w, prec):
@@ -21,7 +28,7 @@ def solver_prec(w, prec):
     return Solver(make_grid(**w["grid"]), make_phys(**w["phys"]), prec=prec)
 
 
-@pytest.mark.parametrize("name", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["fp32", "bf16x3", "store32"])
 @pytest.mark.parametrize("size", [(16, 16, 16), (20, 18, 12)])
 def test_mixed_rhs_close_to_oracle(name, size):
     log(f"[mixed rhs] {name} grid {size}")
@@ -45,7 +52,13 @@ def test_mixed_rhs_close_to_oracle(name, size):
     # value), and the second-derivative operator amplifies an input error by
     # up to ||D2||_inf ~ N^4 / 3 (the CGL second-derivative matrix) relative to
     # the field's variation; the group scale of the right-hand side is at
-    # least that variation, so e_f <= eps_low N^4.
+    # least that variation, so e_f <= eps_low N^4.  The FP32-storage form
+    # rounds the FP64 derivatives once (eps_32 of each) and feeds the mixed
+    # second derivatives FP32 first derivatives (an input error amplified by
+    # ||D1|| ~ N^2): e_f <= eps_32 N^2.
+    if name == "store32":
+        assert e.max() < 2.0 ** -24 * max(size) ** 2
+        return
     eps = {"fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[name]
     assert e.max() < eps * max(size) ** 4
 
@@ -60,8 +73,8 @@ BF16_MISS = ("split-BF16x3 keeps about 16 significand bits of each operand (2^-1
              "100 steps, against the bounds 1e-6 and 2")
 
 
-@pytest.mark.parametrize("name", ["fp32", pytest.param("bf16x3", marks=pytest.mark.xfail(strict=True,
-                                                                                         reason=BF16_MISS))])
+@pytest.mark.parametrize("name", ["fp32", "store32",
+                                  pytest.param("bf16x3", marks=pytest.mark.xfail(strict=True, reason=BF16_MISS))])
 def test_mixed_evolution_within_bounds(name):
     log(f"[mixed evolve] {name} 16^3, 10 RK4 steps")
     w = workload("ks_michel_16x16x16")
@@ -105,13 +118,14 @@ def test_hamiltonian_diagnostic_matches_oracle():
     assert abs(d["ham_linf"] / np.abs(H).max() - 1) < 1e-9
 
 
-def test_fp32_form_full_size_within_bounds():
-    """The FP32 form at 64 x 64 x 128, where its contractions take the
-    copy-ahead pipelined kernels (FP64 and FP32 input rows, all three axes):
+@pytest.mark.parametrize("name", ["fp32", "store32"])
+def test_fp32_form_full_size_within_bounds(name):
+    """The FP32 and FP32-storage forms at 64 x 64 x 128, where their
+    contractions take the copy-ahead pipelined kernels (all three axes):
     after 10 RK4 steps from the same state the density stays within 1e-6
     (relative L2) of the FP64 path and the Hamiltonian-constraint norm within
     a factor 2 of the FP64 run's."""
-    log("[mixed evolve] fp32 64x64x128, 10 RK4 steps vs the FP64 path")
+    log(f"[mixed evolve] {name} 64x64x128, 10 RK4 steps vs the FP64 path")
     w = workload("ks_michel_64x64x128")
     s64 = solver_prec(w, 0)
     s64.init_state()
@@ -120,7 +134,7 @@ def test_fp32_form_full_size_within_bounds():
     ref = s64.get_state()
     d64 = s64.diagnostics()
     s64.close()
-    s = solver_prec(w, PRECS["fp32"])
+    s = solver_prec(w, PRECS[name])
     s.set_state(U0, K0)
     s.step(10)
     got = s.get_state()
@@ -138,3 +152,35 @@ def test_fp32_form_full_size_within_bounds():
     assert l2 < 1e-6
     assert d["ham_l2"] < 2.0 * d64["ham_l2"]
     assert d["nonfinite"] == 0 and d["c2p_fail"] == 0
+
+
+def test_fp32_storage_form_within_bounds_on_the_torus():
+    """The FP32-storage form on the magnetised torus at 128 x 96 x 192 (the
+    second measured configuration, atmosphere nodes included) over its 200
+    RK4 steps from the library's initial data: density within 1e-6 (relative
+    L2, unweighted) of the FP64 path, Hamiltonian-constraint norm within a
+    factor 2, the same atmosphere count.  (The FP32 form misses both here:
+    rho 1.1e-5, norm ratio 20.)"""
+    import workloads
+    w = workloads.WORKLOADS["ks_torus_128x96x192"]
+    steps = w["steps"]
+    log(f"[store32] torus 128x96x192, {steps} RK4 steps vs the FP64 path")
+    out = {}
+    for name, prec in (("fp64", 0), ("store32", 3)):
+        s = solver_prec(w, prec)
+        s.init_state()
+        s.step(steps)
+        d = s.diagnostics()
+        prim = torch.empty((5,) + s.shape, dtype=torch.float64, device="cuda")
+        s.con2prim(s.U, prim)
+        out[name] = (prim[0].clone(), d)
+        s.close()
+    r64, d64 = out["fp64"]
+    r32, d32 = out["store32"]
+    l2 = float(torch.sqrt(torch.sum((r32 - r64) ** 2) / torch.sum(r64 ** 2)))
+    log(f"  rho L2 rel {l2:.2e}; H L2 {d32['ham_l2']:.4e} vs FP64 {d64['ham_l2']:.4e}; "
+        f"atmosphere {d32['c2p_fail']} vs {d64['c2p_fail']}")
+    assert d32["nonfinite"] == 0
+    assert l2 < 1e-6
+    assert d32["ham_l2"] < 2.0 * d64["ham_l2"]
+    assert abs(d32["c2p_fail"] - d64["c2p_fail"]) <= 1e-3 * d64["c2p_fail"]
