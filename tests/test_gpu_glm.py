@@ -77,23 +77,26 @@ def test_glm_ten_steps_match_oracle():
     assert d["nonfinite"] == 0 and d["c2p_fail"] == 0
 
 
-def test_glm_fp32_form_close_to_fp64():
+@pytest.mark.parametrize("form", [1, 3])
+def test_glm_fp32_form_close_to_fp64(form):
+    """The FP32 and FP32-storage forms with GLM (the psi derivatives and the
+    divergence of the field ride in the FP32 flux-derivative arrays)."""
     from paper_2508_18221_amd import Solver, make_grid, make_phys
-    log("[glm mixed] fp32, 16^3, 10 RK4 steps vs the FP64 path")
+    log(f"[glm mixed] prec {form}, 16^3, 10 RK4 steps vs the FP64 path")
     w = glm_workload()
     g, pb, U, K0 = oracle_problem(w)
     U = seeded(g, U)
     out = {}
-    for prec in (0, 1):
+    for prec in (0, form):
         s = Solver(make_grid(**w["grid"]), make_phys(**w["phys"]), prec=prec)
         s.set_state(U, K0)
         s.step(10)
         out[prec] = s.get_state()
         s.close()
-    assert np.isfinite(out[1]).all()
-    rel = np.abs(out[1][32] - out[0][32]).max() / np.abs(out[0][32]).max()
-    log(f"  psi max rel difference FP32 vs FP64: {rel:.2e}")
-    assert rel < 1e-4
+    assert np.isfinite(out[form]).all()
+    rel = np.abs(out[form][32] - out[0][32]).max() / np.abs(out[0][32]).max()
+    log(f"  psi max rel difference vs FP64: {rel:.2e}")
+    assert rel < (1e-4 if form == 1 else 1e-6)
 
 
 def test_glm_damps_a_seeded_divergence():
