@@ -349,7 +349,8 @@ typedef struct grmhd_server grmhd_server;
 
 typedef struct {
   int64_t id;
-  int32_t state;            /* 0 queued, 1 running, 2 done, 3 rejected       */
+  int32_t state;            /* 0 queued, 1 running, 2 done, 3 rejected,
+                               4 cancelled                                   */
   int32_t nr, nth, nph, prec;
   int64_t steps_done, steps_total;
   double dt;                /* T / steps_total                               */
@@ -359,7 +360,7 @@ typedef struct {
 } grmhd_job_info;
 
 typedef struct {
-  int64_t submitted, completed, rejected, running, queued;
+  int64_t submitted, completed, rejected, running, queued, cancelled;
   double p50_latency, p99_latency, mean_latency;  /* completed jobs, seconds  */
   double point_stage_updates;  /* completed work: sum over jobs of 4 P steps */
   double wall;              /* first submission to last completion, seconds  */
@@ -405,6 +406,14 @@ int grmhd_server_submit(grmhd_server* srv, const grmhd_grid* grid, const grmhd_p
 int grmhd_server_tick(grmhd_server* srv, int32_t* n_pending);
 
 int grmhd_server_poll(grmhd_server* srv, int64_t job_id, grmhd_job_info* out);
+/* Cancel a queued or running job.  A queued job leaves the queue at once; a
+ * running job takes part in no further step and its context and arena block
+ * are released by the first tick at which none of its steps is still in
+ * flight on the device (until then it polls as running, with no steps to
+ * go).  Either way it ends in state 4 (cancelled), its memory available to
+ * the jobs admitted after it.  GRMHD_E_ARG for an unknown job, GRMHD_E_STATE
+ * for one already done, rejected or cancelled. */
+int grmhd_server_cancel(grmhd_server* srv, int64_t job_id);
 /* Final state of a finished job submitted with keep_state (n = 32 P; 33 P,
  * psi last, for a GLM job). */
 int grmhd_server_result(grmhd_server* srv, int64_t job_id, double* host_U, size_t n);

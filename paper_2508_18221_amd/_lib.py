@@ -56,7 +56,8 @@ class JobInfo(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
-                ("running", ctypes.c_int64), ("queued", ctypes.c_int64), ("p50_latency", ctypes.c_double),
+                ("running", ctypes.c_int64), ("queued", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("p50_latency", ctypes.c_double),
                 ("p99_latency", ctypes.c_double), ("mean_latency", ctypes.c_double),
                 ("point_stage_updates", ctypes.c_double), ("wall", ctypes.c_double), ("busy", ctypes.c_double),
                 ("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t)]
@@ -97,6 +98,7 @@ SIGNATURES = {
                                            ctypes.c_int32, _P(ctypes.c_int64)]),
     "grmhd_server_tick": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
     "grmhd_server_poll": (ctypes.c_int, [_vp, ctypes.c_int64, _P(JobInfo)]),
+    "grmhd_server_cancel": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "grmhd_server_result": (ctypes.c_int, [_vp, ctypes.c_int64, _dp, ctypes.c_size_t]),
     "grmhd_server_stats": (ctypes.c_int, [_vp, _P(ServerStats)]),
     "grmhd_server_clock": (ctypes.c_double, [_vp]),

@@ -63,7 +63,8 @@ def build(verbose=False, jobs=5, hostsan=False):
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     lib = HOSTSAN_LIB if hostsan else LIB
     tmp = lib + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    # roctx: the ranges around each RK stage and the filter (rocprofv3 --marker-trace)
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs + ["-lrocprofiler-sdk-roctx"]
     subprocess.check_call(cmd)
     os.replace(tmp, lib)
     return lib

@@ -27,6 +27,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <map>
 #include <mutex>
 #include <string>
@@ -553,21 +555,58 @@ int fluid_half_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   return rhs_eval_fixed(c, Us, c->U, 4, c->U, half, rec);
 }
 
+// A roctx range around the host code that enqueues one part of a step (RK
+// stage, filter; seen by rocprofv3 --marker-trace, a no-op without a tool).
+struct Range {
+  explicit Range(const char* m) { roctxRangePushA(m); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 int rk4_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   double* Us = sf(c, SC_US);
   int rc;
+  const bool filt = c->grid.filter_on || c->grid.dealias;
   if (c->phys.split) {  // fluid dt/2, Euler BSSN + gauge dt (matter frozen), fluid dt/2
-    if ((rc = fluid_half_step(c, js, rec))) return rc;
-    if ((rc = rhs_eval(c, c->U, 5, c->U, js, rec))) return rc;
-    if ((rc = fluid_half_step(c, js, rec))) return rc;
-    if ((c->grid.filter_on || c->grid.dealias) && (rc = filter_state(c, js, rec))) return rc;
+    {
+      Range r("grmhd split: fluid half step");
+      if ((rc = fluid_half_step(c, js, rec))) return rc;
+    }
+    {
+      Range r("grmhd split: spacetime Euler step");
+      if ((rc = rhs_eval(c, c->U, 5, c->U, js, rec))) return rc;
+    }
+    {
+      Range r("grmhd split: fluid half step");
+      if ((rc = fluid_half_step(c, js, rec))) return rc;
+    }
+    if (filt) {
+      Range r("grmhd filter");
+      if ((rc = filter_state(c, js, rec))) return rc;
+    }
     return GRMHD_OK;
   }
-  if ((rc = rhs_eval(c, c->U, 1, Us, js, rec))) return rc;
-  if ((rc = rhs_eval(c, Us, 2, Us, js, rec))) return rc;
-  if ((rc = rhs_eval(c, Us, 3, Us, js, rec))) return rc;
-  if ((rc = rhs_eval(c, Us, 4, c->U, js, rec))) return rc;
-  if ((c->grid.filter_on || c->grid.dealias) && (rc = filter_state(c, js, rec))) return rc;
+  {
+    Range r("grmhd RK4 stage 1");
+    if ((rc = rhs_eval(c, c->U, 1, Us, js, rec))) return rc;
+  }
+  {
+    Range r("grmhd RK4 stage 2");
+    if ((rc = rhs_eval(c, Us, 2, Us, js, rec))) return rc;
+  }
+  {
+    Range r("grmhd RK4 stage 3");
+    if ((rc = rhs_eval(c, Us, 3, Us, js, rec))) return rc;
+  }
+  {
+    Range r("grmhd RK4 stage 4");
+    if ((rc = rhs_eval(c, Us, 4, c->U, js, rec))) return rc;
+  }
+  if (filt) {
+    Range r("grmhd filter");
+    if ((rc = filter_state(c, js, rec))) return rc;
+  }
   return GRMHD_OK;
 }
 

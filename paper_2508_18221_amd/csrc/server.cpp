@@ -63,7 +63,8 @@ struct Job {
   grmhd_prec prec;
   double t_end;
   int keep;
-  int state;  // 0 queued, 1 running, 2 done, 3 rejected
+  int state;  // 0 queued, 1 running, 2 done, 3 rejected, 4 cancelled
+  bool cancel = false;  // running, cancelled: released once no step is in flight
   size_t off = 0, bytes = 0, res_bytes = 0;
   grmhd_ctx* ctx = nullptr;
   int64_t steps_total = 0, steps_done = 0;
@@ -319,6 +320,21 @@ static int retire(grmhd_server* s, Job& j, double t) {
   return GRMHD_OK;
 }
 
+// Release the cancelled running jobs that have no step in flight (their
+// class's events have passed every step launched for them).
+static void release_cancelled(grmhd_server* s) {
+  for (auto& j : s->jobs) {
+    if (j.state != 1 || !j.cancel || j.steps_done < j.steps_launched) continue;
+    if (!s->dry) {
+      grmhd::destroy_idle_context(j.ctx);
+      j.ctx = nullptr;
+    }
+    s->arena.release(j.off, j.bytes);
+    j.state = 4;
+    j.t_done = s->now();
+  }
+}
+
 // Count the completed launches of every class (the oldest first, in stream
 // order) and retire jobs that reached their end time.
 static int complete(grmhd_server* s, bool* progress) {
@@ -334,7 +350,7 @@ static int complete(grmhd_server* s, bool* progress) {
       for (size_t i : l.jobs) {
         Job& j = s->jobs[i];
         j.steps_done += 1;
-        if (j.steps_done >= j.steps_total) {
+        if (!j.cancel && j.steps_done >= j.steps_total) {
           int rc = retire(s, j, t);
           if (rc) return rc;
         }
@@ -344,6 +360,7 @@ static int complete(grmhd_server* s, bool* progress) {
       *progress = true;
     }
   }
+  release_cancelled(s);
   if (s->busy_since >= 0.0 && s->inflight_total() == 0) {
     s->busy += s->now() - s->busy_since;
     s->busy_since = -1.0;
@@ -394,7 +411,7 @@ static int launch(grmhd_server* s, bool* progress) {
       std::vector<size_t> ids;
       for (size_t i = 0; i < s->jobs.size(); ++i) {
         const Job& j = s->jobs[i];
-        if (j.state == 1 && j.cls == (int)ci && j.steps_launched < j.steps_total) ids.push_back(i);
+        if (j.state == 1 && !j.cancel && j.cls == (int)ci && j.steps_launched < j.steps_total) ids.push_back(i);
       }
       if (ids.empty()) break;
       Launch l;
@@ -476,6 +493,21 @@ int grmhd_server_poll(grmhd_server* s, int64_t id, grmhd_job_info* out) {
   return GRMHD_OK;
 }
 
+int grmhd_server_cancel(grmhd_server* s, int64_t id) {
+  if (!s || id < 0 || id >= (int64_t)s->jobs.size()) return sfail(GRMHD_E_ARG, "unknown job");
+  Job& j = s->jobs[id];
+  if (j.state == 0) {
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), (size_t)id));
+    j.state = 4;
+    j.t_done = s->now();
+    return GRMHD_OK;
+  }
+  if (j.state != 1 || j.cancel) return sfail(GRMHD_E_STATE, "job already done, rejected or cancelled");
+  j.cancel = true;
+  release_cancelled(s);  // at once if none of its steps is in flight
+  return GRMHD_OK;
+}
+
 int grmhd_server_result(grmhd_server* s, int64_t id, double* host_U, size_t n) {
   if (!s || !host_U || id < 0 || id >= (int64_t)s->jobs.size()) return sfail(GRMHD_E_ARG, "unknown job");
   const Job& j = s->jobs[id];
@@ -495,6 +527,7 @@ int grmhd_server_stats(grmhd_server* s, grmhd_server_summary* out) {
     if (j.state == 0) st.queued += 1;
     if (j.state == 1) st.running += 1;
     if (j.state == 3) st.rejected += 1;
+    if (j.state == 4) st.cancelled += 1;
     if (j.state == 2) {
       st.completed += 1;
       lat.push_back(j.t_done - j.t_arrival);

@@ -212,6 +212,11 @@ class Server:
         check_server(self.lib.grmhd_server_poll(self.srv, int(job_id), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in JobInfo._fields_}
 
+    def cancel(self, job_id):
+        """Cancel a queued or running job; its memory is released as soon as
+        none of its steps is in flight."""
+        check_server(self.lib.grmhd_server_cancel(self.srv, int(job_id)))
+
     def result(self, job_id, shape, nfields=NFIELDS):
         """Kept final state of a finished job (nfields 33 for a GLM job)."""
         U = np.empty((nfields,) + tuple(shape))

@@ -79,3 +79,40 @@ def test_server_result_equals_job_alone():
     s.close()
     assert abs(info["dt"] * info["steps_total"] - T) < 1e-15
     assert np.array_equal(served, alone)
+
+
+def test_server_cancel_mid_run_frees_the_slot():
+    """A budget for one 32x32x64 job: the running job is cancelled with steps
+    still in flight; it takes no further step, its block is released once they
+    complete, and the queued job is admitted into it and ends bitwise where it
+    ends when run alone."""
+    from paper_2508_18221_amd import Server, Solver
+    from test_server_dry import footprint
+    log("[server] cancel a running 32x32x64 job; the queued one takes its block")
+    size = (32, 32, 64)
+    g0, p0 = job(0.3, 60.0, 31, size)
+    g1, p1 = job(0.6, 200.0, 32, size)
+    fp = footprint(g0)
+    srv = Server(budget=fp + 4096, max_batch=32)
+    j0 = srv.submit(g0, p0, 0.2)
+    j1 = srv.submit(g1, p1, 0.05, keep_state=True)
+    for _ in range(3):
+        srv.tick()                      # job 0 running, two steps in flight
+    assert srv.poll(j0)["state"] == 1 and srv.poll(j1)["state"] == 0
+    srv.cancel(j0)
+    while srv.tick() > 0:
+        pass
+    i0, i1 = srv.poll(j0), srv.poll(j1)
+    st = srv.stats()
+    log(f"  job 0 cancelled after {i0['steps_done']} of {i0['steps_total']} steps; job 1 state {i1['state']}")
+    assert i0["state"] == 4 and 0 < i0["steps_done"] < i0["steps_total"]
+    assert i1["state"] == 2 and st["cancelled"] == 1 and st["completed"] == 1 and st["bytes_in_use"] == 0
+    served = srv.result(j1, (size[2], size[1], size[0]))
+    srv.close()
+    s = Solver(g1, p1)
+    s.init_state()
+    s.set_dt(i1["dt"])
+    s.step(i1["steps_total"])
+    alone = s.get_state()
+    s.close()
+    assert np.array_equal(served, alone)

@@ -127,3 +127,33 @@ def test_jobs_without_initial_data_are_refused_at_submission(bad):
     assert srv.poll(ok1)["state"] == 2 and srv.poll(ok2)["state"] == 2
     st = srv.stats()
     assert st["submitted"] == 2 and st["completed"] == 2 and st["queued"] == 0
+
+
+def test_cancel_frees_the_slot():
+    """Cancelling a queued job takes it out of the queue; cancelling a running
+    job releases its block, and the next queued job is admitted into it."""
+    g = make_grid(16, 16, 16)
+    fp = footprint(g)
+    srv = Server(budget=fp + 100, dry=True)           # room for one job
+    phys = make_phys()
+    dt = dt_of(g)
+    ids = [srv.submit(g, phys, 10 * dt) for _ in range(3)]
+    srv.tick()                                       # job 0 admitted and stepped once
+    assert [srv.poll(i)["state"] for i in ids] == [1, 0, 0]
+    srv.cancel(ids[2])                               # queued: leaves the queue at once
+    assert srv.poll(ids[2])["state"] == 4
+    srv.cancel(ids[0])                               # running, no step in flight: released
+    assert srv.poll(ids[0])["state"] == 4 and srv.poll(ids[0])["steps_done"] == 1
+    assert srv.stats()["bytes_in_use"] == 0
+    srv.tick()                                       # job 1 enters the freed block
+    assert srv.poll(ids[1])["state"] == 1
+    for i in (ids[0], ids[2]):
+        with pytest.raises(RuntimeError, match="already done, rejected or cancelled"):
+            srv.cancel(i)
+    with pytest.raises(RuntimeError, match="unknown job"):
+        srv.cancel(99)
+    while srv.tick() > 0:
+        pass
+    st = srv.stats()
+    assert srv.poll(ids[1])["state"] == 2 and st["completed"] == 1 and st["cancelled"] == 2
+    assert st["bytes_in_use"] == 0 and st["point_stage_updates"] == 4 * 16 ** 3 * 10
