@@ -497,7 +497,9 @@ int grmhd_server_cancel(grmhd_server* s, int64_t id) {
   if (!s || id < 0 || id >= (int64_t)s->jobs.size()) return sfail(GRMHD_E_ARG, "unknown job");
   Job& j = s->jobs[id];
   if (j.state == 0) {
-    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), (size_t)id));
+    const auto q = std::find(s->queue.begin(), s->queue.end(), (size_t)id);
+    if (q == s->queue.end()) return sfail(GRMHD_E_STATE, "queued job missing from the queue");
+    s->queue.erase(q);
     j.state = 4;
     j.t_done = s->now();
     return GRMHD_OK;
