@@ -237,7 +237,8 @@ int grmhd_state_ptr(grmhd_ctx* ctx, double** dev_U, double** dev_K0);
  * a GLM context) into dev_dUdt (as many); uses the context's K0 and con2prim
  * guesses.  With cowling = 1 the background is dev_U's spacetime (its first
  * derivatives are recomputed) and fields 0..23 of dev_dUdt are set to zero.
- * dev_U may be the resident state.  Async. */
+ * dev_U may be the resident state; dev_dUdt must not overlap dev_U
+ * (GRMHD_E_ARG).  Async. */
 int grmhd_rhs(grmhd_ctx* ctx, const double* dev_U, double* dev_dUdt);
 
 /* nsteps classic RK4 steps of size grmhd_dt(), each followed by the filter

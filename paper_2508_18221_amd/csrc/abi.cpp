@@ -547,11 +547,12 @@ int fluid_half_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   JobSet half = js;
   for (int j = 0; j < js.n; ++j) half.dt[j] = 0.5 * js.dt[j];
   double* Us = sf(c, SC_US);
+  double* Us2 = sf(c, SC_US2_FIXED);
   int rc;
   if ((rc = background_derivs(c, c->U, half, rec))) return rc;
   if ((rc = rhs_eval_fixed(c, c->U, c->U, 1, Us, half, rec))) return rc;
-  if ((rc = rhs_eval_fixed(c, Us, c->U, 2, Us, half, rec))) return rc;
-  if ((rc = rhs_eval_fixed(c, Us, c->U, 3, Us, half, rec))) return rc;
+  if ((rc = rhs_eval_fixed(c, Us, c->U, 2, Us2, half, rec))) return rc;
+  if ((rc = rhs_eval_fixed(c, Us2, c->U, 3, Us, half, rec))) return rc;
   return rhs_eval_fixed(c, Us, c->U, 4, c->U, half, rec);
 }
 
@@ -565,7 +566,10 @@ struct Range {
 };
 
 int rk4_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
+  // stage states: U^(2) and U^(4) in Us, U^(3) in Us2 (no stage writes the
+  // buffer it reads)
   double* Us = sf(c, SC_US);
+  double* Us2 = sf(c, c->pp.cowling ? SC_US2_FIXED : SC_US2_COUPLED);
   int rc;
   const bool filt = c->grid.filter_on || c->grid.dealias;
   if (c->phys.split) {  // fluid dt/2, Euler BSSN + gauge dt (matter frozen), fluid dt/2
@@ -593,11 +597,11 @@ int rk4_step(grmhd_ctx* c, const JobSet& js, Recorder* rec) {
   }
   {
     Range r("grmhd RK4 stage 2");
-    if ((rc = rhs_eval(c, Us, 2, Us, js, rec))) return rc;
+    if ((rc = rhs_eval(c, Us, 2, Us2, js, rec))) return rc;
   }
   {
     Range r("grmhd RK4 stage 3");
-    if ((rc = rhs_eval(c, Us, 3, Us, js, rec))) return rc;
+    if ((rc = rhs_eval(c, Us2, 3, Us, js, rec))) return rc;
   }
   {
     Range r("grmhd RK4 stage 4");
@@ -980,6 +984,11 @@ int grmhd_rhs(grmhd_ctx* c, const double* dev_U, double* dev_dUdt) {
   if (!c || !dev_U || !dev_dUdt) return fail(GRMHD_E_ARG, "null argument");
   NEED_SCRATCH(c);
   if (!c->have_state) return fail(GRMHD_E_STATE, "no state (init_state or set_state first)");
+  {  // the right-hand side goes to a buffer apart from its input
+    const uintptr_t n = (uintptr_t)(c->pp.glm ? NFA : NF) * c->L.P * sizeof(double);
+    const uintptr_t u = (uintptr_t)dev_U, d = (uintptr_t)dev_dUdt;
+    if (d < u + n && u < d + n) return fail(GRMHD_E_ARG, "dev_U and dev_dUdt overlap");
+  }
   if (c->pp.cowling) {  // the background of this evaluation is dev_U's spacetime
     c->bg_ready = false;
     int rc = background_derivs(c, dev_U, single(c));

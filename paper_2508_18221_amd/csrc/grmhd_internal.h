@@ -35,9 +35,15 @@ enum : int {
   SC_GLM = 243,   // 6   GLM: d_a (sqrt(gamma) B^a) at SC_GLM + a, d_a psi at SC_GLM + 3 + a
   SC_RIC = 249,   // 6   Ricci tensor R_ij of the stage state
   SC_BG = 255,    // 33  fixed-background form: d_a of background field s at SC_BG + 11a + s
-                  //     (s: phi, gt_ij, alpha, beta^i, the D2_FIELD order)
+                  //     (s: phi, gt_ij, alpha, beta^i, the D2_FIELD order);
+                  //     coupled RK4 step: the second stage state (SC_US2_COUPLED)
   SC_NFIELDS = 288
 };
+// The RK4 stages alternate between two stage states: SC_US and this block
+// (coupled form: SC_BG, free there; fixed-background form and the split
+// step's fluid stages: SC_D2, which they leave unused).
+constexpr int SC_US2_COUPLED = SC_BG;
+constexpr int SC_US2_FIXED = SC_D2;
 
 // Resident buffer: fields of P doubles, then operators and small arrays.
 enum : int {
@@ -253,7 +259,9 @@ hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, doub
                            const double* floors, const PointParams& pp, const JobSet& js, hipStream_t s);
 // mode 0: out = L(U_s); 1..4: classic RK4 stage s; 5: forward Euler of the
 // spacetime fields (split step; Us = Un = out).  der: derivative arrays
-// (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.
+// (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.  In
+// modes 0..4 out shares no location with Us, Un or acc (stage 4 may write
+// the Un buffer: it does not read Un), and acc none with Us or Un.
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s);

@@ -25,6 +25,8 @@
 // not differentiated.
 #include <math.h>
 
+#include <type_traits>
+
 #include "grmhd_internal.h"
 
 namespace grmhd {
@@ -524,9 +526,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DAMPED ? 2 
 // phases so that each phase's loads are issued where they are consumed and
 // the live register set stays small.
 //
-// Us, Un, acc and out may alias (in-place stages): no restrict on them; every
-// element is read and written by the same thread.
+// Us, Un, acc and out never share a location that the launch writes: the RK4
+// stages alternate between two stage buffers (stage 4 writes U^n, which it
+// does not read), the accumulator is read and written through acc alone, and
+// a right-hand side (mode 0) goes to a buffer apart from its input.  Declared
+// __restrict__, the loads of Un and the accumulator for one field then need
+// not wait for the stores of the fields before it.  The split step's forward
+// Euler update of the spacetime in place (mode 5, Us = Un = out) is the one
+// instantiation without the qualifier.
 #define PHASE() __asm__ __volatile__("" ::: "memory")
+
+template <bool R, typename T>
+using maybe_restrict = typename std::conditional<R, T* __restrict__, T*>::type;
 
 // Matter terms of one point that the BSSN right-hand sides use: E, S_i,
 // S_ij and the trace of S^i_j.
@@ -647,19 +658,19 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
 #undef LU
 }
 
-// MODE >= 0: the stage mode as a compile-time constant (the FP32-array
-// instantiations: with every update straight-line code the loads of Un and
-// the accumulator issue early: the reduced forms' step 2.3-2.5% faster);
-// MODE = -1: the mode argument (the FP64 instantiation, 1% slower otherwise).
-template <typename DT, int MODE = -1>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rhs_rk(int mode_arg, const double* Us,
+// MODE: the stage mode as a compile-time constant, so that every update is
+// straight-line code and the loads of Un and the accumulator can issue early.
+template <typename DT, int MODE, bool NA = (MODE != 5)>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rhs_rk(
+                                                maybe_restrict<NA, const double> Us,
                                                 const DT* __restrict__ der,
                                                 const double* __restrict__ prim,
                                                 const double* __restrict__ K0p,
                                                 const double* __restrict__ Ric,
-                                                const double* Un, double* acc, double* out,
+                                                maybe_restrict<NA, const double> Un,
+                                                maybe_restrict<NA, double> acc, maybe_restrict<NA, double> out,
                                                 PointParams pp, JobSet js) {
-  const int mode = MODE >= 0 ? MODE : mode_arg;
+  constexpr int mode = MODE;
   const long long P = pp.P;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= P) return;
@@ -694,6 +705,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // 4: out = acc + dt/6 k; 5 (split step): forward Euler out = Un + dt k of the
   // 24 spacetime fields only, the matter fields are not written
   auto emit = [&](int f, double kf) {
+    // kf is formed on every lane: otherwise the compiler moves its loads
+    // into a branch over the non-frozen lanes, behind the stores before it
+    __asm__ __volatile__("" : "+v"(kf));
     if (frozen || (pp.cowling && f < 24)) kf = 0.0;  // Cowling: fixed spacetime
     const size_t e = (size_t)f * P + idx;
     if (mode == 0) {
@@ -894,12 +908,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // background state Ug (phi, gt_ij, A-tilde_ij, K, alpha) and its first
 // derivatives bg (d_a of background field s at 11 a + s, s = phi, gt_ij, alpha,
 // beta^i); the fluid from the stage state Us.  Mode 0 also writes zero
-// right-hand sides for the 24 spacetime fields.  Stage modes as in k_rhs_rk.
-template <typename DT>
-__global__ __launch_bounds__(256) void k_rhs_fixed(int mode, const double* Us, const double* __restrict__ Ug,
-                                                   const double* __restrict__ bg, const DT* __restrict__ der,
-                                                   const double* __restrict__ prim, const double* Un, double* acc,
-                                                   double* out, PointParams pp, JobSet js) {
+// right-hand sides for the 24 spacetime fields.  Stage modes as in k_rhs_rk,
+// with the same promise on the buffers (Ug may be U^n: the background fields
+// it supplies are never written here).
+template <typename DT, int MODE>
+__global__ __launch_bounds__(256) void k_rhs_fixed(const double* __restrict__ Us,
+                                                   const double* __restrict__ Ug, const double* __restrict__ bg,
+                                                   const DT* __restrict__ der, const double* __restrict__ prim,
+                                                   const double* __restrict__ Un, double* __restrict__ acc,
+                                                   double* __restrict__ out, PointParams pp, JobSet js) {
   const long long P = pp.P;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= P) return;
@@ -918,7 +935,9 @@ __global__ __launch_bounds__(256) void k_rhs_fixed(int mode, const double* Us, c
   const int j = (int)(idx % pp.nr);
   const int k = (int)((idx / pp.nr) % pp.nth);
   const bool frozen = (j == 0 || k == 0 || k == pp.nth - 1);
+  constexpr int mode = MODE;
   auto emit = [&](int f, double kf) {
+    __asm__ __volatile__("" : "+v"(kf));  // formed on every lane, as in k_rhs_rk
     if (frozen) kf = 0.0;
     const size_t e = (size_t)f * P + idx;
     if (mode == 0) {
@@ -1348,23 +1367,25 @@ hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* d
                          const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s) {
   if (mode < 0 || mode > 5 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
-  if (der_f32) {
-#define RKF(M)                                                                                           \
-  hipLaunchKernelGGL((k_rhs_rk<float, M>), dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, (const float*)der, \
-                     prim, K0, Ric, Un, acc, out, pp, js)
-    switch (mode) {
-      case 0: RKF(0); break;
-      case 1: RKF(1); break;
-      case 2: RKF(2); break;
-      case 3: RKF(3); break;
-      case 4: RKF(4); break;
-      default: RKF(5); break;
-    }
-#undef RKF
-  } else {
-    hipLaunchKernelGGL(k_rhs_rk<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us,
-                       (const double*)der, prim, K0, Ric, Un, acc, out, pp, js);
+#define RKM(T, M)                                                                                          \
+  hipLaunchKernelGGL((k_rhs_rk<T, M>), dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, (const T*)der, prim, K0, \
+                     Ric, Un, acc, out, pp, js)
+#define RKT(T)                  \
+  switch (mode) {               \
+    case 0: RKM(T, 0); break;   \
+    case 1: RKM(T, 1); break;   \
+    case 2: RKM(T, 2); break;   \
+    case 3: RKM(T, 3); break;   \
+    case 4: RKM(T, 4); break;   \
+    default: RKM(T, 5); break;  \
   }
+  if (der_f32) {
+    RKT(float)
+  } else {
+    RKT(double)
+  }
+#undef RKT
+#undef RKM
   return hipGetLastError();
 }
 
@@ -1372,12 +1393,24 @@ hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const doub
                             const void* der, const double* prim, const double* Un, double* acc, double* out,
                             const PointParams& pp, const JobSet& js, hipStream_t s) {
   if (mode < 0 || mode > 4 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
-  if (der_f32)
-    hipLaunchKernelGGL(k_rhs_fixed<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, Ug, bg,
-                       (const float*)der, prim, Un, acc, out, pp, js);
-  else
-    hipLaunchKernelGGL(k_rhs_fixed<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, mode, Us, Ug, bg,
-                       (const double*)der, prim, Un, acc, out, pp, js);
+#define RFM(T, M)                                                                                        \
+  hipLaunchKernelGGL((k_rhs_fixed<T, M>), dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, Ug, bg, (const T*)der, \
+                     prim, Un, acc, out, pp, js)
+#define RFT(T)                 \
+  switch (mode) {              \
+    case 0: RFM(T, 0); break;  \
+    case 1: RFM(T, 1); break;  \
+    case 2: RFM(T, 2); break;  \
+    case 3: RFM(T, 3); break;  \
+    default: RFM(T, 4); break; \
+  }
+  if (der_f32) {
+    RFT(float)
+  } else {
+    RFT(double)
+  }
+#undef RFT
+#undef RFM
   return hipGetLastError();
 }
 

@@ -55,6 +55,30 @@ def test_single_rhs_matches_oracle_64x64x128():
     assert e.max() < 1e-9
 
 
+def test_rhs_refuses_an_output_that_overlaps_its_input():
+    """The right-hand side goes to a buffer apart from its input (the kernel
+    takes the two as non-overlapping): an overlapping pair is refused before
+    any device work, and the context stays usable."""
+    from paper_2508_18221_amd._lib import GrmhdError
+    log("[rhs overlap] 16^3: dU_dt over the input, shifted by one field, then a separate buffer")
+    w = workload("ks_michel_16x16x16")
+    g, pb, U, K0 = oracle_problem(w)
+    s = solver(w)
+    s.set_state(U, K0)
+    buf = torch.tensor(np.concatenate([U.ravel(), U.ravel()]), device="cuda")
+    n = U.size
+    dU = buf[:n]
+    for out in (buf[:n], buf[n // 32:n // 32 + n]):
+        with pytest.raises(GrmhdError, match="overlap"):
+            s.rhs(dU, out)
+    out = torch.full_like(dU, np.nan)
+    s.rhs(dU, out)
+    torch.cuda.synchronize()
+    e = rhs_errors(out.cpu().numpy().reshape(U.shape), pb.rhs(U, K0), U)
+    s.close()
+    assert e.max() < 1e-11
+
+
 def test_con2prim_and_fluxes_match_oracle():
     log("[c2p] grid 20x18x12")
     w = workload("ks_michel_16x16x16", nr=20, nth=18, nph=12)
