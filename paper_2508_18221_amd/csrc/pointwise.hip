@@ -876,6 +876,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   PHASE();
 
   // ---- phase 6: Gamma-tilde and the Gamma-driver ---------------------------------
+  // d_j d_k beta^i (symmetric pair S6(j, k)), each array read once, and
+  // d_j d_k beta^k
+  double ddb[3][6], ddivb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int kk = jj; kk < 3; ++kk) ddb[i][S6(jj, kk)] = DD(jj, kk, 8 + i);
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) ddivb[jj] = ddb[0][S6(jj, 0)] + ddb[1][S6(jj, 1)] + ddb[2][S6(jj, 2)];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     double t = 0.0;
@@ -888,9 +899,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) {
         t += 2.0 * alpha * Gu[i][S6(jj, kk)] * Atu(jj, kk);
-        t += gtu(jj, kk) * DD(jj, kk, 8 + i);
-        t += gtu(i, jj) * DD(jj, kk, 8 + kk) / 3.0;
+        t += gtu(jj, kk) * ddb[i][S6(jj, kk)];
       }
+      t += gtu(i, jj) * ddivb[jj] / 3.0;
     }
     const double rGt = t + (2.0 / 3.0) * Gd[i] * divb;
     emit(14 + i, rGt);
