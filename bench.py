@@ -58,7 +58,7 @@ def launch_costs(nr, nth, nph):
                     ("deriv_p", "deriv_p2", "deriv_p1")):
         c[k] = (c[a][0] + c[b][0], c[a][1] + c[b][1])
     c["ricci"] = (84 * d, 0.0)                          # gt 6, 33 first and 42 second derivatives in; R 6 out
-    c["rhs_rk"] = (259 * d, 0.0)                        # mean over the 4 stage modes (251, 283, 283, 219)
+    c["rhs_rk"] = (251 * d, 0.0)                        # mean over the 4 stage modes (219, 283, 283, 219)
     for k, n in (("filter_r", nr), ("filter_t", nth), ("filter_p", nph)):
         c[k] = (64 * d, fl(n) * 32)
     return c

@@ -261,13 +261,15 @@ hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, doub
 // spacetime fields (split step; Us = Un = out).  der: derivative arrays
 // (scratch fields SC_D1 .. SC_DF + 23, in that order), FP64 or FP32.  In
 // modes 0..4 out shares no location with Us, Un or acc (stage 4 may write
-// the Un buffer: it does not read Un), and acc none with Us or Un.
+// the Un buffer: it does not read Un), and acc none with Us or Un.  Mode 1
+// takes Us as U^n (Un is not read).
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
                          const double* K0, const double* Ric, const double* Un, double* acc, double* out,
                          const PointParams& pp, const JobSet& js, hipStream_t s);
 // Fixed-background form: GRMHD (and psi) right-hand sides / RK4 stage from the
 // stage fluid Us, background state Ug, background first derivatives bg
-// (SC_BG block) and the flux derivative arrays (der as in launch_rhs_rk).
+// (SC_BG block) and the flux derivative arrays (der as in launch_rhs_rk; the
+// same rules for the buffers and for mode 1).
 hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const double* Ug, const double* bg,
                             const void* der, const double* prim, const double* Un, double* acc, double* out,
                             const PointParams& pp, const JobSet& js, hipStream_t s);

@@ -552,7 +552,8 @@ struct Matter {
 // -sqrt(gamma) gamma^{ij} d_j psi and the psi equation.  Geometry: sqrt(gamma),
 // e^{+-4 phi}, gt_ij and its inverse, A-tilde_ij, K, alpha and the first
 // derivatives of alpha, beta^i, gt_ij and phi ([a][..] = d_a).  Each result goes
-// to emit(f, value) (f = 24..31, and 32 with GLM).
+// to emit(f, value, U_f) (f = 24..31, and 32 with GLM; U_f the stage value of
+// the field, which stage 1 takes as U^n).
 template <typename DT, typename Emit>
 __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __restrict__ der,
                                                const double* __restrict__ prim, long long idx, long long P,
@@ -563,13 +564,16 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
 #define LU(f) Us[(size_t)(f) * P + idx]
 #define LS(g) ((double)ldnt(&der[(size_t)(g) * P + idx]))
   Matter mt;
+  double u[8];  // D, S_j, tau, B^i (densitised)
+#pragma unroll
+  for (int v = 0; v < 8; ++v) u[v] = LU(24 + v);
   const double isg = 1.0 / sqrtg;
-  mt.Em = (LU(28) + LU(24)) * isg;
+  mt.Em = (u[4] + u[0]) * isg;
   const double Em = mt.Em;
   double* Sl = mt.Sl;
-  Sl[0] = LU(25) * isg;
-  Sl[1] = LU(26) * isg;
-  Sl[2] = LU(27) * isg;
+  Sl[0] = u[1] * isg;
+  Sl[1] = u[2] * isg;
+  Sl[2] = u[3] * isg;
   Sym gam, gamu;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
@@ -581,7 +585,7 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
     const double rho = ldnt(&prim[idx]), p = ldnt(&prim[(size_t)P + idx]);
     const double v[3] = {ldnt(&prim[2 * (size_t)P + idx]), ldnt(&prim[3 * (size_t)P + idx]),
                          ldnt(&prim[4 * (size_t)P + idx])};
-    const double B[3] = {LU(29) * isg, LU(30) * isg, LU(31) * isg};
+    const double B[3] = {u[5] * isg, u[6] * isg, u[7] * isg};
     const Mag m = magnetic(v, B, gam);
     const double h = 1.0 + p / rho * pp.gfac;
     const double cw = (rho * h + m.b2) * m.W * m.W;
@@ -645,11 +649,12 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
       if (v >= 1 && v <= 3) r += sqrtg * src[v - 1];
       if (v == 4) r += sqrtg * srcT;
       if (v >= 5) r -= sqrtg * sb[v - 5];
-      emit(24 + v, r);
+      emit(24 + v, r, u[v]);
     }
     if (pp.glm) {  // d_t psi = -c_h^2 d_i(sqrt(gamma) B^i) / sqrt(gamma) - psi / tau
       const double divB = (LS(O_GLM) + LS(O_GLM + 1) + LS(O_GLM + 2)) * isg;
-      emit(32, -pp.ch2 * divB - LU(32) * pp.itau);
+      const double psi = LU(32);
+      emit(32, -pp.ch2 * divB - psi * pp.itau, psi);
     }
   }
   mt.Str = Str;
@@ -700,11 +705,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   };
   // classic RK4 stage update of field f with right-hand side kf; the
   // accumulator holds Un + dt sum_s b_s k_s, so the last stage does not read Un
-  // mode 0: out = k; 1: acc = Un + dt/6 k, out = Un + dt/2 k;
+  // mode 0: out = k; 1 (Us is Un, read once): acc = Un + dt/6 k, out = Un + dt/2 k;
   // 2: acc += dt/3 k, out = Un + dt/2 k; 3: acc += dt/3 k, out = Un + dt k;
   // 4: out = acc + dt/6 k; 5 (split step): forward Euler out = Un + dt k of the
   // 24 spacetime fields only, the matter fields are not written
-  auto emit = [&](int f, double kf) {
+  // us: the stage value of field f (held in a register where the right-hand
+  // side already read it; stage 1 takes it as U^n instead of reading U^n again)
+  auto emit = [&](int f, double kf, double us) {
     // kf is formed on every lane: otherwise the compiler moves its loads
     // into a branch over the non-frozen lanes, behind the stores before it
     __asm__ __volatile__("" : "+v"(kf));
@@ -715,7 +722,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     } else if (mode == 5) {
       if (f < 24) out[e] = ldnt(&Un[e]) + dt * kf;
     } else if (mode == 1) {
-      const double un = ldnt(&Un[e]);
+      const double un = us;  // stage 1 is evaluated at U^n
       acc[e] = un + (dt / 6.0) * kf;
       out[e] = un + 0.5 * dt * kf;
     } else if (mode == 2) {
@@ -765,7 +772,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
     for (int s = 0; s < 6; ++s) dgt[a][s] = D1(a, 1 + s);
   christoffel(gtu, dgt, Gl, Gu, Gd);
-  emit(0, -alpha * K / 6.0 + dot3(beta, dphi) + divb / 6.0);
+  emit(0, -alpha * K / 6.0 + dot3(beta, dphi) + divb / 6.0, phi);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -775,13 +782,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) lie += gt(i, kk) * dbeta[jj][kk] + gt(jj, kk) * dbeta[i][kk];
       const double adv = beta[0] * dgt[0][s] + beta[1] * dgt[1][s] + beta[2] * dgt[2][s];
-      emit(1 + s, -2.0 * alpha * At.m[s] + adv + lie - (2.0 / 3.0) * gt.m[s] * divb);
+      emit(1 + s, -2.0 * alpha * At.m[s] + adv + lie - (2.0 / 3.0) * gt.m[s] * divb, gt.m[s]);
     }
-  emit(17, dot3(beta, dal) - 2.0 * alpha * (pp.gauge_k0 ? (K - K0) : K));
+  emit(17, dot3(beta, dal) - 2.0 * alpha * (pp.gauge_k0 ? (K - K0) : K), alpha);
   {
     const double Bd[3] = {LU(21), LU(22), LU(23)};
 #pragma unroll
-    for (int i = 0; i < 3; ++i) emit(18 + i, 0.75 * Bd[i]);
+    for (int i = 0; i < 3; ++i) emit(18 + i, 0.75 * Bd[i], beta[i]);
   }
   PHASE();
 
@@ -847,7 +854,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) AA += At(i, jj) * Atu(i, jj);
-  emit(13, -trDDa + alpha * (AA + K * K / 3.0) + 4.0 * PI * alpha * (Em + Str) + dot3(beta, dK));
+  emit(13, -trDDa + alpha * (AA + K * K / 3.0) + 4.0 * PI * alpha * (Em + Str) + dot3(beta, dK), K);
   {
     double X[6];
 #pragma unroll
@@ -870,7 +877,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           adv += beta[kk] * D1(kk, 7 + s);
         }
         emit(7 + s, em4 * (X[s] - gt.m[s] * trX / 3.0) + alpha * (K * At.m[s] - 2.0 * AAij) + adv + lie -
-                        (2.0 / 3.0) * At.m[s] * divb);
+                        (2.0 / 3.0) * At.m[s] * divb,
+             At.m[s]);
       }
   }
   PHASE();
@@ -904,8 +912,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       t += gtu(i, jj) * ddivb[jj] / 3.0;
     }
     const double rGt = t + (2.0 / 3.0) * Gd[i] * divb;
-    emit(14 + i, rGt);
-    emit(21 + i, rGt - pp.eta * LU(21 + i));
+    emit(14 + i, rGt, LU(14 + i));
+    const double bd = LU(21 + i);
+    emit(21 + i, rGt - pp.eta * bd, bd);
   }
 #undef D1
 #undef LS
@@ -947,14 +956,14 @@ __global__ __launch_bounds__(256) void k_rhs_fixed(const double* __restrict__ Us
   const int k = (int)((idx / pp.nr) % pp.nth);
   const bool frozen = (j == 0 || k == 0 || k == pp.nth - 1);
   constexpr int mode = MODE;
-  auto emit = [&](int f, double kf) {
+  auto emit = [&](int f, double kf, double us) {
     __asm__ __volatile__("" : "+v"(kf));  // formed on every lane, as in k_rhs_rk
     if (frozen) kf = 0.0;
     const size_t e = (size_t)f * P + idx;
     if (mode == 0) {
       out[e] = kf;
     } else if (mode == 1) {
-      const double un = ldnt(&Un[e]);
+      const double un = us;  // stage 1 is evaluated at U^n
       acc[e] = un + (dt / 6.0) * kf;
       out[e] = un + 0.5 * dt * kf;
     } else if (mode == 2) {
