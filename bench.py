@@ -57,8 +57,9 @@ def launch_costs(nr, nth, nph):
     for k, a, b in (("deriv_r", "deriv_r2", "deriv_r1"), ("deriv_t", "deriv_t2", "deriv_t1"),
                     ("deriv_p", "deriv_p2", "deriv_p1")):
         c[k] = (c[a][0] + c[b][0], c[a][1] + c[b][1])
-    c["ricci"] = (84 * d, 0.0)                          # gt 6, 33 first and 42 second derivatives in; R 6 out
-    c["rhs_rk"] = (251 * d, 0.0)                        # mean over the 4 stage modes (219, 283, 283, 219)
+    c["ricci"] = (84 * d, 0.0)                          # a separate Ricci launch (none in the stage)
+    # RHS with the Ricci tensor: mean over the 4 stage modes (255, 319, 319, 255)
+    c["rhs_rk"] = (287 * d, 0.0)
     for k, n in (("filter_r", nr), ("filter_t", nth), ("filter_p", nph)):
         c[k] = (64 * d, fl(n) * 32)
     return c

@@ -425,7 +425,7 @@ const char* grmhd_server_last_error(void);
 /* ---- timing ---------------------------------------------------------------- */
 
 /* Launch kinds of one RK4 step (per stage: con2prim, 3 flux-derivative and
- * 3 (folded forms) or 6 state-derivative launches, Ricci, RHS; then 3 filter
+ * 3 (folded forms) or 6 state-derivative launches, RHS; then 3 filter
  * launches). */
 enum {
   GRMHD_K_C2P_FLUX = 0,   /* con2prim + densitised fluxes                        */
@@ -435,12 +435,12 @@ enum {
   GRMHD_K_DERIV_T1 = 4,   /* theta axis, first (10 + 11 mixed)                     */
   GRMHD_K_DERIV_P2 = 5,   /* phi axis, first + second                              */
   GRMHD_K_DERIV_P1 = 6,   /* phi axis, first (10 + 22 mixed)                       */
-  GRMHD_K_RHS_RK = 7,     /* BSSN + Valencia RHS and RK4 stage update              */
+  GRMHD_K_RHS_RK = 7,     /* BSSN (Ricci tensor included) + Valencia RHS, RK4 stage */
   GRMHD_K_FILTER_R = 8, GRMHD_K_FILTER_T = 9, GRMHD_K_FILTER_P = 10,
   GRMHD_K_DERIV_R = 11,   /* r axis, first + second and first-only tasks in one launch */
   GRMHD_K_DERIV_T = 12,   /* theta axis, likewise                                      */
   GRMHD_K_DERIV_P = 13,   /* phi axis, likewise                                        */
-  GRMHD_K_RICCI = 14,     /* Ricci tensor of the stage state                           */
+  GRMHD_K_RICCI = 14,     /* a separate Ricci launch: none (count 0; the RHS forms it) */
   GRMHD_K_DFLUX_R = 15,   /* r derivatives of the 8 densitised fluxes                  */
   GRMHD_K_DFLUX_T = 16,   /* theta derivatives of the fluxes                           */
   GRMHD_K_DFLUX_P = 17,   /* phi derivatives of the fluxes                             */

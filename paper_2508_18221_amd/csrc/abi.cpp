@@ -10,9 +10,8 @@
 //                             d_r arrays (mixed r-th)
 //                    ph pass  d_ph, d_phph; d_ph of 10 fields and of the 11
 //                             d_r and 11 d_th arrays (mixed)
-//                    k_ricci  Ricci tensor
-//                    (join)   k_rhs_rk: BSSN + Valencia RHS, boundary freeze,
-//                             RK4 update
+//                    (join)   k_rhs_rk: BSSN (Ricci tensor included) + Valencia
+//                             RHS, boundary freeze, RK4 update
 // After the fourth stage the filter runs as three contraction passes.
 //
 // Fixed background (cowling): the first derivatives of the background metric
@@ -148,8 +147,8 @@ struct grmhd_ctx {
   double* scr;
   hipStream_t stream;
   // second stream of a stage: primitive recovery and the flux derivatives run
-  // there beside the state derivatives and the Ricci tensor (fork and join
-  // events on the context stream)
+  // there beside the state derivatives (fork and join events on the context
+  // stream)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int device;
@@ -488,8 +487,8 @@ int rhs_eval_fixed(grmhd_ctx* c, const double* Uin, const double* Ug, int mode, 
 
 // One RHS evaluation (+ RK stage update for mode >= 1) of the jobs in js,
 // addressed through context c (the first job).  Primitive recovery and the
-// flux derivatives run on the side stream while the state derivatives and the
-// Ricci tensor run on the context stream; the RHS kernel waits for both.  A
+// flux derivatives run on the side stream while the state derivatives run on
+// the context stream; the RHS kernel waits for both.  A
 // profiled evaluation (rec set) runs every launch in order on the context
 // stream so that each launch is timed alone.
 int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSet& js,
@@ -509,11 +508,9 @@ int rhs_eval(grmhd_ctx* c, const double* Uin, int mode, double* out, const JobSe
   if (split) HIPCHK(hipEventRecord(c->ev_join, c->side));
   rc = state_derivs(c, Uin, js, rec);
   if (rc) return rc;
-  HIPCHK(launch_ricci(mixed, Uin, sf(c, SC_D1), sf(c, SC_RIC), c->pp, js, c->stream));
-  MARK(rec, GRMHD_K_RICCI);
   if (split) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
-  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, sf(c, SC_RIC), c->U, sf(c, SC_ACC), out,
-                       c->pp, js, c->stream));
+  HIPCHK(launch_rhs_rk(mode, mixed, Uin, sf(c, SC_D1), c->prim, c->K0, c->U, sf(c, SC_ACC), out, c->pp, js,
+                       c->stream));
   MARK(rec, GRMHD_K_RHS_RK);
   return GRMHD_OK;
 }

@@ -33,7 +33,7 @@ enum : int {
   SC_MX = 186,    // 33  mixed (r th, r ph, th ph) at SC_MX + 11m + s
   SC_DF = 219,    // 24  d_a (alpha sqrt(gamma) F^a_v) at SC_DF + 8a + v
   SC_GLM = 243,   // 6   GLM: d_a (sqrt(gamma) B^a) at SC_GLM + a, d_a psi at SC_GLM + 3 + a
-  SC_RIC = 249,   // 6   Ricci tensor R_ij of the stage state
+                  // 249..254 unused
   SC_BG = 255,    // 33  fixed-background form: d_a of background field s at SC_BG + 11a + s
                   //     (s: phi, gt_ij, alpha, beta^i, the D2_FIELD order);
                   //     coupled RK4 step: the second stage state (SC_US2_COUPLED)
@@ -264,8 +264,8 @@ hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, doub
 // the Un buffer: it does not read Un), and acc none with Us or Un.  Mode 1
 // takes Us as U^n (Un is not read).
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
-                         const double* K0, const double* Ric, const double* Un, double* acc, double* out,
-                         const PointParams& pp, const JobSet& js, hipStream_t s);
+                         const double* K0, const double* Un, double* acc, double* out, const PointParams& pp,
+                         const JobSet& js, hipStream_t s);
 // Fixed-background form: GRMHD (and psi) right-hand sides / RK4 stage from the
 // stage fluid Us, background state Ug, background first derivatives bg
 // (SC_BG block) and the flux derivative arrays (der as in launch_rhs_rk; the
@@ -273,10 +273,6 @@ hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* d
 hipError_t launch_rhs_fixed(int mode, bool der_f32, const double* Us, const double* Ug, const double* bg,
                             const void* der, const double* prim, const double* Un, double* acc, double* out,
                             const PointParams& pp, const JobSet& js, hipStream_t s);
-// Ricci tensor R_ij (6 fields of P doubles, symmetric storage) of the stage
-// state from its derivative arrays (FP64 or FP32)
-hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double* R, const PointParams& pp,
-                        const JobSet& js, hipStream_t s);
 // Hamiltonian constraint H and momentum-constraint norm |M| (P doubles each)
 // from FP64 derivative arrays
 hipError_t launch_ham(const double* U, const double* der, double* H, double* Mn, const PointParams& pp,

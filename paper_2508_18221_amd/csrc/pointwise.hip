@@ -2,8 +2,8 @@
 // structure-of-arrays FP64 streaming from HBM):
 //   k_c2p_flux  : metric reconstruction, primitive recovery (safeguarded
 //                 Newton, or the paper's damped iteration), densitised fluxes
-//   k_ricci     : Ricci tensor of the stage state
-//   k_rhs_rk    : BSSN + gauge RHS with matter sources, Valencia RHS
+//   k_rhs_rk    : BSSN + gauge RHS (Ricci tensor included) with matter
+//                 sources, Valencia RHS
 //                 (-div + sqrt(gamma) S, GLM terms), boundary freeze, RK4 stage
 //                 update (or the split step's Euler update of the spacetime)
 //   k_rhs_fixed : the Valencia RHS and RK4 stage on a fixed background
@@ -412,8 +412,8 @@ __device__ __forceinline__ void ricci(const Sym& gt, const Sym& gtu, const doubl
 constexpr int O_D2 = SC_D2 - SC_D1, O_MX = SC_MX - SC_D1, O_DF = SC_DF - SC_D1, O_GLM = SC_GLM - SC_D1;
 
 // Loads of arrays that a launch reads once: non-temporal, so the streams pass
-// the caches without evicting each other (the RHS and Ricci kernels read
-// 80-200 such arrays per point).
+// the caches without evicting each other (the RHS kernels read 80-240 such
+// arrays per point).
 template <typename T>
 __device__ __forceinline__ T ldnt(const T* p) {
   return __builtin_nontemporal_load(p);
@@ -663,6 +663,11 @@ __device__ __forceinline__ Matter valencia_rhs(const double* Us, const DT* __res
 #undef LU
 }
 
+// LDS slots per thread of the RHS kernel (values parked across the Ricci
+// tensor): E, trace of S^i_j, S_j (3), S_ij (6), beta^i (3), d_a alpha (3),
+// d_a K (3), d_a beta^i (9).
+constexpr int RHS_PARK = 29;
+
 // MODE: the stage mode as a compile-time constant, so that every update is
 // straight-line code and the loads of Un and the accumulator can issue early.
 template <typename DT, int MODE, bool NA = (MODE != 5)>
@@ -671,7 +676,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                 const DT* __restrict__ der,
                                                 const double* __restrict__ prim,
                                                 const double* __restrict__ K0p,
-                                                const double* __restrict__ Ric,
                                                 maybe_restrict<NA, const double> Un,
                                                 maybe_restrict<NA, double> acc, maybe_restrict<NA, double> out,
                                                 PointParams pp, JobSet js) {
@@ -686,7 +690,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     der = shift_ptr(der, jd);
     prim = shift_ptr(prim, jd);
     K0p = shift_ptr(K0p, jd);
-    Ric = shift_ptr(Ric, jd);
     Un = shift_ptr(Un, jd);
     acc = shift_ptr(acc, jd);
     out = shift_ptr(out, jd);
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
   const double K = LU(13);
   const double alpha = LU(17);
-  const double beta[3] = {LU(18), LU(19), LU(20)};
+  double beta[3] = {LU(18), LU(19), LU(20)};
   const double K0 = K0p[idx];
   const double detgt = det_sym(gt);
   const Sym gtu = inv_sym(gt, detgt);
@@ -793,24 +796,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   PHASE();
 
   // ---- phase 3: matter; Valencia right-hand sides ------------------------------
-  const Matter mt = valencia_rhs(Us, der, prim, idx, P, pp, sqrtg, e4, em4, gt, gtu, At, K, alpha, dal, dbeta,
-                                 dgt, dphi, emit);
-  const double Em = mt.Em;
-  const double* Sl = mt.Sl;
-  const Sym& Sij = mt.Sij;
-  const double Str = mt.Str;
+  // Values needed after the Ricci tensor wait in LDS (one slot per thread)
+  // while it is formed: the matter terms and the shift and lapse and K
+  // derivatives.  In registers they would make the kernel spill at two waves
+  // per SIMD; the LDS is otherwise unused.
+  __shared__ double park[RHS_PARK][256];
+  double* const pk = &park[0][threadIdx.x];  // slot q at pk[256 q]
+  {
+    const Matter m3 = valencia_rhs(Us, der, prim, idx, P, pp, sqrtg, e4, em4, gt, gtu, At, K, alpha, dal, dbeta,
+                                   dgt, dphi, emit);
+    pk[0] = m3.Em;
+    pk[256] = m3.Str;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      pk[256 * (2 + q)] = m3.Sl[q];
+      pk[256 * (11 + q)] = beta[q];
+      pk[256 * (14 + q)] = dal[q];
+      pk[256 * (17 + q)] = dK[q];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) pk[256 * (20 + 3 * q + r)] = dbeta[q][r];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) pk[256 * (5 + q)] = m3.Sij.m[q];
+  }
   PHASE();
 
-  // ---- phase 4: Ricci tensor (computed by k_ricci) ------------------------------
-  Sym R;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) R.m[s] = ldnt(&Ric[(size_t)s * P + idx]);
+  // ---- phase 4: conformal Ricci tensor -------------------------------------------
   double dGt[3][3];  // [a][i] = d_a Gt^i
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int i = 0; i < 3; ++i) dGt[a][i] = D1(a, 14 + i);
+  Sym R;
+  ricci(gt, gtu, Gl, Gu, Gd, dGt, dphi, DD, R);
   PHASE();
+  Matter mt;
+  mt.Em = pk[0];
+  mt.Str = pk[256];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    mt.Sl[q] = pk[256 * (2 + q)];
+    beta[q] = pk[256 * (11 + q)];
+    dal[q] = pk[256 * (14 + q)];
+    dK[q] = pk[256 * (17 + q)];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) dbeta[q][r] = pk[256 * (20 + 3 * q + r)];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) mt.Sij.m[q] = pk[256 * (5 + q)];
+  const double Em = mt.Em;
+  const double* Sl = mt.Sl;
+  const Sym& Sij = mt.Sij;
+  const double Str = mt.Str;
 
   // ---- phase 5: D_i D_j alpha, A-tilde contractions, K and A-tilde -------------
   double DDa[6];
@@ -1007,51 +1044,6 @@ __global__ __launch_bounds__(256) void k_rhs_fixed(const double* __restrict__ Us
 #undef LG
   (void)valencia_rhs(Us, der, prim, idx, P, pp, sqrtg, e4, em4, gt, gtu, At, K, alpha, dal, dbeta, dgt, dphi,
                      emit);
-}
-
-// ---------------------------------------------------------------------------
-// Ricci tensor R_ij = Rt_ij + Rphi_ij of the stage state (the heaviest part of
-// the BSSN right-hand side, in a kernel of its own so that the RHS kernel
-// needs fewer live registers): reads gt_ij, d_a phi, d_a gt_ij, d_a Gt^i and
-// the second derivatives of phi and gt_ij; writes 6 fields.
-template <typename DT>
-__global__ __launch_bounds__(256) void k_ricci(const double* __restrict__ Us, const DT* __restrict__ der,
-                                               double* __restrict__ Rout, PointParams pp, JobSet js) {
-  const long long P = pp.P;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= P) return;
-  {
-    const long long jd = js.d[blockIdx.y];
-    Us = shift_ptr(Us, jd);
-    der = shift_ptr(der, jd);
-    Rout = shift_ptr(Rout, jd);
-  }
-#define LS(g) ((double)ldnt(&der[(size_t)(g) * P + idx]))
-  auto DD = [&](int a, int b, int s) -> double {
-    if (a == b) return LS(O_D2 + 11 * a + s);
-    const int lo = a < b ? a : b, hi = a < b ? b : a;
-    const int m = (lo == 0) ? (hi == 1 ? 0 : 1) : 2;
-    return LS(O_MX + 11 * m + s);
-  };
-  Sym gt;
-#pragma unroll
-  for (int s = 0; s < 6; ++s) gt.m[s] = Us[(size_t)(1 + s) * P + idx];
-  const Sym gtu = inv_sym(gt, det_sym(gt));
-  double dgt[3][6], Gl[3][6], Gu[3][6], Gd[3], dGt[3][3], dphi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    dphi[a] = LS(21 * a);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) dgt[a][q] = LS(21 * a + 1 + q);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) dGt[a][i] = LS(21 * a + 14 + i);
-  }
-  christoffel(gtu, dgt, Gl, Gu, Gd);
-  Sym R;
-  ricci(gt, gtu, Gl, Gu, Gd, dGt, dphi, DD, R);
-#pragma unroll
-  for (int s = 0; s < 6; ++s) Rout[(size_t)s * P + idx] = R.m[s];
-#undef LS
 }
 
 // ---------------------------------------------------------------------------
@@ -1372,24 +1364,13 @@ hipError_t launch_c2p_flux(const double* U, const double* Ug, double* prim, doub
   return hipGetLastError();
 }
 
-hipError_t launch_ricci(bool der_f32, const double* Us, const void* der, double* R, const PointParams& pp,
-                        const JobSet& js, hipStream_t s) {
-  if (js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
-  if (der_f32)
-    hipLaunchKernelGGL(k_ricci<float>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, (const float*)der, R, pp, js);
-  else
-    hipLaunchKernelGGL(k_ricci<double>, dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, (const double*)der, R, pp,
-                       js);
-  return hipGetLastError();
-}
-
 hipError_t launch_rhs_rk(int mode, bool der_f32, const double* Us, const void* der, const double* prim,
-                         const double* K0, const double* Ric, const double* Un, double* acc, double* out,
-                         const PointParams& pp, const JobSet& js, hipStream_t s) {
+                         const double* K0, const double* Un, double* acc, double* out, const PointParams& pp,
+                         const JobSet& js, hipStream_t s) {
   if (mode < 0 || mode > 5 || js.n < 1 || js.n > MAXB) return hipErrorInvalidValue;
 #define RKM(T, M)                                                                                          \
   hipLaunchKernelGGL((k_rhs_rk<T, M>), dim3(nblk(pp.P), js.n), dim3(256), 0, s, Us, (const T*)der, prim, K0, \
-                     Ric, Un, acc, out, pp, js)
+                     Un, acc, out, pp, js)
 #define RKT(T)                  \
   switch (mode) {               \
     case 0: RKM(T, 0); break;   \
