@@ -218,6 +218,7 @@ void add(TaskList& tl, int ssel, int src, int dsel, int d0, int d1 = -1) {
   t.dst0 = d0;
   t.dst1 = d1 >= 0 ? d1 : 0;
   t.nmat = d1 >= 0 ? 2 : 1;
+  t.op = 0;
 }
 
 void addm(MixedTaskList& tl, int ssel, int src, int f32, int dsel, int d0, int d1 = -1) {

@@ -534,9 +534,10 @@ __global__ __launch_bounds__(256) void k_contract_fold(TaskList tl, Bases B, con
 // tile; before a tile is read each wave waits only until its copy has
 // landed (vector-memory operations complete in issue order, and exactly the
 // previous tile's stores were issued after it), not for those stores.
-// Requirements (checked by the launcher): N = 2 HP with HP in {16, 32, 48,
-// 64, 96} (one operator only at 96: two would not fit in registers),
-// inner a multiple of TC, no row scales (the angular operators carry none).
+// A one-operator task applies operator tk.op (0 or 1).  Requirements
+// (checked by the launcher): N = 2 HP with HP in {16, 32, 48, 64, 96} (one
+// operator only at 96: two would not fit in registers), inner a multiple of
+// TC, no row scales (the angular operators carry none).
 constexpr int PIPE_CH = 1152;  // bytes between copy chunks (1 KB + 128 B)
 
 
@@ -548,6 +549,16 @@ constexpr int PIPE_CH = 1152;  // bytes between copy chunks (1 KB + 128 B)
 inline int pipe_tiles_per_group(long long all) {
   return all <= 2048 ? 4 : (int)std::min(8LL, all / 1024);
 }
+
+// Two-operator launches of the strided axes run as one-operator tasks (a
+// first-and-second-derivative task becomes two tasks reading the same input)
+// from half size 48 up: the one-operator kernel holds half the operator
+// fragments, so more waves share a SIMD, which outweighs reading those inputs
+// twice there (torus 128x96x192 step 12.27 -> 11.98 ms; the phi pass at
+// 64x64x128 95.5 -> 91.4 us); at half sizes 16 and 32 the second read costs
+// more than the waves gain.  At 96 the two-operator form would not fit the
+// registers at all.
+constexpr bool pipe_one_operator(int hp) { return hp >= 48; }
 
 // Waves per workgroup: 4, or 6 for the half sizes 48 and 96 (3 or 6 row
 // blocks), so that every wave owns one 16 x 16 output block per tile.
@@ -617,14 +628,17 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
     const size_t hh = (size_t)HP * HP;
     // operator fragments: lane (lr, lk) holds E^T / O^T [4 ks + lk][16 wi + lr]
     double a[NMAT][2][NKS];
+    // a one-operator task applies operator tk.op
+    const bool second = NMAT == 1 && tk.op == 1;
 #pragma unroll
     for (int m = 0; m < NMAT; ++m) {
-      const double* __restrict__ F = m == 0 ? F0 : F1;
+      const double* __restrict__ F = (m == 0 && !second) ? F0 : F1;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) a[m][h][ks] = F[h * hh + (size_t)(4 * ks + lk) * HP + 16 * wi + lr];
     }
+    const double s0 = second ? sig1 : sig0;
     copy_tile(0, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -665,7 +679,7 @@ __global__ __launch_bounds__(64 * pipe_waves<HP>()) void k_contract_pipe(TaskLis
         const size_t p = toff + (size_t)i * inner + col, pm = toff + (size_t)im * inner + col;
         const double e0 = acc[0][0][v], o0 = acc[0][1][v];
         dst0[p] = (OT)(e0 + o0);
-        dst0[pm] = (OT)(sig0 * (e0 - o0));
+        dst0[pm] = (OT)(s0 * (e0 - o0));
         if (NMAT > 1) {
           const double e1 = acc[NMAT - 1][0][v], o1 = acc[NMAT - 1][1][v];
           dst1[p] = (OT)(e1 + o1);
@@ -917,22 +931,38 @@ static hipError_t launch_fold_t(int axis, int nmat, const TaskList& tl, const Ba
 #undef LP
         return hipGetLastError();
       };
-      if (Hpad == 96 && nmat == 2) {
-        // one pass per operator: every task's first operator, then the
-        // second operator of the two-operator tasks
+      if (nmat == 2 && pipe_one_operator(Hpad)) {
+        // one operator per task: a two-operator task becomes two tasks
+        TaskList one;
+        one.n = 0;
+        bool fits = true;
+        for (int i = 0; i < tl.n && fits; ++i) {
+          const int k = tl.t[i].nmat == 2 ? 2 : 1;
+          if (one.n + k > MAX_TASKS) fits = false;
+          for (int m = 0; m < k && fits; ++m) {
+            Task t = tl.t[i];
+            t.nmat = 1;
+            t.op = m;
+            if (m == 1) t.dst0 = tl.t[i].dst1;
+            one.t[one.n++] = t;
+          }
+        }
+        if (fits) return launch(one, 1, op0, op1);
         TaskList la = tl, lb;
         lb.n = 0;
         for (int i = 0; i < tl.n; ++i) {
           la.t[i].nmat = 1;
+          la.t[i].op = 0;
           if (tl.t[i].nmat == 2) {
             lb.t[lb.n] = tl.t[i];
             lb.t[lb.n].dst0 = tl.t[i].dst1;
             lb.t[lb.n].nmat = 1;
+            lb.t[lb.n].op = 1;
             ++lb.n;
           }
         }
-        hipError_t e = launch(la, 1, op0, op0);
-        if (e == hipSuccess && lb.n > 0) e = launch(lb, 1, op1, op1);
+        hipError_t e = launch(la, 1, op0, op1);
+        if (e == hipSuccess && lb.n > 0) e = launch(lb, 1, op0, op1);
         return e;
       }
       return launch(tl, nmat, op0, op1);

@@ -66,6 +66,7 @@ struct Task {
   int dst_sel, dst0;    // destination of matrix 0
   int dst1;             // destination of matrix 1 (same base as dst0)
   int nmat;             // operators this task applies (1 or 2)
+  int op;               // nmat == 1: which operator (0 or 1; copy-ahead kernels of the strided axes)
 };
 constexpr int MAX_TASKS = 64;
 struct TaskList {
