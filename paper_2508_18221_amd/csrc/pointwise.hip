@@ -521,10 +521,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DAMPED ? 2 
 // Second-derivative field index s: phi 0, gt 1..6, alpha 7, beta 8..10.
 //
 // The kernel finishes one group of right-hand sides at a time and applies the
-// RK4 stage update to it at once (phi, gt, gauge; Valencia; K and A-tilde;
-// Gamma-tilde and the driver), with compiler scheduling barriers between the
-// phases so that each phase's loads are issued where they are consumed and
-// the live register set stays small.
+// RK4 stage update to it at once (phi, gt, gauge; Valencia; then the
+// conformal Ricci tensor; K and A-tilde; Gamma-tilde and the driver), with
+// compiler scheduling barriers between the phases so that each phase's loads
+// are issued where they are consumed and the live register set stays small.
 //
 // Us, Un, acc and out never share a location that the launch writes: the RK4
 // stages alternate between two stage buffers (stage 4 writes U^n, which it
